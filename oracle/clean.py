@@ -1,0 +1,166 @@
+"""FP64 Hogbom CLEAN, clean-beam fit and restore (oracle; test infrastructure).
+
+Algorithm 1 (`improved_clean`) finds the strength and position of the peak of the map,
+then repeatedly runs a CLEAN iteration and searches for the peak again while the peak is
+above the sky level mu_a; Sec. 4.3 fixes the loop gain at gamma = 0.1 and uses the
+threshold to stop.  The paper's production deconvolver is Steer CLEAN; the hot path here
+is the classic Hogbom CLEAN (Sec. 2) it builds on:
+
+    R = dirty, model = 0
+    for i < niter:
+        p = argmax |R| (ties: lowest linear index y N + x)
+        stop if |R[p]| <= threshold
+        f = gamma R[p];  model[p] += f;  record (p, f)
+        R[y, x] -= f beam[y - p_y + N, x - p_x + N]     for all (x, y) in the N x N map
+
+The beam is the 2N x 2N dirty beam (peak at (N, N)), "twice as large as the image" so a
+point can be subtracted from any pixel (Sec. 3.2.1).
+
+Clean beam (Algorithm 1's `gpu_cpsf`; the paper does not say how it is made): the main
+lobe is the 4-connected region around (N, N) where the beam exceeds 0.35; a Gaussian with
+peak 1, exp(-(a dx^2 + b dx dy + c dy^2)), is fitted to ln(beam) over the lobe by linear
+least squares.  Restored image = R + model convolved (linear, not circular) with that
+Gaussian, cropped to N x N.
+
+Pins (tests/test_oracle_clean.py): a single point source gives model = S (1 - (1-g)^n) and
+residual = S (1-g)^n times the beam window; gain 1 stops after one pick; niter 0 leaves R
+equal to the dirty map; equal peaks resolve to the lower index; R + model (*) beam window
+reproduces the dirty map; an exactly Gaussian beam is fitted exactly.
+"""
+from __future__ import annotations
+
+import math
+from collections import deque
+
+import numpy as np
+
+
+def _window(beam, N, py, px):
+    return beam[N - py: 2 * N - py, N - px: 2 * N - px]
+
+
+def hogbom(dirty, beam, gain=0.1, niter=100, threshold=0.0, positive_only=False):
+    """Returns (residual, model, comp_idx, comp_flux)."""
+    R = np.array(dirty, dtype=np.float64, copy=True)
+    N = R.shape[0]
+    B = np.asarray(beam, dtype=np.float64)
+    assert R.shape == (N, N) and B.shape == (2 * N, 2 * N)
+    model = np.zeros((N, N))
+    idx, flux = [], []
+    for _ in range(int(niter)):
+        p = int(np.argmax(R if positive_only else np.abs(R)))   # first maximum = lowest index
+        py, px = divmod(p, N)
+        peak = R[py, px]
+        if abs(peak) <= threshold:
+            break
+        f = gain * peak
+        model[py, px] += f
+        idx.append(p)
+        flux.append(f)
+        R -= f * _window(B, N, py, px)
+    return R, model, np.asarray(idx, np.int64), np.asarray(flux, np.float64)
+
+
+def replay(dirty, beam, comp_idx, comp_flux, gain=0.1, threshold=0.0, eps=None, n_stop=None):
+    """Validate a component list produced elsewhere (several answers are correct under near-ties).
+
+    Re-runs the loop in FP64 following the given picks: pick i is accepted iff
+    |R_i[p_i]| >= max|R_i| - eps and |flux_i - gain R_i[p_i]| <= gain eps.  Returns
+    (ok, first_bad_index, residual, model).  eps defaults to 1e-5 max|dirty|.
+    """
+    R = np.array(dirty, dtype=np.float64, copy=True)
+    N = R.shape[0]
+    B = np.asarray(beam, dtype=np.float64)
+    if eps is None:
+        eps = 1e-5 * float(np.max(np.abs(R)))
+    model = np.zeros((N, N))
+    for i, (p, fl) in enumerate(zip(np.asarray(comp_idx), np.asarray(comp_flux))):
+        p = int(p)
+        py, px = divmod(p, N)
+        m = float(np.max(np.abs(R)))
+        if abs(R[py, px]) < m - eps or abs(fl - gain * R[py, px]) > gain * eps:
+            return False, i, R, model
+        f = gain * R[py, px]
+        model[py, px] += f
+        R -= f * _window(B, N, py, px)
+    if n_stop is not None and n_stop < len(comp_idx):
+        return False, n_stop, R, model
+    return True, -1, R, model
+
+
+def main_lobe(beam, threshold=0.35):
+    """4-connected region around the centre (N, N) where beam > threshold (boolean mask)."""
+    P = beam.shape[0]
+    c = P // 2
+    mask = np.zeros(beam.shape, bool)
+    if not beam[c, c] > threshold:
+        return mask
+    q = deque([(c, c)])
+    mask[c, c] = True
+    while q:
+        y, x = q.popleft()
+        for dy, dx in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+            yy, xx = y + dy, x + dx
+            if 0 <= yy < P and 0 <= xx < P and not mask[yy, xx] and beam[yy, xx] > threshold:
+                mask[yy, xx] = True
+                q.append((yy, xx))
+    return mask
+
+
+def fit_clean_beam(beam, threshold=0.35):
+    """Least-squares Gaussian fit; returns (a, b, c, bmaj_px, bmin_px, pa_rad).
+
+    bmaj/bmin are FWHM in pixels; pa is the angle of the major axis from +x towards +y.
+    """
+    B = np.asarray(beam, np.float64)
+    P = B.shape[0]
+    c0 = P // 2
+    mask = main_lobe(B, threshold)
+    ys, xs = np.nonzero(mask)
+    dx = (xs - c0).astype(np.float64)
+    dy = (ys - c0).astype(np.float64)
+    A = np.stack([dx * dx, dx * dy, dy * dy], axis=1)
+    rhs = -np.log(B[ys, xs])
+    ata = A.T @ A
+    atb = A.T @ rhs
+    a, b, c = np.linalg.solve(ata, atb)
+    return (a, b, c) + gaussian_axes(a, b, c)
+
+
+def gaussian_axes(a, b, c):
+    q = np.array([[a, b / 2.0], [b / 2.0, c]])
+    ev, evec = np.linalg.eigh(q)            # ascending: ev[0] smallest -> major axis
+    lmin, lmax = ev
+    bmaj = 2.0 * math.sqrt(math.log(2.0) / lmin)
+    bmin = 2.0 * math.sqrt(math.log(2.0) / lmax)
+    vx, vy = evec[:, 0]
+    pa = math.atan2(vy, vx)
+    if pa < 0:
+        pa += math.pi
+    if pa >= math.pi:
+        pa -= math.pi
+    return bmaj, bmin, pa
+
+
+def restore(residual, model, abc):
+    """R + sum over model pixels of model[p] exp(-(a dx^2 + b dx dy + c dy^2)), full extent."""
+    a, b, c = abc[:3]
+    N = residual.shape[0]
+    out = np.array(residual, np.float64, copy=True)
+    yy, xx = np.mgrid[0:N, 0:N]
+    for p in np.flatnonzero(model):
+        py, px = divmod(int(p), N)
+        dx = xx - px
+        dy = yy - py
+        out += model[py, px] * np.exp(-(a * dx * dx + b * dx * dy + c * dy * dy))
+    return out
+
+
+def clean_identity(dirty, beam, residual, model):
+    """max |R + model (*) beam window - dirty| (linear convolution with the 2N beam)."""
+    N = dirty.shape[0]
+    acc = np.array(residual, np.float64, copy=True)
+    for p in np.flatnonzero(model):
+        py, px = divmod(int(p), N)
+        acc += model[py, px] * _window(np.asarray(beam, np.float64), N, py, px)
+    return float(np.max(np.abs(acc - dirty)))
