@@ -1,0 +1,180 @@
+/*
+ * mi.h -- C ABI of the MI355X (gfx950) imaging hot path for MUSER-style solar
+ * radio-interferometric data (Mei et al., "GPU-Based High-Performance Imaging for
+ * Mingantu Spectral RadioHeliograph").
+ *
+ * The calls follow the paper's statement of the imaging problem (Algorithm 1):
+ *   dirty_image(visibilities, UVW, weight_mode) -> dirty image, dirty beam, clean beam
+ *   CLEAN: find the peak, subtract the beam at the loop gain, repeat until the peak
+ *   falls to a threshold (Sec. 4.3), then restore.
+ * plus the adjoint of the imaging operator (FFT then degrid).
+ *
+ * Conventions shared by every entry point
+ *  - All data pointers are DEVICE pointers owned by the caller unless marked "host".
+ *    The library never allocates or frees caller-visible memory.
+ *  - Every call is asynchronous on the given HIP stream (0 = the null stream).  The
+ *    first call with a new batch descriptor builds a plan (workspace, device tables) and
+ *    may synchronise once; later calls with an identical descriptor do not synchronise.
+ *  - Argument errors are detected on the host before any launch; the call then returns
+ *    a nonzero mi_status, writes nothing, and mi_last_error() describes the problem.
+ *  - Per-instance problems (no kept visibilities, ...) do not abort the batch: they are
+ *    reported through batch->status (device int32 per instance, MI_INST_* bits).
+ *  - No C++ exception crosses this interface.  A context is not thread-safe: use one
+ *    context per host thread/stream.
+ *  - Images are row-major [y][x] float32.  Pixel (x, y) is at (l, m) =
+ *    ((x - N/2) dl, (y - N/2) dl).  Visibilities follow V = sum I exp(-2 pi i (ul + vm));
+ *    the imager uses exp(+2 pi i (ul + vm)).
+ *  - uv are (u, v) pairs in wavelengths, float32 [M][2]; w_in are input weights,
+ *    float32 [M] (a visibility with w_in <= 0 is flagged and ignored).
+ *  - Gridding kernel: truncated prolate spheroidal function (Sec. 3.2.3), support 7
+ *    cells, alpha = 1, tabulated at 128 points per cell, with grid correction.
+ *  - Image sizes N are powers of two in [64, 4096]; the dirty beam is 2N x 2N ("twice
+ *    as large as the image", Sec. 3.2.1) with the same pixel size, peak 1 at (N, N).
+ */
+#ifndef MI_H
+#define MI_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { float re, im; } mi_c64;
+typedef int mi_status;
+typedef struct mi_ctx mi_ctx;
+
+enum {
+  MI_OK = 0,
+  MI_ERR_ARG = 1,          /* NULL pointer, bad enum, negative count, ...            */
+  MI_ERR_SHAPE = 2,        /* N not a power of two in [64, 4096], bad offsets, ...    */
+  MI_ERR_UNSUPPORTED = 3,  /* valid request the library does not implement           */
+  MI_ERR_NOMEM = 4,        /* workspace allocation failed                            */
+  MI_ERR_DEVICE = 5,       /* a HIP runtime call failed                              */
+  MI_ERR_INSTANCE = 6      /* reserved for callers that fold status[] into one code  */
+};
+
+/* Per-instance status bits written to batch->status (0 = fine). */
+enum {
+  MI_INST_EMPTY = 1,          /* no visibility kept (all flagged or off the grid)     */
+  MI_INST_LOBE_CLIPPED = 2,   /* clean-beam main lobe reached the fit box edge        */
+  MI_INST_RESTORE_CLIPPED = 4,/* restoring Gaussian wider than the restore window     */
+  MI_INST_TEST_FAILED = 8,    /* forced by MI_TEST_FAIL_INSTANCE (failure-path tests) */
+  MI_INST_ABORTED = 16        /* a CLEAN team barrier timed out; outputs incomplete     */
+};
+
+/* Weighting mode, as Algorithm 1's wgtGrid_kernel: mode 1 = uniform, otherwise natural. */
+enum { MI_NATURAL = 0, MI_UNIFORM = 1 };
+
+/* Grid layouts returned by mi_grid. */
+enum {
+  MI_LAYOUT_FULL = 0,  /* full centred P x P complex grid G[j][i], cell (i-P/2, j-P/2) */
+  MI_LAYOUT_HALF = 1   /* half plane u <= 0: P/2 lines (u index i = 1..P/2), each P long
+                          in v: H[i-1][j] = G[j][i]                                      */
+};
+
+/* A batch of independent imaging instances (channel x snapshot x polarisation). */
+typedef struct {
+  int32_t n_inst;              /* number of instances, >= 1                           */
+  const int64_t* vis_offset;   /* host, n_inst+1, CSR offsets into vis/uv/w_in         */
+  const int32_t* n_img;        /* host, n_inst, image size N per instance              */
+  const double* cell_rad;      /* host, n_inst, pixel size dl in radians (> 0)         */
+  const int8_t* weight_mode;   /* host, n_inst, MI_NATURAL or MI_UNIFORM               */
+  int32_t* status;             /* device, n_inst, MI_INST_* bits; may be NULL          */
+} mi_batch;
+
+/* CLEAN parameters (Sec. 4.3: loop gain gamma = 0.1; stop when the peak reaches the
+ * threshold, or after niter components). */
+typedef struct {
+  float gain;                  /* loop gain in (0, 1]                                  */
+  const int32_t* niter;        /* host, n_inst, component cap per instance (>= 0)      */
+  const float* threshold;      /* host, n_inst, stop when |peak| <= threshold; or NULL */
+  int32_t positive_only;       /* 0: peak of |R| (default); 1: peak of R               */
+} mi_clean_params;
+
+/* Create / destroy a context on HIP device `device`.  The context owns plans,
+ * workspaces and constant tables. */
+mi_status mi_ctx_create(mi_ctx** ctx, int device);
+mi_status mi_ctx_destroy(mi_ctx* ctx);
+/* Text of the last error on this context ("" if none).  Owned by the context. */
+const char* mi_last_error(const mi_ctx* ctx);
+/* Library version string (static). */
+const char* mi_version(void);
+
+/* Convolutional gridding with natural or uniform weighting (Sec. 3.2.3; Algorithm 1,
+ * wgtGrid_kernel).  For every kept visibility (w_in > 0 and its nearest cell c within
+ * |c| <= N/2 - 4 in both axes) and its Hermitian mirror, adds w * V * K to the 7 x 7
+ * cells around it.  Uniform weights are w_in / (sum of w_in over all samples, mirrors
+ * included, whose nearest N-grid cell is the same).
+ *   which  = 0: dirty grid (complex, N x N, cell du = 1/(N dl)),
+ *            1: beam grid (V = 1, 2N x 2N, cell du/2; imaginary part 0),
+ *            2: both, dirty grids of all instances first, then beam grids.
+ *   layout = MI_LAYOUT_FULL or MI_LAYOUT_HALF; instances are packed back to back in
+ *            grid_out (P*P resp. P*P/2 complex each, P = N or 2N).
+ *   b0_out (device, optional): double [n_inst][2] = B0 of the N grid and of the 2N grid
+ *            (transform of the weight grid at the centre divided by corr(0)^2).
+ *   n_kept_out (device, optional): int32 [n_inst] kept input visibilities.       */
+mi_status mi_grid(mi_ctx* ctx, const mi_batch* batch, const mi_c64* vis, const float* uv,
+                  const float* w_in, int which, int layout, mi_c64* grid_out,
+                  double* b0_out, int32_t* n_kept_out, hipStream_t stream);
+
+/* In-place, unnormalised, centred 2-D inverse DFT of complex P x P arrays (the transform
+ * that turns the grid into the dirty image, Sec. 3.2.3):
+ *   I[y][x] = sum_{j,i} G[j][i] exp(+2 pi i ((i-P/2)(x-P/2) + (j-P/2)(y-P/2)) / P).
+ *   n (host, n_inst): P per array, power of two in [64, 8192];
+ *   offs (host, n_inst): element offset of each array in data (complex elements). */
+mi_status mi_ifft2(mi_ctx* ctx, mi_c64* data, const int32_t* n, const int64_t* offs,
+                   int32_t n_inst, hipStream_t stream);
+
+/* Dirty image (Algorithm 1, dirty_image): grid, inverse FFT, grid correction and
+ * normalisation so that a point source of flux S at the phase centre images to S.
+ *   dirty_out: float32, N*N per instance, packed back to back.
+ *   beam_out (optional): float32, (2N)^2 per instance -- the dirty beam, as from
+ *            mi_dirty_beam, computed from the same prep pass.
+ *   b0_out (optional): double [n_inst][2], as in mi_grid.
+ * An instance with no kept visibility gets an all-zero image and MI_INST_EMPTY.    */
+mi_status mi_dirty_image(mi_ctx* ctx, const mi_batch* batch, const mi_c64* vis,
+                         const float* uv, const float* w_in, float* dirty_out,
+                         float* beam_out, double* b0_out, hipStream_t stream);
+
+/* Dirty beam (Algorithm 1, gpu_dpsf): the image of unit visibilities on the 2N grid
+ * (Sec. 3.2.1), normalised to exactly 1 at (N, N).  beam_out: (2N)^2 per instance. */
+mi_status mi_dirty_beam(mi_ctx* ctx, const mi_batch* batch, const float* uv,
+                        const float* w_in, float* beam_out, hipStream_t stream);
+
+/* Hogbom CLEAN with restore (Algorithm 1, improved_clean; Sec. 4.3).
+ *   dirty: float32 N*N per instance; beam: float32 (2N)^2 per instance (peak at (N, N)).
+ *   Per iteration: p = argmax |R| (ties: lowest y*N + x), stop if |R[p]| <= threshold,
+ *   f = gain * R[p] (double), model[p] += f, R -= f * beam[y - p_y + N][x - p_x + N].
+ *   residual_out: float32 N*N; model_out: double N*N (optional);
+ *   comp_idx (int32) / comp_flux (double): niter[i] slots per instance, packed back to
+ *   back in instance order (optional, both or neither); n_comp_out: int32 [n_inst]
+ *   components taken (optional);
+ *   restored_out (optional): residual + components convolved with the clean beam, a
+ *   Gaussian fitted to the beam's main lobe (4-connected, beam > 0.35);
+ *   cbeam_out (optional): double [n_inst][6] = a, b, c of exp(-(a dx^2 + b dx dy +
+ *   c dy^2)) in pixels, FWHM major and minor axes (pixels), position angle (radians,
+ *   major axis from +x towards +y, in [0, pi)).
+ * The whole loop runs inside one persistent launch: each image is owned by a team of
+ * workgroups that keeps the residual in LDS.                                          */
+mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty,
+                          const float* beam, const mi_clean_params* params,
+                          float* residual_out, double* model_out, int32_t* comp_idx,
+                          double* comp_flux, int32_t* n_comp_out, float* restored_out,
+                          double* cbeam_out, hipStream_t stream);
+
+/* Adjoint of the imaging operator: FFT, then degrid.
+ *   image: float32 N*N per instance.  vis_out: complex, one per input visibility.
+ *   adjoint = 0: prediction P(y)_k = sum_taps K_k(cell) F[y / (corr_x corr_y)](cell),
+ *                F the centred unnormalised forward DFT;
+ *   adjoint = 1: (A^T y)_k = (2 w_k / B0_N) P(y)_k, the transpose of mi_dirty_image
+ *                under the real inner products <a,b> = sum a b and Re sum conj(v) u.
+ *   Visibilities that are not kept get 0.                                            */
+mi_status mi_degrid(mi_ctx* ctx, const mi_batch* batch, const float* image, const float* uv,
+                    const float* w_in, int adjoint, mi_c64* vis_out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MI_H */

@@ -61,12 +61,14 @@ def hogbom(dirty, beam, gain=0.1, niter=100, threshold=0.0, positive_only=False)
     return R, model, np.asarray(idx, np.int64), np.asarray(flux, np.float64)
 
 
-def replay(dirty, beam, comp_idx, comp_flux, gain=0.1, threshold=0.0, eps=None, n_stop=None):
+def replay(dirty, beam, comp_idx, comp_flux, gain=0.1, threshold=0.0, eps=None, n_stop=None,
+           positive_only=False):
     """Validate a component list produced elsewhere (several answers are correct under near-ties).
 
-    Re-runs the loop in FP64 following the given picks: pick i is accepted iff
-    |R_i[p_i]| >= max|R_i| - eps and |flux_i - gain R_i[p_i]| <= gain eps.  Returns
-    (ok, first_bad_index, residual, model).  eps defaults to 1e-5 max|dirty|.
+    Re-runs the loop in FP64 following the given picks: pick i is accepted iff its peak
+    value (|R_i[p_i]|, or R_i[p_i] with positive_only) is within eps of the map's peak
+    value, and |flux_i - gain R_i[p_i]| <= gain eps.  Returns (ok, first_bad_index,
+    residual, model).  eps defaults to 1e-5 max|dirty|.
     """
     R = np.array(dirty, dtype=np.float64, copy=True)
     N = R.shape[0]
@@ -77,8 +79,11 @@ def replay(dirty, beam, comp_idx, comp_flux, gain=0.1, threshold=0.0, eps=None, 
     for i, (p, fl) in enumerate(zip(np.asarray(comp_idx), np.asarray(comp_flux))):
         p = int(p)
         py, px = divmod(p, N)
-        m = float(np.max(np.abs(R)))
-        if abs(R[py, px]) < m - eps or abs(fl - gain * R[py, px]) > gain * eps:
+        if positive_only:
+            m, val = float(np.max(R)), R[py, px]
+        else:
+            m, val = float(np.max(np.abs(R))), abs(R[py, px])
+        if val < m - eps or abs(fl - gain * R[py, px]) > gain * eps:
             return False, i, R, model
         f = gain * R[py, px]
         model[py, px] += f
@@ -107,10 +112,17 @@ def main_lobe(beam, threshold=0.35):
     return mask
 
 
-def fit_clean_beam(beam, threshold=0.35):
+DEGENERATE_ABC = (4.0 * math.log(2.0), 0.0, 4.0 * math.log(2.0))   # FWHM of one pixel
+
+
+def fit_clean_beam(beam, threshold=0.35, return_flag=False):
     """Least-squares Gaussian fit; returns (a, b, c, bmaj_px, bmin_px, pa_rad).
 
     bmaj/bmin are FWHM in pixels; pa is the angle of the major axis from +x towards +y.
+    Degenerate lobes are decided by pixel counts: if no lobe pixel has dx dy != 0, the
+    cross term is fixed at b = 0 and (a, c) are fitted (both axes must hold pixels);
+    otherwise, or if the 3 x 3 system is numerically singular, the fit falls back to a
+    one-pixel FWHM circular Gaussian and the flag is set.
     """
     B = np.asarray(beam, np.float64)
     P = B.shape[0]
@@ -119,12 +131,26 @@ def fit_clean_beam(beam, threshold=0.35):
     ys, xs = np.nonzero(mask)
     dx = (xs - c0).astype(np.float64)
     dy = (ys - c0).astype(np.float64)
-    A = np.stack([dx * dx, dx * dy, dy * dy], axis=1)
     rhs = -np.log(B[ys, xs])
-    ata = A.T @ A
-    atb = A.T @ rhs
-    a, b, c = np.linalg.solve(ata, atb)
-    return (a, b, c) + gaussian_axes(a, b, c)
+    degenerate = False
+    if np.any(dx * dy != 0):
+        A = np.stack([dx * dx, dx * dy, dy * dy], axis=1)
+        ata = A.T @ A
+        det = np.linalg.det(ata)
+        if abs(det) < 1e-9 * abs(ata[0, 0] * ata[1, 1] * ata[2, 2]):
+            degenerate = True
+        else:
+            a, b, c = np.linalg.solve(ata, A.T @ rhs)
+    elif np.any(dx != 0) and np.any(dy != 0):
+        A = np.stack([dx * dx, dy * dy], axis=1)
+        a, c = np.linalg.solve(A.T @ A, A.T @ rhs)
+        b = 0.0
+    else:
+        degenerate = True
+    if degenerate:
+        a, b, c = DEGENERATE_ABC
+    out = (a, b, c) + gaussian_axes(a, b, c)
+    return (out, degenerate) if return_flag else out
 
 
 def gaussian_axes(a, b, c):

@@ -56,14 +56,20 @@ class Prep:
         self.N, self.W, self.os = int(N), int(W), int(os)
         scale = float(N) * float(cell_rad)
         g = uv64 * scale
-        self.c = rhaz(g).astype(np.int64)
-        self.o = rhaz((g - self.c) * os).astype(np.int64)
+        cd = rhaz(g)
         lim = self.N // 2 - 1 - (self.W - 1) // 2
         w_in = np.asarray(w_in, dtype=np.float32).astype(np.float64)
-        self.keep = (w_in > 0) & np.all(np.abs(self.c) <= lim, axis=1)
+        # keep decision in FP64 before any integer conversion (NaN/inf/huge -> dropped)
+        with np.errstate(invalid="ignore"):
+            self.keep = (w_in > 0) & np.all(np.abs(cd) <= lim, axis=1)
+        g = np.where(self.keep[:, None], g, 0.0)
+        cd = np.where(self.keep[:, None], cd, 0.0)
+        self.c = cd.astype(np.int64)
+        self.o = rhaz((g - cd) * os).astype(np.int64)
         g2 = 2.0 * g
-        self.c2 = rhaz(g2).astype(np.int64)
-        self.o2 = rhaz((g2 - self.c2) * os).astype(np.int64)
+        c2 = rhaz(g2)
+        self.c2 = c2.astype(np.int64)
+        self.o2 = rhaz((g2 - c2) * os).astype(np.int64)
         self.w_in = w_in
 
     @property

@@ -1,0 +1,70 @@
+"""ctypes loader for libmi.so (the HIP library).  There is no fallback implementation:
+if the library is missing or fails to load, every call raises."""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int, c_int32, c_void_p
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmi.so")
+
+MI_OK, MI_ERR_ARG, MI_ERR_SHAPE, MI_ERR_UNSUPPORTED, MI_ERR_NOMEM, MI_ERR_DEVICE, MI_ERR_INSTANCE = range(7)
+MI_INST_EMPTY, MI_INST_LOBE_CLIPPED, MI_INST_RESTORE_CLIPPED, MI_INST_TEST_FAILED = 1, 2, 4, 8
+MI_NATURAL, MI_UNIFORM = 0, 1
+MI_LAYOUT_FULL, MI_LAYOUT_HALF = 0, 1
+
+# every entry point declared in include/mi.h
+EXPORTS = ("mi_ctx_create", "mi_ctx_destroy", "mi_last_error", "mi_version", "mi_grid", "mi_ifft2",
+           "mi_dirty_image", "mi_dirty_beam", "mi_hogbom_clean", "mi_degrid")
+
+
+class MiBatch(ctypes.Structure):
+    _fields_ = [("n_inst", c_int32), ("vis_offset", c_void_p), ("n_img", c_void_p), ("cell_rad", c_void_p),
+                ("weight_mode", c_void_p), ("status", c_void_p)]
+
+
+class MiCleanParams(ctypes.Structure):
+    _fields_ = [("gain", c_float), ("niter", c_void_p), ("threshold", c_void_p), ("positive_only", c_int32)]
+
+
+class MiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mi error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1712_06913_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = c_void_p
+    L.mi_ctx_create.argtypes = [POINTER(c_void_p), c_int]
+    L.mi_ctx_destroy.argtypes = [vp]
+    L.mi_last_error.argtypes = [vp]
+    L.mi_last_error.restype = c_char_p
+    L.mi_version.restype = c_char_p
+    L.mi_grid.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, c_int, c_int, vp, vp, vp, vp]
+    L.mi_ifft2.argtypes = [vp, vp, vp, vp, c_int32, vp]
+    L.mi_dirty_image.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, vp, vp, vp, vp]
+    L.mi_dirty_beam.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, vp]
+    L.mi_hogbom_clean.argtypes = [vp, POINTER(MiBatch), vp, vp, POINTER(MiCleanParams), vp, vp, vp, vp, vp, vp,
+                                  vp, vp]
+    L.mi_degrid.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, c_int, vp, vp]
+    for name in EXPORTS:
+        if name not in ("mi_last_error", "mi_version"):
+            getattr(L, name).restype = c_int
+    _lib = L
+    return L
+
+
+def check(ctx, code: int):
+    if code != MI_OK:
+        msg = lib().mi_last_error(ctx).decode() if ctx else ""
+        raise MiError(code, msg)

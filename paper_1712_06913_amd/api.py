@@ -1,0 +1,171 @@
+"""Python binding of the C ABI (include/mi.h) over torch device tensors.
+
+Only argument marshalling happens here: every step of the imaging path runs in the HIP
+library.  Tensors must live on the context's device; calls are enqueued on torch's
+current stream and do not synchronise.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, Optional
+
+import numpy as np
+import torch
+
+from . import _native as nat
+
+_ctx_cache: Dict[int, ctypes.c_void_p] = {}
+
+
+def context(device: int = 0) -> ctypes.c_void_p:
+    """Per-device library context (created on first use, kept for the process)."""
+    if device not in _ctx_cache:
+        ctx = ctypes.c_void_p()
+        code = nat.lib().mi_ctx_create(ctypes.byref(ctx), device)
+        if code != nat.MI_OK:
+            raise nat.MiError(code, "mi_ctx_create failed")
+        _ctx_cache[device] = ctx
+    return _ctx_cache[device]
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to the library must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Batch:
+    """Host-side batch descriptor (mi_batch) plus a device status array."""
+
+    def __init__(self, vis_offset, n_img, cell_rad, weight_mode, device="cuda:0"):
+        self.vis_offset = np.ascontiguousarray(vis_offset, dtype=np.int64)
+        self.n_img = np.ascontiguousarray(n_img, dtype=np.int32)
+        self.cell_rad = np.ascontiguousarray(cell_rad, dtype=np.float64)
+        self.weight_mode = np.ascontiguousarray(weight_mode, dtype=np.int8)
+        self.device = torch.device(device)
+        self.n_inst = len(self.n_img)
+        self.status = torch.zeros(self.n_inst, dtype=torch.int32, device=self.device)
+        self.img_off = np.concatenate([[0], np.cumsum(self.n_img.astype(np.int64) ** 2)])
+        self.beam_off = 4 * self.img_off
+        self._c = nat.MiBatch(
+            self.n_inst, self.vis_offset.ctypes.data, self.n_img.ctypes.data, self.cell_rad.ctypes.data,
+            self.weight_mode.ctypes.data, self.status.data_ptr())
+
+    @classmethod
+    def from_workload(cls, wl, device="cuda:0") -> "Batch":
+        return cls(wl.vis_offset, wl.n_img, wl.cell_rad, wl.weight_mode, device)
+
+    @property
+    def c(self):
+        return ctypes.byref(self._c)
+
+    @property
+    def ctx(self):
+        return context(self.device.index or 0)
+
+    def split(self, flat: torch.Tensor, beam: bool = False):
+        """Views of a packed per-instance image array as a list of (P, P) tensors."""
+        off = self.beam_off if beam else self.img_off
+        out = []
+        for i in range(self.n_inst):
+            P = int(self.n_img[i]) * (2 if beam else 1)
+            out.append(flat[off[i]: off[i] + P * P].view(P, P))
+        return out
+
+
+def workload_tensors(wl, device="cuda:0"):
+    """Device copies (vis complex64, uv float32 [M,2], w float32) of a synthetic workload."""
+    dev = torch.device(device)
+    vis = torch.from_numpy(np.ascontiguousarray(wl.vis)).to(dev)
+    uv = torch.from_numpy(np.ascontiguousarray(wl.uv)).to(dev)
+    w = torch.from_numpy(np.ascontiguousarray(wl.w)).to(dev)
+    return vis, uv, w
+
+
+def dirty_image(batch: Batch, vis, uv, w, beam: bool = True, out=None, beam_out=None, b0_out=None):
+    """mi_dirty_image: packed float32 dirty images (and beams), plus B0 per instance."""
+    dev = batch.device
+    out = torch.empty(int(batch.img_off[-1]), dtype=torch.float32, device=dev) if out is None else out
+    if beam and beam_out is None:
+        beam_out = torch.empty(int(batch.beam_off[-1]), dtype=torch.float32, device=dev)
+    b0_out = torch.empty(2 * batch.n_inst, dtype=torch.float64, device=dev) if b0_out is None else b0_out
+    nat.check(batch.ctx, nat.lib().mi_dirty_image(batch.ctx, batch.c, _ptr(vis), _ptr(uv), _ptr(w), _ptr(out),
+                                                  _ptr(beam_out if beam else None), _ptr(b0_out), _stream(dev)))
+    return out, (beam_out if beam else None), b0_out
+
+
+def dirty_beam(batch: Batch, uv, w, out=None):
+    dev = batch.device
+    out = torch.empty(int(batch.beam_off[-1]), dtype=torch.float32, device=dev) if out is None else out
+    nat.check(batch.ctx, nat.lib().mi_dirty_beam(batch.ctx, batch.c, _ptr(uv), _ptr(w), _ptr(out), _stream(dev)))
+    return out
+
+
+def grid(batch: Batch, vis, uv, w, which: int = 0, layout: int = nat.MI_LAYOUT_FULL, out=None):
+    """mi_grid: packed complex64 grids; returns (grid, b0 [n,2] float64, n_kept int32)."""
+    dev = batch.device
+    n = batch.n_img.astype(np.int64)
+    per_full = {0: n * n, 1: 4 * n * n}
+    per_half = {0: n * n // 2, 1: 2 * n * n}
+    per = per_full if layout == nat.MI_LAYOUT_FULL else per_half
+    total = int(per[0].sum() * (which != 1) + per[1].sum() * (which != 0))
+    out = torch.empty(total, dtype=torch.complex64, device=dev) if out is None else out
+    b0 = torch.empty(2 * batch.n_inst, dtype=torch.float64, device=dev)
+    nk = torch.empty(batch.n_inst, dtype=torch.int32, device=dev)
+    nat.check(batch.ctx, nat.lib().mi_grid(batch.ctx, batch.c, _ptr(vis), _ptr(uv), _ptr(w), which, layout,
+                                           _ptr(out), _ptr(b0), _ptr(nk), _stream(dev)))
+    return out, b0, nk
+
+
+def ifft2(data: torch.Tensor, n, offs, device: int = 0):
+    """mi_ifft2 in place on a packed complex64 tensor."""
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    ctx = context(device)
+    nat.check(ctx, nat.lib().mi_ifft2(ctx, _ptr(data), n.ctypes.data, offs.ctypes.data, len(n),
+                                      _stream(data.device)))
+    return data
+
+
+def hogbom_clean(batch: Batch, dirty, beam, niter, gain: float = 0.1, threshold=None, positive_only=False,
+                 restore: bool = True, want_model: bool = True, want_components: bool = True):
+    """mi_hogbom_clean; returns a dict of device tensors."""
+    dev = batch.device
+    niter = np.ascontiguousarray(niter, dtype=np.int32)
+    thr = None if threshold is None else np.ascontiguousarray(threshold, dtype=np.float32)
+    nimg = int(batch.img_off[-1])
+    res = {"residual": torch.empty(nimg, dtype=torch.float32, device=dev)}
+    res["model"] = torch.empty(nimg, dtype=torch.float64, device=dev) if want_model else None
+    ncomp_total = max(1, int(niter.sum()))
+    if want_components:
+        res["comp_idx"] = torch.full((ncomp_total,), -1, dtype=torch.int32, device=dev)
+        res["comp_flux"] = torch.zeros(ncomp_total, dtype=torch.float64, device=dev)
+    else:
+        res["comp_idx"] = res["comp_flux"] = None
+    res["n_comp"] = torch.zeros(batch.n_inst, dtype=torch.int32, device=dev)
+    res["restored"] = torch.empty(nimg, dtype=torch.float32, device=dev) if restore else None
+    res["cbeam"] = torch.zeros(6 * batch.n_inst, dtype=torch.float64, device=dev) if restore else None
+    res["comp_off"] = np.concatenate([[0], np.cumsum(niter.astype(np.int64))])
+    prm = nat.MiCleanParams(float(gain), niter.ctypes.data, None if thr is None else thr.ctypes.data,
+                            1 if positive_only else 0)
+    nat.check(batch.ctx, nat.lib().mi_hogbom_clean(
+        batch.ctx, batch.c, _ptr(dirty), _ptr(beam), ctypes.byref(prm), _ptr(res["residual"]), _ptr(res["model"]),
+        _ptr(res["comp_idx"]), _ptr(res["comp_flux"]), _ptr(res["n_comp"]), _ptr(res["restored"]),
+        _ptr(res["cbeam"]), _stream(dev)))
+    return res
+
+
+def degrid(batch: Batch, image, uv, w, adjoint: bool = False, out=None):
+    """mi_degrid: prediction P(y) (adjoint=False) or A^T y (adjoint=True), complex64 per visibility."""
+    dev = batch.device
+    m = int(batch.vis_offset[-1])
+    out = torch.empty(m, dtype=torch.complex64, device=dev) if out is None else out
+    nat.check(batch.ctx, nat.lib().mi_degrid(batch.ctx, batch.c, _ptr(image), _ptr(uv), _ptr(w),
+                                             1 if adjoint else 0, _ptr(out), _stream(dev)))
+    return out

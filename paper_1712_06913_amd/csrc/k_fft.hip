@@ -1,0 +1,368 @@
+// LDS-resident Stockham FFTs for the imaging transform and its adjoint (gfx950, FP64).
+//
+// Sec. 3.2.3: an inverse FFT of the gridded visibilities gives the dirty image (with the
+// disk at the centre, Algorithm 1).  The centred transform
+//   I[y][x] = sum G[j][i] exp(+2 pi i ((i-P/2)(x-P/2) + (j-P/2)(y-P/2)) / P)
+// is computed for even P as (-1)^(x+y) IDFT[(-1)^(i+j) G], so no shift passes are needed:
+// the gridder applies (-1)^(i+j) when it flushes a tile and the last pass applies
+// (-1)^(x+y) together with the grid correction 1/(corr(x) corr(y)) and 1/B0.
+//
+// Precision: the correction divides by corr(x) corr(y), about 1e-6 in the map corners for
+// the prolate spheroidal kernel, so rounding in the grid and the transform is amplified by
+// up to ~1e6 there.  Grid, transform and correction therefore run in FP64; inputs and
+// output images are FP32.
+//
+// The grid is Hermitian, so only the half plane u <= 0 is stored: P/2 lines (u index
+// i = 1..P/2; i = 0 is never touched by the 7-tap kernel and is zero), each P cells long
+// in v.  Two passes, each LDS-resident and reading/writing whole contiguous blocks:
+//   pass A  (k_fft_a): nl lines per workgroup, length-P complex FFT along v, written as
+//           one contiguous block Yb[line_block][y][line % nl] over the same footprint;
+//   pass B  (k_fft_b_c2r): ny rows y per workgroup; rebuilds the Hermitian spectrum
+//           along u from the blocks, length-P FFT, real part, correction, normalisation.
+// The adjoint runs the mirror image (k_fft_b_r2c then k_fft_a_fwd); mi_ifft2 uses
+// k_fft_c2c_t twice on full complex arrays.
+//
+// Twiddles come from a table exp(+2 pi i t / 8192) computed on the host in FP64.
+#include "mi_internal.h"
+
+namespace mi {
+
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+// multiply by s*i (s = +1 or -1)
+__device__ __forceinline__ double2 mul_si(double2 a, double s) { return make_double2(-s * a.y, s * a.x); }
+
+template <int R> __device__ __forceinline__ void small_dft(double2* x, double s);
+
+template <> __device__ __forceinline__ void small_dft<2>(double2* x, double) {
+  double2 a = x[0], b = x[1];
+  x[0] = cadd(a, b);
+  x[1] = csub(a, b);
+}
+
+template <> __device__ __forceinline__ void small_dft<4>(double2* x, double s) {
+  double2 t0 = cadd(x[0], x[2]), t1 = csub(x[0], x[2]);
+  double2 t2 = cadd(x[1], x[3]), t3 = mul_si(csub(x[1], x[3]), s);
+  x[0] = cadd(t0, t2);
+  x[2] = csub(t0, t2);
+  x[1] = cadd(t1, t3);
+  x[3] = csub(t1, t3);
+}
+
+template <> __device__ __forceinline__ void small_dft<8>(double2* x, double s) {
+  double2 e[4] = {x[0], x[2], x[4], x[6]};
+  double2 o[4] = {x[1], x[3], x[5], x[7]};
+  small_dft<4>(e, s);
+  small_dft<4>(o, s);
+  const double r = 0.70710678118654752440;
+  // w8^q = exp(s i pi q / 4)
+  double2 o1 = cmul(o[1], make_double2(r, s * r));
+  double2 o2 = mul_si(o[2], s);
+  double2 o3 = cmul(o[3], make_double2(-r, s * r));
+  x[0] = cadd(e[0], o[0]);
+  x[4] = csub(e[0], o[0]);
+  x[1] = cadd(e[1], o1);
+  x[5] = csub(e[1], o1);
+  x[2] = cadd(e[2], o2);
+  x[6] = csub(e[2], o2);
+  x[3] = cadd(e[3], o3);
+  x[7] = csub(e[3], o3);
+}
+
+// One Stockham radix-R pass over nl lines of P points held in LDS (line stride P).
+// L = product of the radices already applied.  Butterfly b of a line reads x[b + m P/R]
+// and writes y[(b/L) L R + b%L + q L] after twiddling by exp(s 2 pi i m (b%L) / (L R)).
+template <int R, int ELEMS, int THREADS>
+__device__ __forceinline__ void stockham_pass(double2* buf, int log2P, int log2L, int nl, double s,
+                                              const double2* __restrict__ tw) {
+  constexpr int BPT = ELEMS / THREADS / R;
+  constexpr int LOG2R = R == 8 ? 3 : (R == 4 ? 2 : 1);
+  const int log2nb = log2P - LOG2R;
+  const int nb = 1 << log2nb;
+  const int total = nl << log2nb;
+  const int L = 1 << log2L;
+  const int tw_shift = (13 - log2L - LOG2R);   // table length 8192 = 2^13
+  double2 x[BPT][R];
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int b = threadIdx.x + q * THREADS;
+    if (b < total) {
+      const int line = b >> log2nb, bb = b & (nb - 1);
+      const double2* src = buf + (line << log2P) + bb;
+#pragma unroll
+      for (int m = 0; m < R; ++m) x[q][m] = src[m << log2nb];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int b = threadIdx.x + q * THREADS;
+    if (b < total) {
+      const int line = b >> log2nb, bb = b & (nb - 1);
+      const int j = bb & (L - 1), blk = bb >> log2L;
+      if (L > 1) {
+#pragma unroll
+        for (int m = 1; m < R; ++m) {
+          double2 w = tw[(m * j) << tw_shift];
+          w.y *= s;
+          x[q][m] = cmul(x[q][m], w);
+        }
+      }
+      small_dft<R>(x[q], s);
+      double2* dst = buf + (line << log2P) + (blk << (log2L + LOG2R)) + j;
+#pragma unroll
+      for (int m = 0; m < R; ++m) dst[m << log2L] = x[q][m];
+    }
+  }
+  __syncthreads();
+}
+
+// Full length-P FFT (sign s) of nl lines in LDS; nl * P <= ELEMS.
+template <int ELEMS, int THREADS>
+__device__ void lds_fft(double2* buf, int log2P, int nl, double s, const double2* __restrict__ tw) {
+  int done = 0, rem = log2P;
+  while (rem > 0) {
+    const int r = (rem == 4 || rem == 2) ? 2 : (rem == 1 ? 1 : 3);
+    if (r == 3) stockham_pass<8, ELEMS, THREADS>(buf, log2P, done, nl, s, tw);
+    else if (r == 2) stockham_pass<4, ELEMS, THREADS>(buf, log2P, done, nl, s, tw);
+    else stockham_pass<2, ELEMS, THREADS>(buf, log2P, done, nl, s, tw);
+    done += r;
+    rem -= r;
+  }
+}
+
+__device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
+
+template <int ELEMS>
+__device__ __forceinline__ int lines_per_block(int P) {
+  const int nl = ELEMS / P;
+  return nl > P / 2 ? P / 2 : nl;
+}
+
+}  // namespace
+
+// Pass A (inverse): half-grid lines -> FFT along v -> contiguous block Yb[b][y][l].
+template <int ELEMS, int THREADS>
+__global__ void __launch_bounds__(THREADS)
+k_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int beam,
+        double2* __restrict__ grid, Tables T) {
+  __shared__ double2 buf[ELEMS];
+  const FftWork wk = work[blockIdx.x];
+  const InstDesc d = inst[wk.inst];
+  const int P = beam ? 2 * d.N : d.N, log2P = ilog2(P);
+  const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
+  double2* blk = grid + (beam ? d.gb_off : d.gd_off) + (int64_t)wk.first * P;   // block start
+  const int n = nl * P;
+  for (int q = threadIdx.x; q < n; q += THREADS) buf[q] = blk[q];
+  __syncthreads();
+  lds_fft<ELEMS, THREADS>(buf, log2P, nl, +1.0, T.twiddle);
+  for (int q = threadIdx.x; q < n; q += THREADS) {
+    const int y = q >> log2nl, l = q & (nl - 1);
+    blk[q] = buf[(l << log2P) + y];
+  }
+}
+
+// Pass B (inverse, complex-to-real): rows y0..y0+ny-1 of the image.
+template <int ELEMS, int THREADS>
+__global__ void __launch_bounds__(THREADS)
+k_fft_b_c2r(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int beam,
+            const double2* __restrict__ yb, const double* __restrict__ b0, Tables T,
+            float* __restrict__ out) {
+  __shared__ double2 buf[ELEMS];
+  const FftWork wk = work[blockIdx.x];
+  const InstDesc d = inst[wk.inst];
+  const int P = beam ? 2 * d.N : d.N, log2P = ilog2(P), h = P / 2;
+  const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
+  const int ny = nl;
+  const int y0 = wk.first;
+  const double2* src = yb + (beam ? d.gb_off : d.gd_off);
+  // element (line k', row y) of the blocked layout: (k'/nl) nl P + y nl + k' % nl
+  const int nblk = h / nl;
+  const int per_blk = ny * nl;
+  for (int q = threadIdx.x; q < nblk * per_blk; q += THREADS) {
+    const int b = q / per_blk, r = q - b * per_blk;
+    const int yl = r >> log2nl, l = r & (nl - 1);
+    const double2 v = src[(int64_t)b * nl * P + (int64_t)(y0 + yl) * nl + l];
+    const int k = b * nl + l + 1;          // u frequency index 1..P/2
+    double2* row = buf + (yl << log2P);
+    row[k] = v;
+    if (k < h) row[P - k] = make_double2(v.x, -v.y);
+  }
+  for (int yl = threadIdx.x; yl < ny; yl += THREADS) buf[yl << log2P] = make_double2(0.0, 0.0);
+  __syncthreads();
+  lds_fft<ELEMS, THREADS>(buf, log2P, ny, +1.0, T.twiddle);
+  const double bd = b0[2 * wk.inst + (beam ? 1 : 0)];
+  const double inv_b0 = bd > 0.0 ? 1.0 / bd : 0.0;
+  const double* ic = T.inv_corr + (P - 64);
+  float* o = out + (beam ? d.beam_off : d.img_off) + (int64_t)y0 * P;
+  for (int q = threadIdx.x; q < ny * P; q += THREADS) {
+    const int yl = q >> log2P, x = q & (P - 1);
+    const int y = y0 + yl;
+    double s = ic[x] * (ic[y] * inv_b0);
+    if ((x + y) & 1) s = -s;
+    o[q] = (float)(buf[q].x * s);
+  }
+}
+
+// Adjoint pass B^T: image rows -> pre-correction and (-1)^(x+y) -> forward FFT along x ->
+// keep u frequencies 1..P/2 -> blocked layout.
+template <int ELEMS, int THREADS>
+__global__ void __launch_bounds__(THREADS)
+k_fft_b_r2c(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
+            const float* __restrict__ img, Tables T, double2* __restrict__ yb) {
+  __shared__ double2 buf[ELEMS];
+  const FftWork wk = work[blockIdx.x];
+  const InstDesc d = inst[wk.inst];
+  const int P = d.N, log2P = ilog2(P), h = P / 2;
+  const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
+  const int ny = nl;
+  const int y0 = wk.first;
+  const double* ic = T.inv_corr + (P - 64);
+  const float* src = img + d.img_off + (int64_t)y0 * P;
+  for (int q = threadIdx.x; q < ny * P; q += THREADS) {
+    const int yl = q >> log2P, x = q & (P - 1);
+    const int y = y0 + yl;
+    double s = ic[x] * ic[y];
+    if ((x + y) & 1) s = -s;
+    buf[q] = make_double2((double)src[q] * s, 0.0);
+  }
+  __syncthreads();
+  lds_fft<ELEMS, THREADS>(buf, log2P, ny, -1.0, T.twiddle);
+  double2* dst = yb + d.gd_off;
+  const int nblk = h / nl, per_blk = ny * nl;
+  for (int q = threadIdx.x; q < nblk * per_blk; q += THREADS) {
+    const int b = q / per_blk, r = q - b * per_blk;
+    const int yl = r >> log2nl, l = r & (nl - 1);
+    const int k = b * nl + l + 1;
+    dst[(int64_t)b * nl * P + (int64_t)(y0 + yl) * nl + l] = buf[(yl << log2P) + k];
+  }
+}
+
+// Adjoint pass A^T: blocked layout -> forward FFT along v -> (-1)^(i+j) -> half grid lines.
+template <int ELEMS, int THREADS>
+__global__ void __launch_bounds__(THREADS)
+k_fft_a_fwd(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, Tables T,
+            double2* __restrict__ grid) {
+  __shared__ double2 buf[ELEMS];
+  const FftWork wk = work[blockIdx.x];
+  const InstDesc d = inst[wk.inst];
+  const int P = d.N, log2P = ilog2(P);
+  const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
+  double2* blk = grid + d.gd_off + (int64_t)wk.first * P;
+  const int n = nl * P;
+  for (int q = threadIdx.x; q < n; q += THREADS) {
+    const int y = q >> log2nl, l = q & (nl - 1);
+    buf[(l << log2P) + y] = blk[q];
+  }
+  __syncthreads();
+  lds_fft<ELEMS, THREADS>(buf, log2P, nl, -1.0, T.twiddle);
+  for (int q = threadIdx.x; q < n; q += THREADS) {
+    const int l = q >> log2P, j = q & (P - 1);
+    double2 v = buf[q];
+    if (((wk.first + l + 1) + j) & 1) { v.x = -v.x; v.y = -v.y; }
+    blk[q] = v;
+  }
+}
+
+// Generic complex lines -> FFT -> transposed write, for mi_ifft2 (two passes).
+// src lines of length P (stride P), nl lines per block; dst[y * P + line].
+// pre: multiply input (line, n) by (-1)^(line+n); post: output (y, line) by (-1)^(y+line).
+template <int ELEMS, int THREADS, class TIn, class TOut>
+__global__ void __launch_bounds__(THREADS)
+k_fft_c2c_t(const int* __restrict__ n_arr, const int64_t* __restrict__ offs, const FftWork* __restrict__ work,
+            const TIn* __restrict__ src, TOut* __restrict__ dst, Tables T, double s, int pre, int post) {
+  __shared__ double2 buf[ELEMS];
+  const FftWork wk = work[blockIdx.x];
+  const int P = n_arr[wk.inst], log2P = ilog2(P);
+  int nl = ELEMS / P;
+  if (nl > P) nl = P;
+  const int log2nl = ilog2(nl);
+  const int64_t off = offs[wk.inst];
+  const TIn* in = src + off + (int64_t)wk.first * P;
+  const int n = nl * P;
+  for (int q = threadIdx.x; q < n; q += THREADS) {
+    const TIn v = in[q];
+    double2 d = make_double2((double)v.x, (double)v.y);
+    if (pre && (((q >> log2P) + wk.first + (q & (P - 1))) & 1)) { d.x = -d.x; d.y = -d.y; }
+    buf[q] = d;
+  }
+  __syncthreads();
+  lds_fft<ELEMS, THREADS>(buf, log2P, nl, s, T.twiddle);
+  TOut* out = dst + off;
+  for (int q = threadIdx.x; q < n; q += THREADS) {
+    const int y = q >> log2nl, l = q & (nl - 1);
+    double2 v = buf[(l << log2P) + y];
+    const int line = wk.first + l;
+    if (post && ((y + line) & 1)) { v.x = -v.x; v.y = -v.y; }
+    TOut o;
+    o.x = v.x;
+    o.y = v.y;
+    out[(int64_t)y * P + line] = o;
+  }
+}
+
+// ---- host launchers.  elems selects the LDS block: 4096 complex doubles (64 KB, 256
+// threads) or 8192 (128 KB, 512 threads, needed only for P = 8192).
+#define MI_FFT_DISPATCH(KERNEL, ...)                                                              \
+  do {                                                                                            \
+    if (elems == 8192)                                                                            \
+      hipLaunchKernelGGL((KERNEL<8192, 512>), dim3(n_work), dim3(512), 0, st, __VA_ARGS__);       \
+    else                                                                                          \
+      hipLaunchKernelGGL((KERNEL<4096, 256>), dim3(n_work), dim3(256), 0, st, __VA_ARGS__);       \
+  } while (0)
+
+hipError_t launch_fft_a(int elems, const InstDesc* inst, const FftWork* work, int n_work, int beam, double2* grid,
+                        const Tables& T, hipStream_t st) {
+  if (n_work <= 0) return hipSuccess;
+  MI_FFT_DISPATCH(k_fft_a, inst, work, beam, grid, T);
+  return hipGetLastError();
+}
+hipError_t launch_fft_b_c2r(int elems, const InstDesc* inst, const FftWork* work, int n_work, int beam,
+                            const double2* yb, const double* b0, const Tables& T, float* out, hipStream_t st) {
+  if (n_work <= 0) return hipSuccess;
+  MI_FFT_DISPATCH(k_fft_b_c2r, inst, work, beam, yb, b0, T, out);
+  return hipGetLastError();
+}
+hipError_t launch_fft_b_r2c(int elems, const InstDesc* inst, const FftWork* work, int n_work, const float* img,
+                            const Tables& T, double2* yb, hipStream_t st) {
+  if (n_work <= 0) return hipSuccess;
+  MI_FFT_DISPATCH(k_fft_b_r2c, inst, work, img, T, yb);
+  return hipGetLastError();
+}
+hipError_t launch_fft_a_fwd(int elems, const InstDesc* inst, const FftWork* work, int n_work, const Tables& T,
+                            double2* grid, hipStream_t st) {
+  if (n_work <= 0) return hipSuccess;
+  MI_FFT_DISPATCH(k_fft_a_fwd, inst, work, T, grid);
+  return hipGetLastError();
+}
+hipError_t launch_fft_c2c_t_f2d(int elems, const int* n_arr, const int64_t* offs, const FftWork* work, int n_work,
+                                const float2* src, double2* dst, const Tables& T, double s, int pre, int post,
+                                hipStream_t st) {
+  if (n_work <= 0) return hipSuccess;
+  if (elems == 8192)
+    hipLaunchKernelGGL((k_fft_c2c_t<8192, 512, float2, double2>), dim3(n_work), dim3(512), 0, st, n_arr, offs, work,
+                       src, dst, T, s, pre, post);
+  else
+    hipLaunchKernelGGL((k_fft_c2c_t<4096, 256, float2, double2>), dim3(n_work), dim3(256), 0, st, n_arr, offs, work,
+                       src, dst, T, s, pre, post);
+  return hipGetLastError();
+}
+hipError_t launch_fft_c2c_t_d2f(int elems, const int* n_arr, const int64_t* offs, const FftWork* work, int n_work,
+                                const double2* src, float2* dst, const Tables& T, double s, int pre, int post,
+                                hipStream_t st) {
+  if (n_work <= 0) return hipSuccess;
+  if (elems == 8192)
+    hipLaunchKernelGGL((k_fft_c2c_t<8192, 512, double2, float2>), dim3(n_work), dim3(512), 0, st, n_arr, offs, work,
+                       src, dst, T, s, pre, post);
+  else
+    hipLaunchKernelGGL((k_fft_c2c_t<4096, 256, double2, float2>), dim3(n_work), dim3(256), 0, st, n_arr, offs, work,
+                       src, dst, T, s, pre, post);
+  return hipGetLastError();
+}
+
+}  // namespace mi

@@ -1,0 +1,719 @@
+// C ABI of the imaging hot path: contexts, plans, argument validation, launches.
+//
+// The entry points follow Algorithm 1: dirty_image (gridding with natural/uniform
+// weighting, inverse FFT, grid correction) returning the dirty image and dirty beam, and
+// the CLEAN loop (Sec. 4.3) with restore; plus the adjoint (FFT then degrid).
+//
+// A plan is built the first time a batch descriptor is seen (keyed by its contents): it
+// holds the per-instance device descriptors, tile/work maps and the workspace, so later
+// calls with the same descriptor launch without allocating or synchronising.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/mi.h"
+#include "mi_internal.h"
+#include "mi_tables.h"
+
+namespace mi {
+
+
+// launchers (defined next to their kernels)
+hipError_t launch_bin(const InstDesc*, int, const float2*, const float*, const Tables&, float*, double*, int*, int*,
+                      float*, int*, int*, int*, int*, int*, int*, int, int, size_t, hipStream_t);
+hipError_t launch_grid(const InstDesc*, const int*, int, int, const float2*, const float2*, const float*,
+                       const float*, const int*, const int*, const int*, const Tables&, double2*, int, hipStream_t);
+hipError_t launch_grid_f32(const InstDesc*, const int*, int, int, const float2*, const float2*, const float*,
+                           const float*, const int*, const int*, const int*, const Tables&, float2*, int,
+                           hipStream_t);
+hipError_t launch_expand_full(const InstDesc*, int, int, const double2*, float2*, const int64_t*, hipStream_t);
+hipError_t launch_fill_u32(unsigned*, int64_t, unsigned, hipStream_t);
+hipError_t launch_fft_a(int, const InstDesc*, const FftWork*, int, int, double2*, const Tables&, hipStream_t);
+hipError_t launch_fft_b_c2r(int, const InstDesc*, const FftWork*, int, int, const double2*, const double*,
+                            const Tables&, float*, hipStream_t);
+hipError_t launch_fft_b_r2c(int, const InstDesc*, const FftWork*, int, const float*, const Tables&, double2*,
+                            hipStream_t);
+hipError_t launch_fft_a_fwd(int, const InstDesc*, const FftWork*, int, const Tables&, double2*, hipStream_t);
+hipError_t launch_fft_c2c_t_f2d(int, const int*, const int64_t*, const FftWork*, int, const float2*, double2*,
+                                const Tables&, double, int, int, hipStream_t);
+hipError_t launch_fft_c2c_t_d2f(int, const int*, const int64_t*, const FftWork*, int, const double2*, float2*,
+                                const Tables&, double, int, int, hipStream_t);
+hipError_t clean_max_blocks_per_cu(size_t, int*);
+hipError_t launch_clean(const CleanArgs&, int, size_t, hipStream_t);
+hipError_t launch_beamfit(const InstDesc*, int, const float*, double*, int*, int*, hipStream_t);
+hipError_t launch_degrid(const InstDesc*, int, int, const float2*, const float*, const float*, const double*,
+                         const double2*, const Tables&, int, float2*, hipStream_t);
+
+// LDS block (complex doubles) used by the FFT kernels for a transform of length P, and
+// the lines (pass A) / rows (pass B) it holds.
+int fft_elems_for(int P) { return P > FFT_ELEMS_SMALL ? FFT_ELEMS_LARGE : FFT_ELEMS_SMALL; }
+int fft_lines_per_block_host(int P, int elems) {
+  int nl = elems / P;
+  return nl > P / 2 ? P / 2 : nl;
+}
+
+// --------------------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+};
+
+struct MiError {
+  mi_status code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(mi_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  throw MiError{code, buf};
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) fail(MI_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+T* dev_alloc(DevBuf& b, size_t count) {
+  size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+  if (b.bytes >= bytes) return static_cast<T*>(b.p);
+  if (b.p) { (void)hipFree(b.p); b.p = nullptr; b.bytes = 0; }
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) { b.p = nullptr; fail(MI_ERR_NOMEM, "hipMalloc(%zu bytes) failed", bytes); }
+  b.bytes = bytes;
+  return static_cast<T*>(b.p);
+}
+
+template <class T>
+T* upload(DevBuf& b, const std::vector<T>& h) {
+  T* d = dev_alloc<T>(b, h.size());
+  if (!h.empty()) HIPCHK(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return d;
+}
+
+uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* c = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+  return h;
+}
+
+struct CleanPlan {
+  std::vector<int32_t> niter;
+  std::vector<float> thr;
+  bool has_thr = false;
+  int G = 0, T = 0, xcd_map = 0, n_blocks = 0;
+  size_t lds = 0;
+  int64_t total_comp = 0;
+  DevBuf team_off, team_imgs, niter_d, thr_d, comp_off, slots, bar, comp_idx, comp_flux, cbeam, rrad;
+};
+
+struct Plan {
+  // key
+  std::vector<int64_t> off;
+  std::vector<int32_t> n;
+  std::vector<double> cell;
+  std::vector<int8_t> mode;
+  int n_inst = 0;
+  int64_t total_vis = 0;
+  int max_N = 0, max_nvis = 0;
+  std::vector<InstDesc> h_inst;
+  int64_t total_img = 0, total_beam = 0, total_gd = 0, total_gb = 0, total_ent = 0, total_cnt = 0;
+  int tiles_d = 0, tiles_b = 0;
+  size_t bin_lds = 0;
+  int n_wa_d = 0, n_wb_d = 0, n_wa_b = 0, n_wb_b = 0;
+  int elems_d = FFT_ELEMS_SMALL, elems_b = FFT_ELEMS_SMALL;
+  DevBuf inst, tile_inst_d, tile_inst_b, wa_d, wb_d, wa_b, wb_b;
+  // workspace
+  DevBuf wts, b0, nkept, cnt, ent_d, ent_b, ts_d, tc_d, ts_b, tc_b, gd, gb, status_ws, full_off;
+  std::map<uint64_t, std::unique_ptr<CleanPlan>> cleans;
+};
+
+struct IfftPlan {
+  std::vector<int32_t> n;
+  std::vector<int64_t> offs;
+  int64_t total = 0;
+  int n_work1 = 0;
+  int elems = FFT_ELEMS_SMALL;
+  DevBuf n_d, offs_d, work;
+};
+
+}  // namespace mi
+
+struct mi_ctx {
+  int device = 0;
+  std::string err;
+  mi::Tables T{};
+  mi::DevBuf tab, tsum, tw, icorr;
+  std::map<uint64_t, std::unique_ptr<mi::Plan>> plans;
+  std::map<uint64_t, std::unique_ptr<mi::IfftPlan>> ifft_plans;
+  mi::DevBuf ifft_scratch;
+  int fail_inst = -1;
+  int n_cu = 256;
+};
+
+namespace mi {
+namespace {
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2i(int v) { int r = 0; while ((1 << r) < v) ++r; return r; }
+
+void check_batch(const mi_batch* b) {
+  if (!b) fail(MI_ERR_ARG, "batch is NULL");
+  if (b->n_inst < 1) fail(MI_ERR_ARG, "batch->n_inst must be >= 1 (got %d)", b->n_inst);
+  if (!b->vis_offset || !b->n_img || !b->cell_rad || !b->weight_mode)
+    fail(MI_ERR_ARG, "batch host arrays (vis_offset, n_img, cell_rad, weight_mode) must not be NULL");
+  if (b->vis_offset[0] != 0) fail(MI_ERR_SHAPE, "vis_offset[0] must be 0");
+  for (int i = 0; i < b->n_inst; ++i) {
+    const int N = b->n_img[i];
+    if (!is_pow2(N) || N < N_MIN || N > N_MAX)
+      fail(MI_ERR_SHAPE, "n_img[%d] = %d is not a power of two in [%d, %d]", i, N, N_MIN, N_MAX);
+    if (!(b->cell_rad[i] > 0.0) || !std::isfinite(b->cell_rad[i]))
+      fail(MI_ERR_ARG, "cell_rad[%d] must be finite and > 0", i);
+    if (b->weight_mode[i] != MI_NATURAL && b->weight_mode[i] != MI_UNIFORM)
+      fail(MI_ERR_ARG, "weight_mode[%d] = %d is not MI_NATURAL or MI_UNIFORM", i, (int)b->weight_mode[i]);
+    const int64_t cnt = b->vis_offset[i + 1] - b->vis_offset[i];
+    if (cnt < 0) fail(MI_ERR_SHAPE, "vis_offset must be non-decreasing (instance %d)", i);
+    if (cnt > (1 << 27)) fail(MI_ERR_SHAPE, "instance %d has %lld visibilities (max 2^27)", i, (long long)cnt);
+  }
+}
+
+Plan* get_plan(mi_ctx* ctx, const mi_batch* b) {
+  check_batch(b);
+  const int n = b->n_inst;
+  uint64_t h = fnv1a(&n, sizeof n);
+  h = fnv1a(b->vis_offset, sizeof(int64_t) * (n + 1), h);
+  h = fnv1a(b->n_img, sizeof(int32_t) * n, h);
+  h = fnv1a(b->cell_rad, sizeof(double) * n, h);
+  h = fnv1a(b->weight_mode, sizeof(int8_t) * n, h);
+  auto it = ctx->plans.find(h);
+  if (it != ctx->plans.end()) {
+    Plan* p = it->second.get();
+    if (p->n_inst == n && std::equal(p->off.begin(), p->off.end(), b->vis_offset) &&
+        std::equal(p->n.begin(), p->n.end(), b->n_img) && std::equal(p->cell.begin(), p->cell.end(), b->cell_rad) &&
+        std::equal(p->mode.begin(), p->mode.end(), b->weight_mode))
+      return p;
+  }
+  if (ctx->plans.size() >= 16) ctx->plans.erase(ctx->plans.begin());
+  auto P = std::make_unique<Plan>();
+  P->n_inst = n;
+  P->off.assign(b->vis_offset, b->vis_offset + n + 1);
+  P->n.assign(b->n_img, b->n_img + n);
+  P->cell.assign(b->cell_rad, b->cell_rad + n);
+  P->mode.assign(b->weight_mode, b->weight_mode + n);
+  P->total_vis = P->off[n];
+  P->h_inst.resize(n);
+  std::vector<int> tile_inst_d, tile_inst_b;
+  std::vector<FftWork> wa_d, wb_d, wa_b, wb_b;
+  int max_tiles = 0;
+  int maxN = 0;
+  for (int i = 0; i < n; ++i) maxN = std::max(maxN, (int)b->n_img[i]);
+  P->elems_d = fft_elems_for(maxN);
+  P->elems_b = fft_elems_for(2 * maxN);
+  for (int i = 0; i < n; ++i) {
+    InstDesc& d = P->h_inst[i];
+    std::memset(&d, 0, sizeof d);
+    const int N = P->n[i];
+    d.vis_off = P->off[i];
+    d.n_vis = (int32_t)(P->off[i + 1] - P->off[i]);
+    d.N = N;
+    d.log2N = ilog2i(N);
+    d.mode = P->mode[i];
+    d.scale = (double)N * P->cell[i];
+    d.img_off = P->total_img;
+    d.beam_off = P->total_beam;
+    d.gd_off = P->total_gd;
+    d.gb_off = P->total_gb;
+    d.ent_off = P->total_ent;
+    d.cnt_off = d.mode == MI_UNIFORM ? P->total_cnt : -1;
+    d.tile_base_d = P->tiles_d;
+    d.tile_base_b = P->tiles_b;
+    P->total_img += (int64_t)N * N;
+    P->total_beam += 4LL * N * N;
+    P->total_gd += (int64_t)N * N / 2;
+    P->total_gb += 2LL * N * N;
+    P->total_ent += (int64_t)ENT_PER_VIS * d.n_vis;
+    if (d.mode == MI_UNIFORM) P->total_cnt += (int64_t)N * N;
+    const int ntd = (N / 2 / TK) * (N / TJ), ntb = (N / TK) * (2 * N / TJ);
+    P->tiles_d += ntd;
+    P->tiles_b += ntb;
+    max_tiles = std::max(max_tiles, std::max(ntd, ntb));
+    for (int t = 0; t < ntd; ++t) tile_inst_d.push_back(i);
+    for (int t = 0; t < ntb; ++t) tile_inst_b.push_back(i);
+    const int nld = fft_lines_per_block_host(N, P->elems_d), nlb = fft_lines_per_block_host(2 * N, P->elems_b);
+    for (int l = 0; l < N / 2; l += nld) wa_d.push_back({i, l});
+    for (int y = 0; y < N; y += nld) wb_d.push_back({i, y});
+    for (int l = 0; l < N; l += nlb) wa_b.push_back({i, l});
+    for (int y = 0; y < 2 * N; y += nlb) wb_b.push_back({i, y});
+    P->max_N = std::max(P->max_N, N);
+    P->max_nvis = std::max(P->max_nvis, d.n_vis);
+  }
+  if (P->total_ent >= (1LL << 31)) fail(MI_ERR_SHAPE, "batch too large: %lld gridding entries", (long long)P->total_ent);
+  P->bin_lds = (size_t)max_tiles * sizeof(int);
+  if (P->bin_lds > 140 * 1024) fail(MI_ERR_UNSUPPORTED, "tile count per instance too large");
+  upload(P->inst, P->h_inst);
+  upload(P->tile_inst_d, tile_inst_d);
+  upload(P->tile_inst_b, tile_inst_b);
+  upload(P->wa_d, wa_d);
+  upload(P->wb_d, wb_d);
+  upload(P->wa_b, wa_b);
+  upload(P->wb_b, wb_b);
+  P->n_wa_d = (int)wa_d.size();
+  P->n_wb_d = (int)wb_d.size();
+  P->n_wa_b = (int)wa_b.size();
+  P->n_wb_b = (int)wb_b.size();
+  Plan* raw = P.get();
+  ctx->plans[h] = std::move(P);
+  return raw;
+}
+
+// Prep + weights + B0 + binning (k_bin).  Returns the status pointer used.
+int* run_bin(mi_ctx* ctx, Plan* P, const mi_batch* b, const float* uv, const float* w_in, bool beam,
+             hipStream_t st) {
+  float* wts = dev_alloc<float>(P->wts, P->total_vis);
+  double* b0 = dev_alloc<double>(P->b0, 2 * P->n_inst);
+  int* nk = dev_alloc<int>(P->nkept, P->n_inst);
+  float* cnt = dev_alloc<float>(P->cnt, P->total_cnt);
+  int* ed = dev_alloc<int>(P->ent_d, P->total_ent);
+  int* eb = beam ? dev_alloc<int>(P->ent_b, P->total_ent) : nullptr;
+  int* tsd = dev_alloc<int>(P->ts_d, P->tiles_d);
+  int* tcd = dev_alloc<int>(P->tc_d, P->tiles_d);
+  int* tsb = beam ? dev_alloc<int>(P->ts_b, P->tiles_b) : nullptr;
+  int* tcb = beam ? dev_alloc<int>(P->tc_b, P->tiles_b) : nullptr;
+  int* status = b->status ? b->status : dev_alloc<int>(P->status_ws, P->n_inst);
+  HIPCHK(launch_bin(static_cast<const InstDesc*>(P->inst.p), P->n_inst, reinterpret_cast<const float2*>(uv), w_in,
+                    ctx->T, wts, b0, nk, status, cnt, ed, eb, tsd, tcd, tsb, tcb, ctx->fail_inst, beam ? 1 : 0,
+                    P->bin_lds, st));
+  return status;
+}
+
+template <class OutT>
+void run_grid(mi_ctx* ctx, Plan* P, const mi_c64* vis, const float* uv, const float* w_in, bool beam, OutT* out,
+              int modulate, hipStream_t st) {
+  const InstDesc* inst = static_cast<const InstDesc*>(P->inst.p);
+  const int* tmap = static_cast<const int*>(beam ? P->tile_inst_b.p : P->tile_inst_d.p);
+  const int nt = beam ? P->tiles_b : P->tiles_d;
+  const int* ent = static_cast<const int*>(beam ? P->ent_b.p : P->ent_d.p);
+  const int* ts = static_cast<const int*>(beam ? P->ts_b.p : P->ts_d.p);
+  const int* tc = static_cast<const int*>(beam ? P->tc_b.p : P->tc_d.p);
+  const float2* v = beam ? nullptr : reinterpret_cast<const float2*>(vis);
+  const float* wts = static_cast<const float*>(P->wts.p);
+  if constexpr (std::is_same<OutT, double2>::value)
+    HIPCHK(launch_grid(inst, tmap, nt, beam ? 1 : 0, v, reinterpret_cast<const float2*>(uv), w_in, wts, ent, ts, tc,
+                       ctx->T, out, modulate, st));
+  else
+    HIPCHK(launch_grid_f32(inst, tmap, nt, beam ? 1 : 0, v, reinterpret_cast<const float2*>(uv), w_in, wts, ent, ts,
+                           tc, ctx->T, out, modulate, st));
+}
+
+void run_image(mi_ctx* ctx, Plan* P, bool beam, float* out, hipStream_t st) {
+  const InstDesc* inst = static_cast<const InstDesc*>(P->inst.p);
+  double2* g = beam ? static_cast<double2*>(P->gb.p) : static_cast<double2*>(P->gd.p);
+  const double* b0 = static_cast<const double*>(P->b0.p);
+  if (!beam) {
+    HIPCHK(launch_fft_a(P->elems_d, inst, static_cast<const FftWork*>(P->wa_d.p), P->n_wa_d, 0, g, ctx->T, st));
+    HIPCHK(launch_fft_b_c2r(P->elems_d, inst, static_cast<const FftWork*>(P->wb_d.p), P->n_wb_d, 0, g, b0, ctx->T,
+                            out, st));
+  } else {
+    HIPCHK(launch_fft_a(P->elems_b, inst, static_cast<const FftWork*>(P->wa_b.p), P->n_wa_b, 1, g, ctx->T, st));
+    HIPCHK(launch_fft_b_c2r(P->elems_b, inst, static_cast<const FftWork*>(P->wb_b.p), P->n_wb_b, 1, g, b0, ctx->T,
+                            out, st));
+  }
+}
+
+void copy_b0(Plan* P, double* b0_out, hipStream_t st) {
+  if (b0_out)
+    HIPCHK(hipMemcpyAsync(b0_out, P->b0.p, sizeof(double) * 2 * P->n_inst, hipMemcpyDeviceToDevice, st));
+}
+
+template <class F>
+mi_status guard(mi_ctx* ctx, F&& f) {
+  if (!ctx) return MI_ERR_ARG;
+  ctx->err.clear();
+  try {
+    f();
+    return MI_OK;
+  } catch (const MiError& e) {
+    ctx->err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    ctx->err = "host allocation failed";
+    return MI_ERR_NOMEM;
+  } catch (...) {
+    ctx->err = "unexpected internal error";
+    return MI_ERR_DEVICE;
+  }
+}
+
+void need(const void* p, const char* name) {
+  if (!p) fail(MI_ERR_ARG, "%s must not be NULL", name);
+}
+
+}  // namespace
+}  // namespace mi
+
+using namespace mi;
+
+extern "C" {
+
+const char* mi_version(void) { return "mi 0.1 (gfx950)"; }
+
+const char* mi_last_error(const mi_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+mi_status mi_ctx_create(mi_ctx** out, int device) {
+  if (!out) return MI_ERR_ARG;
+  *out = nullptr;
+  mi_ctx* ctx = nullptr;
+  try {
+    ctx = new mi_ctx();
+  } catch (...) {
+    return MI_ERR_NOMEM;
+  }
+  mi_status s = guard(ctx, [&] {
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) fail(MI_ERR_ARG, "device %d out of range (%d devices)", device, ndev);
+    HIPCHK(hipSetDevice(device));
+    ctx->device = device;
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, device));
+    ctx->n_cu = prop.multiProcessorCount;
+    const char* fi = std::getenv("MI_TEST_FAIL_INSTANCE");
+    ctx->fail_inst = fi ? std::atoi(fi) : -1;
+    HostTables H = build_host_tables(W, OS, 1.0, 200);
+    ctx->T.tab = upload(ctx->tab, H.tab);
+    ctx->T.tsum = upload(ctx->tsum, H.tsum);
+    ctx->T.twiddle = reinterpret_cast<const double2*>(upload(ctx->tw, H.twiddle));
+    ctx->T.inv_corr = upload(ctx->icorr, H.inv_corr);
+    ctx->T.inv_corr0_sq = 1.0 / (H.corr0 * H.corr0);
+  });
+  if (s != MI_OK) {
+    std::fprintf(stderr, "mi_ctx_create: %s\n", ctx->err.c_str());
+    delete ctx;
+    return s;
+  }
+  *out = ctx;
+  return MI_OK;
+}
+
+mi_status mi_ctx_destroy(mi_ctx* ctx) {
+  if (!ctx) return MI_ERR_ARG;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  delete ctx;
+  return MI_OK;
+}
+
+mi_status mi_grid(mi_ctx* ctx, const mi_batch* batch, const mi_c64* vis, const float* uv, const float* w_in,
+                  int which, int layout, mi_c64* grid_out, double* b0_out, int32_t* n_kept_out,
+                  hipStream_t stream) {
+  return guard(ctx, [&] {
+    if (which < 0 || which > 2) fail(MI_ERR_ARG, "which must be 0 (dirty), 1 (beam) or 2 (both)");
+    if (layout != MI_LAYOUT_FULL && layout != MI_LAYOUT_HALF) fail(MI_ERR_ARG, "bad layout %d", layout);
+    need(uv, "uv");
+    need(w_in, "w_in");
+    need(grid_out, "grid_out");
+    if (which != 1) need(vis, "vis");
+    if (reinterpret_cast<uintptr_t>(grid_out) % 16) fail(MI_ERR_ARG, "grid_out must be 16-byte aligned");
+    HIPCHK(hipSetDevice(ctx->device));
+    Plan* P = get_plan(ctx, batch);
+    const bool want_d = which != 1, want_b = which != 0;
+    run_bin(ctx, P, batch, uv, w_in, want_b, stream);
+    float2* out = reinterpret_cast<float2*>(grid_out);
+    const int64_t full_d = [&] { int64_t s = 0; for (int N : P->n) s += (int64_t)N * N; return s; }();
+    if (layout == MI_LAYOUT_HALF) {
+      if (want_d) run_grid<float2>(ctx, P, vis, uv, w_in, false, out, 0, stream);
+      if (want_b) run_grid<float2>(ctx, P, vis, uv, w_in, true, out + (want_d ? P->total_gd : 0), 0, stream);
+    } else {
+      std::vector<int64_t> offs(P->n_inst);
+      int64_t* offd = dev_alloc<int64_t>(P->full_off, 2 * P->n_inst);
+      std::vector<int64_t> h(2 * P->n_inst);
+      int64_t s = 0;
+      for (int i = 0; i < P->n_inst; ++i) { h[i] = s; s += (int64_t)P->n[i] * P->n[i]; }
+      int64_t s2 = want_d ? full_d : 0;
+      for (int i = 0; i < P->n_inst; ++i) { h[P->n_inst + i] = s2; s2 += 4LL * P->n[i] * P->n[i]; }
+      HIPCHK(hipMemcpyAsync(offd, h.data(), sizeof(int64_t) * h.size(), hipMemcpyHostToDevice, stream));
+      HIPCHK(hipStreamSynchronize(stream));   // pageable source: keep it alive until copied
+      const InstDesc* inst = static_cast<const InstDesc*>(P->inst.p);
+      if (want_d) {
+        double2* g = dev_alloc<double2>(P->gd, P->total_gd);
+        run_grid<double2>(ctx, P, vis, uv, w_in, false, g, 0, stream);
+        HIPCHK(launch_expand_full(inst, P->n_inst, 0, g, out, offd, stream));
+      }
+      if (want_b) {
+        double2* g = dev_alloc<double2>(P->gb, P->total_gb);
+        run_grid<double2>(ctx, P, vis, uv, w_in, true, g, 0, stream);
+        HIPCHK(launch_expand_full(inst, P->n_inst, 1, g, out, offd + P->n_inst, stream));
+      }
+    }
+    copy_b0(P, b0_out, stream);
+    if (n_kept_out)
+      HIPCHK(hipMemcpyAsync(n_kept_out, P->nkept.p, sizeof(int) * P->n_inst, hipMemcpyDeviceToDevice, stream));
+  });
+}
+
+mi_status mi_ifft2(mi_ctx* ctx, mi_c64* data, const int32_t* n, const int64_t* offs, int32_t n_inst,
+                   hipStream_t stream) {
+  return guard(ctx, [&] {
+    need(data, "data");
+    need(n, "n");
+    need(offs, "offs");
+    if (n_inst < 1) fail(MI_ERR_ARG, "n_inst must be >= 1");
+    for (int i = 0; i < n_inst; ++i) {
+      if (!is_pow2(n[i]) || n[i] < 64 || n[i] > 8192)
+        fail(MI_ERR_SHAPE, "n[%d] = %d is not a power of two in [64, 8192]", i, n[i]);
+      if (offs[i] < 0) fail(MI_ERR_SHAPE, "offs[%d] < 0", i);
+    }
+    if (reinterpret_cast<uintptr_t>(data) % 8) fail(MI_ERR_ARG, "data must be 8-byte aligned");
+    HIPCHK(hipSetDevice(ctx->device));
+    uint64_t h = fnv1a(&n_inst, sizeof n_inst);
+    h = fnv1a(n, sizeof(int32_t) * n_inst, h);
+    h = fnv1a(offs, sizeof(int64_t) * n_inst, h);
+    auto it = ctx->ifft_plans.find(h);
+    IfftPlan* P;
+    if (it != ctx->ifft_plans.end() && std::equal(it->second->n.begin(), it->second->n.end(), n) &&
+        std::equal(it->second->offs.begin(), it->second->offs.end(), offs)) {
+      P = it->second.get();
+    } else {
+      if (ctx->ifft_plans.size() >= 16) ctx->ifft_plans.erase(ctx->ifft_plans.begin());
+      auto up = std::make_unique<IfftPlan>();
+      up->n.assign(n, n + n_inst);
+      up->offs.assign(offs, offs + n_inst);
+      std::vector<FftWork> work;
+      int64_t end = 0;
+      int maxn = 0;
+      for (int i = 0; i < n_inst; ++i) maxn = std::max(maxn, n[i]);
+      up->elems = fft_elems_for(maxn);
+      for (int i = 0; i < n_inst; ++i) {
+        int nl = up->elems / n[i];
+        if (nl > n[i]) nl = n[i];
+        for (int l = 0; l < n[i]; l += nl) work.push_back({i, l});
+        end = std::max<int64_t>(end, offs[i] + (int64_t)n[i] * n[i]);
+      }
+      up->total = end;
+      up->n_work1 = (int)work.size();
+      upload(up->n_d, up->n);
+      upload(up->offs_d, up->offs);
+      upload(up->work, work);
+      P = up.get();
+      ctx->ifft_plans[h] = std::move(up);
+    }
+    double2* scratch = dev_alloc<double2>(ctx->ifft_scratch, P->total);
+    float2* d = reinterpret_cast<float2*>(data);
+    HIPCHK(launch_fft_c2c_t_f2d(P->elems, static_cast<const int*>(P->n_d.p), static_cast<const int64_t*>(P->offs_d.p),
+                                static_cast<const FftWork*>(P->work.p), P->n_work1, d, scratch, ctx->T, +1.0, 1, 0,
+                                stream));
+    HIPCHK(launch_fft_c2c_t_d2f(P->elems, static_cast<const int*>(P->n_d.p), static_cast<const int64_t*>(P->offs_d.p),
+                                static_cast<const FftWork*>(P->work.p), P->n_work1, scratch, d, ctx->T, +1.0, 0, 1,
+                                stream));
+  });
+}
+
+mi_status mi_dirty_image(mi_ctx* ctx, const mi_batch* batch, const mi_c64* vis, const float* uv, const float* w_in,
+                         float* dirty_out, float* beam_out, double* b0_out, hipStream_t stream) {
+  return guard(ctx, [&] {
+    need(vis, "vis");
+    need(uv, "uv");
+    need(w_in, "w_in");
+    need(dirty_out, "dirty_out");
+    HIPCHK(hipSetDevice(ctx->device));
+    Plan* P = get_plan(ctx, batch);
+    const bool beam = beam_out != nullptr;
+    run_bin(ctx, P, batch, uv, w_in, beam, stream);
+    double2* gd = dev_alloc<double2>(P->gd, P->total_gd);
+    run_grid<double2>(ctx, P, vis, uv, w_in, false, gd, 1, stream);
+    run_image(ctx, P, false, dirty_out, stream);
+    if (beam) {
+      double2* gb = dev_alloc<double2>(P->gb, P->total_gb);
+      run_grid<double2>(ctx, P, vis, uv, w_in, true, gb, 1, stream);
+      run_image(ctx, P, true, beam_out, stream);
+    }
+    copy_b0(P, b0_out, stream);
+  });
+}
+
+mi_status mi_dirty_beam(mi_ctx* ctx, const mi_batch* batch, const float* uv, const float* w_in, float* beam_out,
+                        hipStream_t stream) {
+  return guard(ctx, [&] {
+    need(uv, "uv");
+    need(w_in, "w_in");
+    need(beam_out, "beam_out");
+    HIPCHK(hipSetDevice(ctx->device));
+    Plan* P = get_plan(ctx, batch);
+    run_bin(ctx, P, batch, uv, w_in, true, stream);
+    double2* gb = dev_alloc<double2>(P->gb, P->total_gb);
+    run_grid<double2>(ctx, P, nullptr, uv, w_in, true, gb, 1, stream);
+    run_image(ctx, P, true, beam_out, stream);
+  });
+}
+
+mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty, const float* beam,
+                          const mi_clean_params* prm, float* residual_out, double* model_out, int32_t* comp_idx,
+                          double* comp_flux, int32_t* n_comp_out, float* restored_out, double* cbeam_out,
+                          hipStream_t stream) {
+  return guard(ctx, [&] {
+    need(dirty, "dirty");
+    need(beam, "beam");
+    need(prm, "params");
+    need(residual_out, "residual_out");
+    need(prm->niter, "params->niter");
+    if ((comp_idx == nullptr) != (comp_flux == nullptr)) fail(MI_ERR_ARG, "comp_idx and comp_flux: both or neither");
+    if (!(prm->gain > 0.0f && prm->gain <= 1.0f)) fail(MI_ERR_ARG, "gain must be in (0, 1]");
+    HIPCHK(hipSetDevice(ctx->device));
+    Plan* P = get_plan(ctx, batch);
+    const int n = P->n_inst;
+    for (int i = 0; i < n; ++i)
+      if (prm->niter[i] < 0) fail(MI_ERR_ARG, "niter[%d] < 0", i);
+    int G_min = 1;
+    for (int N : P->n) G_min = std::max(G_min, (N * N) / 32768);
+    if (G_min > 256) fail(MI_ERR_UNSUPPORTED, "CLEAN of N = %d does not fit on-chip (max N = 2048)", P->max_N);
+    // clean plan: team shape, LPT assignment, device copies of niter / thresholds
+    uint64_t h = fnv1a(prm->niter, sizeof(int32_t) * n);
+    const bool has_thr = prm->threshold != nullptr;
+    if (has_thr) h = fnv1a(prm->threshold, sizeof(float) * n, h ^ 0x9e3779b97f4a7c15ull);
+    CleanPlan* C = nullptr;
+    auto it = P->cleans.find(h);
+    if (it != P->cleans.end() && std::equal(it->second->niter.begin(), it->second->niter.end(), prm->niter) &&
+        it->second->has_thr == has_thr &&
+        (!has_thr || std::equal(it->second->thr.begin(), it->second->thr.end(), prm->threshold))) {
+      C = it->second.get();
+    } else {
+      if (P->cleans.size() >= 8) P->cleans.erase(P->cleans.begin());
+      auto up = std::make_unique<CleanPlan>();
+      C = up.get();
+      C->niter.assign(prm->niter, prm->niter + n);
+      C->has_thr = has_thr;
+      if (has_thr) C->thr.assign(prm->threshold, prm->threshold + n);
+      // team size: enough workgroups for the largest residual to fit in LDS, then grown
+      // while the chip has idle CUs
+      int per_cu = 0;
+      int G = G_min;
+      size_t lds = (size_t)(P->max_N * P->max_N / G) * sizeof(float);
+      HIPCHK(clean_max_blocks_per_cu(lds, &per_cu));
+      if (per_cu < 1) fail(MI_ERR_UNSUPPORTED, "CLEAN kernel cannot be resident (LDS %zu bytes)", lds);
+      const int cap = per_cu * ctx->n_cu;
+      while (G * 2 <= 256 && (int64_t)G * 2 * n <= cap && G * 2 <= (P->max_N * P->max_N) / 1024) G *= 2;
+      lds = (size_t)(P->max_N * P->max_N / G) * sizeof(float);
+      HIPCHK(clean_max_blocks_per_cu(lds, &per_cu));
+      const int cap2 = per_cu * ctx->n_cu;
+      int T = std::min(n, cap2 / G);
+      if (T < 1) fail(MI_ERR_UNSUPPORTED, "CLEAN team of %d workgroups exceeds the device", G);
+      int xcd = 0;
+      if (T >= 8 && G <= 32) { T -= T % 8; xcd = 1; }
+      C->G = G;
+      C->T = T;
+      C->xcd_map = xcd;
+      C->n_blocks = T * G;
+      C->lds = lds;
+      // LPT: images sorted by N^2 * niter, each to the least-loaded team
+      std::vector<int> order(n);
+      for (int i = 0; i < n; ++i) order[i] = i;
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (double)P->n[a] * P->n[a] * (C->niter[a] + 1) > (double)P->n[b] * P->n[b] * (C->niter[b] + 1);
+      });
+      std::vector<double> load(T, 0.0);
+      std::vector<std::vector<int>> lists(T);
+      for (int i : order) {
+        int t = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        lists[t].push_back(i);
+        load[t] += (double)P->n[i] * P->n[i] * (C->niter[i] + 1);
+      }
+      std::vector<int> toff(T + 1, 0), timgs;
+      for (int t = 0; t < T; ++t) {
+        toff[t + 1] = toff[t] + (int)lists[t].size();
+        timgs.insert(timgs.end(), lists[t].begin(), lists[t].end());
+      }
+      std::vector<int64_t> coff(n);
+      int64_t s = 0;
+      for (int i = 0; i < n; ++i) { coff[i] = s; s += C->niter[i]; }
+      C->total_comp = s;
+      upload(C->team_off, toff);
+      upload(C->team_imgs, timgs);
+      upload(C->niter_d, C->niter);
+      if (has_thr) upload(C->thr_d, C->thr);
+      upload(C->comp_off, coff);
+      dev_alloc<unsigned long long>(C->slots, (size_t)T * 2 * G);
+      dev_alloc<unsigned>(C->bar, T);
+      P->cleans[h] = std::move(up);
+    }
+    int* status = batch->status;
+    if (status) HIPCHK(launch_fill_u32(reinterpret_cast<unsigned*>(status), n, 0u, stream));
+    const bool restore = restored_out != nullptr;
+    double* cbeam = cbeam_out;
+    int* rrad = dev_alloc<int>(C->rrad, n);
+    if (restore || cbeam_out) {
+      if (!cbeam) cbeam = dev_alloc<double>(C->cbeam, 6 * (size_t)n);
+      HIPCHK(launch_beamfit(static_cast<const InstDesc*>(P->inst.p), n, beam, cbeam, rrad, status, stream));
+    }
+    int* cidx = comp_idx;
+    double* cflx = comp_flux;
+    if (!cidx && restore) {
+      cidx = dev_alloc<int>(C->comp_idx, (size_t)std::max<int64_t>(C->total_comp, 1));
+      cflx = dev_alloc<double>(C->comp_flux, (size_t)std::max<int64_t>(C->total_comp, 1));
+    }
+    HIPCHK(launch_fill_u32(static_cast<unsigned*>(C->bar.p), C->T, 0u, stream));
+    CleanArgs A{};
+    A.inst = static_cast<const InstDesc*>(P->inst.p);
+    A.team_off = static_cast<const int*>(C->team_off.p);
+    A.team_imgs = static_cast<const int*>(C->team_imgs.p);
+    A.G = C->G;
+    A.xcd_map = C->xcd_map;
+    A.dirty = dirty;
+    A.beam = beam;
+    A.niter = static_cast<const int*>(C->niter_d.p);
+    A.thr = has_thr ? static_cast<const float*>(C->thr_d.p) : nullptr;
+    A.gain = prm->gain;
+    A.posonly = prm->positive_only ? 1 : 0;
+    A.cbeam = restore ? cbeam : nullptr;
+    A.rrad = rrad;
+    A.resid = residual_out;
+    A.model = model_out;
+    A.comp_off = static_cast<const int64_t*>(C->comp_off.p);
+    A.comp_idx = cidx;
+    A.comp_flux = cflx;
+    A.ncomp = n_comp_out;
+    A.restored = restored_out;
+    A.slots = static_cast<unsigned long long*>(C->slots.p);
+    A.bar = static_cast<unsigned*>(C->bar.p);
+    A.status = status;
+    HIPCHK(launch_clean(A, C->n_blocks, C->lds, stream));
+  });
+}
+
+mi_status mi_degrid(mi_ctx* ctx, const mi_batch* batch, const float* image, const float* uv, const float* w_in,
+                    int adjoint, mi_c64* vis_out, hipStream_t stream) {
+  return guard(ctx, [&] {
+    need(image, "image");
+    need(uv, "uv");
+    need(w_in, "w_in");
+    need(vis_out, "vis_out");
+    if (adjoint != 0 && adjoint != 1) fail(MI_ERR_ARG, "adjoint must be 0 or 1");
+    HIPCHK(hipSetDevice(ctx->device));
+    Plan* P = get_plan(ctx, batch);
+    run_bin(ctx, P, batch, uv, w_in, false, stream);
+    double2* g = dev_alloc<double2>(P->gd, P->total_gd);
+    const InstDesc* inst = static_cast<const InstDesc*>(P->inst.p);
+    HIPCHK(launch_fft_b_r2c(P->elems_d, inst, static_cast<const FftWork*>(P->wb_d.p), P->n_wb_d, image, ctx->T, g,
+                            stream));
+    HIPCHK(launch_fft_a_fwd(P->elems_d, inst, static_cast<const FftWork*>(P->wa_d.p), P->n_wa_d, ctx->T, g, stream));
+    HIPCHK(launch_degrid(inst, P->n_inst, P->max_nvis, reinterpret_cast<const float2*>(uv), w_in,
+                         static_cast<const float*>(P->wts.p), static_cast<const double*>(P->b0.p), g, ctx->T,
+                         adjoint, reinterpret_cast<float2*>(vis_out), stream));
+  });
+}
+
+}  // extern "C"

@@ -120,3 +120,26 @@ def test_restore_without_components_is_residual_and_single_component_is_gaussian
     out = clean.restore(np.zeros((N, N)), model, abc)
     assert out[4, 9] == 2.0
     assert abs(out[5, 9] - 2.0 * math.exp(-0.3)) < 1e-14 and abs(out[4, 10] - 2.0 * math.exp(-0.2)) < 1e-14
+
+
+def test_fit_degenerate_lobes_follow_pixel_count_rules():
+    N = 16
+    # plus-shaped lobe (only axis neighbours above 0.35): b fixed at 0, a and c exact
+    beam = _gauss_beam(N, 0.6, 0.0, 0.9)
+    (a, b, c, *_), flag = clean.fit_clean_beam(beam, return_flag=True)
+    assert clean.main_lobe(beam).sum() == 5
+    assert not flag and b == 0.0 and abs(a - 0.6) < 1e-12 and abs(c - 0.9) < 1e-12
+    # single-pixel lobe: one-pixel FWHM default, flagged
+    beam = _gauss_beam(N, 3.0, 0.0, 3.0)
+    (a, b, c, bmaj, bmin, _), flag = clean.fit_clean_beam(beam, return_flag=True)
+    assert flag and (a, b, c) == clean.DEGENERATE_ABC and abs(bmaj - 1.0) < 1e-12
+
+
+def test_replay_positive_only_uses_signed_peak():
+    wl = synth.random_instances(13, [32], m_range=(150, 150))
+    v, uv, w = wl.instance(0)
+    N, cell = 32, float(wl.cell_rad[0])
+    dirty = imager.dirty_image(v, uv, w, N, cell, 0)
+    beam = imager.dirty_beam(uv, w, N, cell, 0)
+    _, _, idx, flux = clean.hogbom(dirty, beam, niter=40, positive_only=True)
+    assert clean.replay(dirty, beam, idx, flux, positive_only=True)[0]
