@@ -1,0 +1,229 @@
+"""Benchmark of the MUSER imaging hot path on one MI355X.
+
+A step is one pass of the whole hot path over one batch: dirty image and dirty beam
+(prep, weighting, gridding, inverse FFT, correction), batched Hogbom CLEAN with clean-beam
+fit and restore, and the adjoint (FFT then degrid) of the residual.  The headline value is
+images/s for the 1024^2 MUSER-II-like batch (520 channels, 1770 baselines, 5000 CLEAN
+iterations each), with inputs resident in HBM.  Prints ONE JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c4|c1]
+                  [--no-cpu-baseline] [--no-plain] [--only-steps]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--only-steps", action="store_true", help="timed steps only (for profilers)")
+    ap.add_argument("--plain-subset", type=int, default=8)
+    return ap.parse_args()
+
+
+def make_workload(name):
+    from paper_1712_06913_amd import synth
+    if name == "c1":
+        return synth.c1_snapshot()
+    if name == "c2":
+        return synth.c2_muser1_batch()
+    if name == "c3":
+        return synth.c3_muser2()
+    return synth.c4_uneven()
+
+
+def cpu_baseline(wl):
+    """The FP64 oracle on one instance of the workload, single process (numpy, 1 thread)."""
+    from oracle import clean, imager
+    i = 0
+    v, uv, w = wl.instance(i)
+    N, cell, mode, niter = int(wl.n_img[i]), float(wl.cell_rad[i]), int(wl.weight_mode[i]), int(wl.niter[i])
+    t0 = time.perf_counter()
+    dirty = imager.dirty_image(v, uv, w, N, cell, mode)
+    beam = imager.dirty_beam(uv, w, N, cell, mode)
+    R, model, idx, flux = clean.hogbom(dirty, beam, gain=wl.gain, niter=niter)
+    abc = clean.fit_clean_beam(beam)
+    clean.restore(R, model, abc)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "images/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 of {wl.n_inst} instances of {wl.name} (N={N}, {len(v)} baselines, {niter} iterations), "
+                      f"full pipeline dirty+beam+CLEAN+restore in FP64 numpy, single process; {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: the imaging instances are independent and this build runs on "
+              f"a single MI355X (requested --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1712_06913_amd import api
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    log(f"generating workload {args.workload}")
+    wl = make_workload(args.workload)
+    log(f"workload {wl.name}: {wl.n_inst} instances, {int(wl.vis_offset[-1])} visibilities")
+    niter = wl.niter.astype(np.int32)
+    b = api.Batch.from_workload(wl, dev)
+    vis, uv, w = api.workload_tensors(wl, dev)
+    n_inst = wl.n_inst
+    img_elems = int(b.img_off[-1])
+    beam_elems = int(b.beam_off[-1])
+    dirty = torch.empty(img_elems, dtype=torch.float32, device=dev)
+    beam = torch.empty(beam_elems, dtype=torch.float32, device=dev)
+    b0 = torch.empty(2 * n_inst, dtype=torch.float64, device=dev)
+    grid_half = torch.empty(int((b.n_img.astype(np.int64) ** 2 // 2).sum() + (2 * b.n_img.astype(np.int64) ** 2).sum()),
+                            dtype=torch.complex64, device=dev)
+    adj = torch.empty(int(wl.vis_offset[-1]), dtype=torch.complex64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        api.dirty_image(b, vis, uv, w, beam=True, out=dirty, beam_out=beam, b0_out=b0)
+        if ev is not None:
+            ev[1].record(stream)
+        res = api.hogbom_clean(b, dirty, beam, niter, gain=wl.gain, restore=True)
+        if ev is not None:
+            ev[2].record(stream)
+        api.degrid(b, res["residual"], uv, w, adjoint=True, out=adj)
+        if ev is not None:
+            ev[3].record(stream)
+        return res
+
+    for i in range(args.warmup):
+        res = step()
+        torch.cuda.synchronize()
+        log(f"warmup step {i} done")
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        res = step(evs[k])
+    torch.cuda.synchronize()
+    log(f"{args.steps} timed steps done")
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+    img_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    clean_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    adj_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    if args.only_steps:
+        print(json.dumps({"ms_per_step": ms_step, "imaging_ms": img_ms, "clean_ms": clean_ms, "adjoint_ms": adj_ms}))
+        return
+    n_comp = res["n_comp"].cpu().numpy()
+    status = b.status.cpu().numpy()
+
+    # gridding alone (prep, weights, dirty grid, beam grid): gridded visibilities per second
+    _, _, nk = api.grid(b, vis, uv, w, which=2, layout=1, out=grid_half)
+    torch.cuda.synchronize()
+    kept = int(nk.cpu().numpy().sum())
+    ge = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    reps = 5
+    ge[0].record(stream)
+    for _ in range(reps):
+        api.grid(b, vis, uv, w, which=2, layout=1, out=grid_half)
+    ge[1].record(stream)
+    torch.cuda.synchronize()
+    grid_ms = ge[0].elapsed_time(ge[1]) / reps
+
+    # roofline of the dominant kernel (k_clean): algorithmic bytes = per iteration the
+    # beam window (4 N^2 bytes; the residual stays in LDS) plus once per image the dirty
+    # map in, residual + restored out (3 x 4 N^2) and the FP64 model out (8 N^2)
+    N2 = b.n_img.astype(np.float64) ** 2
+    clean_bytes = float(np.sum(4.0 * N2 * n_comp + 20.0 * N2))
+    achieved = clean_bytes / (clean_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_clean",
+            "kernel_ms": clean_ms, "algorithmic_bytes": clean_bytes}
+
+    out = {
+        "metric": "images/s (grid+iFFT+Hogbom CLEAN, 1024^2, batched)",
+        "value": n_inst / (ms_step * 1e-3),
+        "unit": "images/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (grid/FFT f64)", "data": "synthetic",
+        "config": {"workload": wl.name, "n_inst": n_inst, "N": sorted(set(int(x) for x in b.n_img)),
+                   "visibilities": int(wl.vis_offset[-1]), "niter_total": int(niter.sum()),
+                   "gain": wl.gain, "weighting": "natural" if not wl.weight_mode.any() else "mixed/uniform"},
+        "stage_ms": {"dirty_image_and_beam": img_ms, "clean_restore": clean_ms, "adjoint": adj_ms,
+                     "gridding_only": grid_ms},
+        "gridded_vis_per_s": kept / (grid_ms * 1e-3),
+        "kept_visibilities": kept,
+        "components_total": int(n_comp.sum()),
+        "instance_status_nonzero": int(np.count_nonzero(status)),
+        "roofline": roof,
+    }
+
+    if not args.no_plain:
+        # plain path: one instance per call, CLEAN spread over the whole GPU for that image
+        k = min(args.plain_subset, n_inst)
+        sub = wl.subset(range(k))
+        sb = api.Batch.from_workload(sub, dev)
+        sv, suv, sw = api.workload_tensors(sub, dev)
+        singles = []
+        for i in range(k):
+            s1 = sub.subset([i])
+            bb = api.Batch.from_workload(s1, dev)
+            tv, tuv, tw = api.workload_tensors(s1, dev)
+            singles.append((s1, bb, tv, tuv, tw))
+
+        def plain_once():
+            for s1, bb, tv, tuv, tw in singles:
+                d, bm, _ = api.dirty_image(bb, tv, tuv, tw, beam=True)
+                r = api.hogbom_clean(bb, d, bm, s1.niter, gain=s1.gain, restore=True)
+                api.degrid(bb, r["residual"], tuv, tw, adjoint=True)
+
+        def batched_once():
+            d, bm, _ = api.dirty_image(sb, sv, suv, sw, beam=True)
+            r = api.hogbom_clean(sb, d, bm, sub.niter, gain=sub.gain, restore=True)
+            api.degrid(sb, r["residual"], suv, sw, adjoint=True)
+
+        plain_once()
+        batched_once()
+        torch.cuda.synchronize()
+        log("plain/batched warmup done")
+        t0 = time.perf_counter()
+        plain_once()
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        batched_once()
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        out["plain"] = {"subset": f"first {k} instances", "plain_images_per_s": k / tp,
+                        "batched_images_per_s_same_subset": k / tb, "batched_over_plain_same_subset": tp / tb,
+                        "full_batch_over_plain": out["value"] / (k / tp)}
+
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -61,7 +61,8 @@ enum {
   MI_INST_LOBE_CLIPPED = 2,   /* clean-beam main lobe reached the fit box edge        */
   MI_INST_RESTORE_CLIPPED = 4,/* restoring Gaussian wider than the restore window     */
   MI_INST_TEST_FAILED = 8,    /* forced by MI_TEST_FAIL_INSTANCE (failure-path tests) */
-  MI_INST_ABORTED = 16        /* a CLEAN team barrier timed out; outputs incomplete     */
+  MI_INST_ABORTED = 16,       /* a CLEAN team barrier timed out; outputs incomplete     */
+  MI_INST_XCD_MISMATCH = 32   /* a CLEAN workgroup ran off the XCD its team relies on   */
 };
 
 /* Weighting mode, as Algorithm 1's wgtGrid_kernel: mode 1 = uniform, otherwise natural. */
@@ -91,6 +92,9 @@ typedef struct {
   const int32_t* niter;        /* host, n_inst, component cap per instance (>= 0)      */
   const float* threshold;      /* host, n_inst, stop when |peak| <= threshold; or NULL */
   int32_t positive_only;       /* 0: peak of |R| (default); 1: peak of R               */
+  int32_t team_size;           /* workgroups per image (power of two); 0 = automatic.
+                                  Values up to 32 keep an image on one XCD; larger teams
+                                  spread one image over several XCDs (the "plain" path) */
 } mi_clean_params;
 
 /* Create / destroy a context on HIP device `device`.  The context owns plans,

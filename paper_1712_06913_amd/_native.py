@@ -24,7 +24,8 @@ class MiBatch(ctypes.Structure):
 
 
 class MiCleanParams(ctypes.Structure):
-    _fields_ = [("gain", c_float), ("niter", c_void_p), ("threshold", c_void_p), ("positive_only", c_int32)]
+    _fields_ = [("gain", c_float), ("niter", c_void_p), ("threshold", c_void_p), ("positive_only", c_int32),
+                ("team_size", c_int32)]
 
 
 class MiError(RuntimeError):

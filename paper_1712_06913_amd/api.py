@@ -134,7 +134,7 @@ def ifft2(data: torch.Tensor, n, offs, device: int = 0):
 
 
 def hogbom_clean(batch: Batch, dirty, beam, niter, gain: float = 0.1, threshold=None, positive_only=False,
-                 restore: bool = True, want_model: bool = True, want_components: bool = True):
+                 restore: bool = True, want_model: bool = True, want_components: bool = True, team_size: int = 0):
     """mi_hogbom_clean; returns a dict of device tensors."""
     dev = batch.device
     niter = np.ascontiguousarray(niter, dtype=np.int32)
@@ -153,7 +153,7 @@ def hogbom_clean(batch: Batch, dirty, beam, niter, gain: float = 0.1, threshold=
     res["cbeam"] = torch.zeros(6 * batch.n_inst, dtype=torch.float64, device=dev) if restore else None
     res["comp_off"] = np.concatenate([[0], np.cumsum(niter.astype(np.int64))])
     prm = nat.MiCleanParams(float(gain), niter.ctypes.data, None if thr is None else thr.ctypes.data,
-                            1 if positive_only else 0)
+                            1 if positive_only else 0, int(team_size))
     nat.check(batch.ctx, nat.lib().mi_hogbom_clean(
         batch.ctx, batch.c, _ptr(dirty), _ptr(beam), ctypes.byref(prm), _ptr(res["residual"]), _ptr(res["model"]),
         _ptr(res["comp_idx"]), _ptr(res["comp_flux"]), _ptr(res["n_comp"]), _ptr(res["restored"]),

@@ -28,11 +28,43 @@ namespace mi {
 constexpr int CL_THREADS = 1024;
 constexpr int CL_WAVES = CL_THREADS / 64;
 constexpr int RESTORE_RMAX = 64;
+// Word 3 of a raw buffer resource descriptor on gfx9-family GPUs (untyped dword access).
+constexpr int BUFFER_RSRC_WORD3 = 0x00020000;
 constexpr int FIT_HALF = 63;                 // fit box half-width (pixels)
 constexpr int FIT_BOX = 2 * FIT_HALF + 1;
 
 
 namespace {
+
+// ---- team communication.  Slots hold 64-bit keys
+//   (peak bits << 32) | ((2^24 - 1 - index) << 8) | (seq << 1) | sign
+// where seq is a 7-bit barrier sequence number.  All shared words (slots, component list)
+// are accessed with agent-scope relaxed atomics, which are coherent per location across
+// CUs and XCDs; ordering between them is made explicit with s_waitcnt vmcnt(0).  No
+// release/acquire fences are used: on this GPU those write back and invalidate the whole
+// L2, which would also evict the beam window every iteration.  The LOCAL variant only
+// changes team placement (all members of a team on one XCD, sharing its L2).
+__device__ __forceinline__ void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+template <bool LOCAL>
+__device__ __forceinline__ unsigned long long ld_shared_u64(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool LOCAL>
+__device__ __forceinline__ unsigned ld_shared_u32(const unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool LOCAL>
+__device__ __forceinline__ void st_shared_u64(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool LOCAL>
+__device__ __forceinline__ void st_shared_u32(unsigned* p, unsigned v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ unsigned long long make_key(float r, int idx, int posonly) {
   const unsigned b = __float_as_uint(r);
@@ -65,86 +97,95 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
   return v;
 }
 
-// Workgroup max of a key; result returned to every thread.
-__device__ unsigned long long block_max_key(unsigned long long k, unsigned long long* red) {
-  k = wave_max_u64(k);
+__device__ __forceinline__ float wave_max_f(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Workgroup maxima (all threads get the result).
+__device__ float block_max_f(float v, float* red) {
+  v = wave_max_f(v);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) red[wave] = k;
+  if (lane == 0) red[wave] = v;
   __syncthreads();
-  if (wave == 0) {
-    unsigned long long v = lane < CL_WAVES ? red[lane] : 0ull;
-    v = wave_max_u64(v);
-    if (lane == 0) red[CL_WAVES] = v;
-  }
-  __syncthreads();
-  const unsigned long long r = red[CL_WAVES];
+  float r = red[0];
+#pragma unroll
+  for (int w = 1; w < CL_WAVES; ++w) r = fmaxf(r, red[w]);
   __syncthreads();
   return r;
 }
 
-// Local argmax over the chunk (initial search, no subtraction).
-__device__ unsigned long long chunk_argmax(const float* R, int chunk, int c0, int posonly) {
-  float bv = 0.f;
-  int bi = -1;
-  float ba = -1.f;
-  for (int q = threadIdx.x; q < chunk; q += CL_THREADS) {
-    const float r = R[q];
-    const float a = posonly ? r : fabsf(r);
-    if (bi < 0 || a > ba) { ba = a; bv = r; bi = c0 + q; }
-  }
-  return bi < 0 ? 0ull : make_key(bv, bi, posonly);
-}
-
-// Fused beam subtraction and local argmax.
-__device__ unsigned long long chunk_subtract_argmax(float* R, int chunk, int c0, int log2N, int N,
-                                                    const float* __restrict__ bm, float f, int py, int px,
-                                                    int posonly) {
-  const int twoN = 2 * N;
-  float bv = 0.f;
-  int bi = -1;
-  float ba = -1.f;
-  const float* bwin = bm + (int64_t)(N - py) * twoN + (N - px);   // beam[y - py + N][x - px + N]
-  for (int q = threadIdx.x; q < chunk; q += CL_THREADS) {
-    const int g = c0 + q;
-    const int y = g >> log2N, x = g & (N - 1);
-    const float r = R[q] - f * bwin[(int64_t)y * twoN + x];
-    R[q] = r;
-    const float a = posonly ? r : fabsf(r);
-    if (bi < 0 || a > ba) { ba = a; bv = r; bi = g; }
-  }
-  return bi < 0 ? 0ull : make_key(bv, bi, posonly);
-}
-
-// Team barrier: every member arrives once per call; `target` = G * (calls so far + 1).
-// The wait is bounded: after BARRIER_SPIN_LIMIT polls (seconds) the workgroup gives up and
-// returns false, so a broken launch ends instead of spinning forever.
-constexpr unsigned BARRIER_SPIN_LIMIT = 1u << 24;
-
-__device__ __forceinline__ bool team_barrier(unsigned* bar, unsigned target, int* flag) {
+__device__ unsigned long long block_max_u64(unsigned long long k, unsigned long long* red) {
+  k = wave_max_u64(k);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = k;
   __syncthreads();
+  unsigned long long r = red[0];
+#pragma unroll
+  for (int w = 1; w < CL_WAVES; ++w) r = red[w] > r ? red[w] : r;
+  __syncthreads();
+  return r;
+}
+
+// Publish this workgroup's key for barrier `seq` and return the maximum over the team's G
+// keys once all of them carry `seq`.  Returns false if the wait timed out.
+constexpr unsigned POLL_LIMIT = 1u << 22;
+
+template <bool LOCAL>
+__device__ bool team_exchange(unsigned long long* slots, int G, int member, unsigned seq, unsigned long long key,
+                              unsigned long long* red, unsigned long long& best) {
+  const unsigned s7 = seq & 127u;
+  const unsigned long long* sl = slots + (seq & 1u) * G;
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned spins = 0;
-    int ok = 1;
-    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > BARRIER_SPIN_LIMIT) { ok = 0; break; }
+    wait_vm();                                     // earlier stores (component list) first
+    st_shared_u64<LOCAL>(const_cast<unsigned long long*>(sl) + member, (key & ~0xFEull) | (s7 << 1));
+  }
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    unsigned long long k = 0ull;
+    for (int m0 = 0; m0 < G; m0 += 64) {
+      const int m = m0 + lane;
+      bool done = m >= G;
+      unsigned spins = 0;
+      unsigned long long v = 0ull;
+      while (true) {
+        if (!done) {
+          v = ld_shared_u64<LOCAL>(sl + m);
+          done = ((unsigned)(v >> 1) & 127u) == s7;
+        }
+        if (__all(done)) break;
+        if (++spins > POLL_LIMIT) {
+          if (lane == 0) red[CL_WAVES] = ~0ull;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      if (done && m < G) k = v > k ? v : k;
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    *flag = ok;
+    k = wave_max_u64(k);
+    if (lane == 0 && red[CL_WAVES] != ~0ull) red[CL_WAVES] = k;
   }
   __syncthreads();
-  return *flag != 0;
+  best = red[CL_WAVES];
+  __syncthreads();
+  if (threadIdx.x == 0) red[CL_WAVES] = 0ull;
+  return best != ~0ull;
 }
 
 }  // namespace
 
+// Residual in registers: thread t of member m owns pixels c0 + k 1024 + t, k < PPT
+// (c0 = m N^2/G).  For N <= 1024 and G <= N, c0 is a row start and 1024 is a multiple of
+// N, so pixel k of a thread sits 2048 k floats further into the beam window than pixel 0:
+// the load address is a uniform (SGPR) base plus one per-thread constant.
+template <int PPT, bool LOCAL>
 __global__ void __launch_bounds__(CL_THREADS)
 k_clean(CleanArgs A) {
-  extern __shared__ float R[];
-  __shared__ unsigned long long red[CL_WAVES + 1];
-  __shared__ int bar_ok;
+  extern __shared__ float Rl[];                       // restore staging (when requested)
+  __shared__ float red_f[CL_WAVES];
+  __shared__ unsigned long long red_k[CL_WAVES + 1];
   const int G = A.G;
+  const int tid = threadIdx.x;
   int team, member;
   if (A.xcd_map) {
     const int x = blockIdx.x & 7, r = blockIdx.x >> 3;
@@ -154,106 +195,163 @@ k_clean(CleanArgs A) {
     team = blockIdx.x / G;
     member = blockIdx.x % G;
   }
-  unsigned* bar = A.bar + team;
   unsigned long long* slots = A.slots + (size_t)team * 2 * G;
-  unsigned nbar = 0;
-  const int tid = threadIdx.x;
+  if (tid == 0) red_k[CL_WAVES] = 0ull;
+  if (LOCAL && tid == 0 && A.status && A.team_off[team] < A.team_off[team + 1]) {
+    // the XCD-local protocol assumes block b runs on XCD b % 8
+    unsigned xcc;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+    if ((int)(xcc & 7u) != (int)(blockIdx.x & 7)) atomicOr(&A.status[A.team_imgs[A.team_off[team]]], 32);
+  }
+  __syncthreads();
+  unsigned seq = 0;
+  const float NaN = __uint_as_float(0x7fc00000u);
+  const int posonly = A.posonly;
 
   for (int ti = A.team_off[team]; ti < A.team_off[team + 1]; ++ti) {
-    const int img = A.team_imgs[ti];
+    const int img = __builtin_amdgcn_readfirstlane(A.team_imgs[ti]);
     const InstDesc d = A.inst[img];
-    const int N = d.N, log2N = d.log2N;
+    const int N = d.N, log2N = d.log2N, twoN = 2 * N;
     const int chunk = (N * N) / G;
     const int c0 = member * chunk;
-    const float* dirty = A.dirty + d.img_off + c0;
-    for (int q = tid; q < chunk; q += CL_THREADS) R[q] = dirty[q];
-    if (A.model) {
-      double* m = A.model + d.img_off + c0;
-      for (int q = tid; q < chunk; q += CL_THREADS) m[q] = 0.0;
+    const int kmax = (chunk + 1023) >> 10;            // uniform
+    const bool tvalid = tid < chunk;                  // false only when chunk < 1024
+    const int vt = tvalid ? ((tid >> log2N) * twoN + (tid & (N - 1))) : 0;
+    const unsigned vtb = (unsigned)vt * 4u;          // byte offset, zero-extended
+    const int row0 = c0 >> log2N;
+    float R[PPT];
+    {
+      const float* dsrc = A.dirty + d.img_off + c0 + tid;
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) R[k] = (k < kmax && tvalid) ? dsrc[k << 10] : NaN;
     }
-    __syncthreads();
+    if (A.model) {
+      double* m = A.model + d.img_off + c0 + tid;
+#pragma unroll
+      for (int k = 0; k < PPT; ++k)
+        if (k < kmax && tvalid) m[k << 10] = 0.0;
+    }
     const int niter = A.niter[img];
     const float thr = A.thr ? A.thr[img] : 0.0f;
-    const float* bm = A.beam + d.beam_off;
-    unsigned long long key = block_max_key(chunk_argmax(R, chunk, c0, A.posonly), red);
+    const int64_t coff = A.comp_off[img];
+    const float* bimg = A.beam + d.beam_off;
+    float f = 0.0f;                                   // pending pick (none yet)
+    int py = N / 2, px = N / 2;
     int it = 0;
-    for (; it < niter; ++it) {
-      const int par = nbar & 1;
-      if (tid == 0)
-        __hip_atomic_store(&slots[par * G + member], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      ++nbar;
-      if (!team_barrier(bar, nbar * (unsigned)G, &bar_ok)) {
-        if (tid == 0 && A.status) atomicOr(&A.status[img], 16);
-        return;
-      }
-      unsigned long long k = 0ull;
-      for (int m = tid; m < G; m += 64)
-        if (tid < 64) {
-          unsigned long long t = __hip_atomic_load(&slots[par * G + m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          k = t > k ? t : k;
+    bool aborted = false;
+    for (;; ++it) {
+      // apply the pending pick and find the local peak; no per-pixel branches: pixels a
+      // thread does not own hold NaN (fma keeps NaN, fmaxf ignores it) and read a safe
+      // in-window address chosen by a uniform select
+      // raw buffer loads: SGPR resource at the window origin, fixed per-thread VGPR
+      // offset, per-k SGPR offset (8 KB per k); records end at the image's beam end
+      const int64_t win0 = (int64_t)(N - py + row0) * twoN + (N - px);
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float*>(bimg + win0), 0, (int)((4LL * N * N - win0) * 4), BUFFER_RSRC_WORD3);
+      float best = posonly ? -INFINITY : -1.0f;
+      float bv[PPT];
+#pragma unroll
+      for (int k = 0; k < PPT; ++k)
+        bv[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)vtb, k < kmax ? 8192 * k : 0, 0));
+      if (posonly) {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+          R[k] = fmaf(-f, bv[k], R[k]);
+          best = fmaxf(best, R[k]);
         }
-      if (tid < 64) {
-        k = wave_max_u64(k);
-        if (tid == 0) red[CL_WAVES] = k;
+      } else {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+          R[k] = fmaf(-f, bv[k], R[k]);
+          best = fmaxf(best, fabsf(R[k]));
+        }
       }
-      __syncthreads();
-      const unsigned long long best = red[CL_WAVES];
-      __syncthreads();
+      if (it == niter) break;
+      const float wmax = block_max_f(best, red_f);
+      unsigned long long key = 0ull;
+      if (best == wmax) {
+        int kf = -1;
+#pragma unroll
+        for (int k = PPT - 1; k >= 0; --k)             // lowest k wins: scan downwards
+          if ((posonly ? R[k] : fabsf(R[k])) == wmax) kf = k;
+        float rv = 0.0f;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+          if (k == kf) rv = R[k];
+        key = make_key(rv, c0 + (kf << 10) + tid, posonly);
+      }
+      key = block_max_u64(key, red_k);
+      unsigned long long tkey;
+      ++seq;
+      if (!team_exchange<LOCAL>(slots, G, member, seq, key, red_k, tkey)) { aborted = true; break; }
       int p;
       float val;
-      decode_key(best, A.posonly, p, val);
+      decode_key(tkey, posonly, p, val);
+      p = __builtin_amdgcn_readfirstlane(p);
+      val = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, val)));
       if (!(fabsf(val) > thr)) break;
-      const double f = (double)A.gain * (double)val;
+      const double fd = (double)A.gain * (double)val;
       if (tid == 0) {
-        if (A.model && p >= c0 && p < c0 + chunk) A.model[d.img_off + p] += f;
+        if (A.model && p >= c0 && p < c0 + chunk) A.model[d.img_off + p] += fd;
         if (member == 0 && A.comp_idx) {
-          A.comp_idx[A.comp_off[img] + it] = p;
-          A.comp_flux[A.comp_off[img] + it] = f;
+          st_shared_u32<LOCAL>(reinterpret_cast<unsigned*>(A.comp_idx + coff + it), (unsigned)p);
+          st_shared_u64<LOCAL>(reinterpret_cast<unsigned long long*>(A.comp_flux + coff + it),
+                               (unsigned long long)__double_as_longlong(fd));
         }
       }
-      key = block_max_key(chunk_subtract_argmax(R, chunk, c0, log2N, N, bm, (float)f, p >> log2N, p & (N - 1),
-                                                A.posonly), red);
+      f = (float)fd;
+      py = p >> log2N;
+      px = p & (N - 1);
+    }
+    if (aborted) {
+      if (tid == 0 && A.status) atomicOr(&A.status[img], 16);
+      return;
     }
     if (member == 0 && tid == 0 && A.ncomp) A.ncomp[img] = it;
-    __syncthreads();
-    float* ro = A.resid + d.img_off + c0;
-    for (int q = tid; q < chunk; q += CL_THREADS) ro[q] = R[q];
-
+    {
+      float* ro = A.resid + d.img_off + c0 + tid;
+#pragma unroll
+      for (int k = 0; k < PPT; ++k)
+        if (k < kmax && tvalid) ro[k << 10] = R[k];
+    }
     if (A.restored && A.cbeam) {
-      // all components must be visible to every member
-      ++nbar;
-      if (!team_barrier(bar, nbar * (unsigned)G, &bar_ok)) {
+      // every member needs the whole component list
+      unsigned long long dummy;
+      ++seq;
+      if (!team_exchange<LOCAL>(slots, G, member, seq, 0ull, red_k, dummy)) {
         if (tid == 0 && A.status) atomicOr(&A.status[img], 16);
         return;
       }
+#pragma unroll
+      for (int k = 0; k < PPT; ++k)
+        if (k < kmax && tvalid) Rl[(k << 10) + tid] = R[k];
+      __syncthreads();
       const float ga = (float)A.cbeam[6 * img + 0], gb = (float)A.cbeam[6 * img + 1],
                   gc = (float)A.cbeam[6 * img + 2];
       const int rr = A.rrad[img];
       const int side = 2 * rr + 1;
-      const int row_lo = c0 >> log2N, row_hi = (c0 + chunk - 1) >> log2N;
+      const int row_hi = (c0 + chunk - 1) >> log2N;
       for (int i = 0; i < it; ++i) {
-        const int p = __hip_atomic_load(&A.comp_idx[A.comp_off[img] + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int py = p >> log2N, px = p & (N - 1);
-        if (py + rr < row_lo || py - rr > row_hi) continue;
-        const unsigned long long fb = __hip_atomic_load(
-            reinterpret_cast<unsigned long long*>(&A.comp_flux[A.comp_off[img] + i]), __ATOMIC_RELAXED,
-            __HIP_MEMORY_SCOPE_AGENT);
-        const float f = (float)__longlong_as_double((long long)fb);
+        const int p = (int)ld_shared_u32<LOCAL>(reinterpret_cast<const unsigned*>(A.comp_idx + coff + i));
+        const int cy = p >> log2N, cx = p & (N - 1);
+        if (cy + rr < row0 || cy - rr > row_hi) continue;
+        const float fc = (float)__longlong_as_double(
+            (long long)ld_shared_u64<LOCAL>(reinterpret_cast<const unsigned long long*>(A.comp_flux + coff + i)));
         for (int w = tid; w < side * side; w += CL_THREADS) {
           const int dy = w / side - rr, dx = w % side - rr;
-          const int y = py + dy, x = px + dx;
+          const int y = cy + dy, x = cx + dx;
           if (y < 0 || y >= N || x < 0 || x >= N) continue;
           const int g = (y << log2N) + x;
           if (g < c0 || g >= c0 + chunk) continue;
           const float e = (float)dx * (ga * (float)dx + gb * (float)dy) + gc * (float)dy * (float)dy;
-          atomicAdd(&R[g - c0], f * expf(-e));
+          atomicAdd(&Rl[g - c0], fc * expf(-e));
         }
       }
       __syncthreads();
       float* rs = A.restored + d.img_off + c0;
-      for (int q = tid; q < chunk; q += CL_THREADS) rs[q] = R[q];
+      for (int q = tid; q < chunk; q += CL_THREADS) rs[q] = Rl[q];
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -430,16 +528,32 @@ __global__ void k_degrid(const InstDesc* __restrict__ inst, const float2* __rest
 }
 
 // ---- host launchers ----
-hipError_t clean_max_blocks_per_cu(size_t lds_bytes, int* nb) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, reinterpret_cast<const void*>(k_clean), CL_THREADS,
-                                                      lds_bytes);
+#define MI_CLEAN_KERNEL(PPT, LOCAL) reinterpret_cast<const void*>(&k_clean<PPT, LOCAL>)
+
+static const void* clean_kernel(int ppt, bool local) {
+  switch (ppt) {
+    case 1: return local ? MI_CLEAN_KERNEL(1, true) : MI_CLEAN_KERNEL(1, false);
+    case 2: return local ? MI_CLEAN_KERNEL(2, true) : MI_CLEAN_KERNEL(2, false);
+    case 4: return local ? MI_CLEAN_KERNEL(4, true) : MI_CLEAN_KERNEL(4, false);
+    case 8: return local ? MI_CLEAN_KERNEL(8, true) : MI_CLEAN_KERNEL(8, false);
+    case 16: return local ? MI_CLEAN_KERNEL(16, true) : MI_CLEAN_KERNEL(16, false);
+    case 32: return local ? MI_CLEAN_KERNEL(32, true) : MI_CLEAN_KERNEL(32, false);
+    default: return nullptr;
+  }
 }
 
-hipError_t launch_clean(const CleanArgs& A, int n_blocks, size_t lds_bytes, hipStream_t st) {
+hipError_t clean_max_blocks_per_cu(int ppt, bool local, size_t lds, int* nb) {
+  const void* k = clean_kernel(ppt, local);
+  if (!k) return hipErrorInvalidValue;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k, CL_THREADS, lds);
+}
+
+hipError_t launch_clean(const CleanArgs& A, int ppt, bool local, int n_blocks, size_t lds, hipStream_t st) {
+  const void* k = clean_kernel(ppt, local);
+  if (!k) return hipErrorInvalidValue;
   CleanArgs a = A;
   void* args[] = {&a};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_clean), dim3(n_blocks), dim3(CL_THREADS), args,
-                                    lds_bytes, st);
+  return hipLaunchCooperativeKernel(k, dim3(n_blocks), dim3(CL_THREADS), args, lds, st);
 }
 
 hipError_t launch_beamfit(const InstDesc* inst, int n_inst, const float* beam, double* cbeam, int* rrad,

@@ -47,8 +47,8 @@ hipError_t launch_fft_c2c_t_f2d(int, const int*, const int64_t*, const FftWork*,
                                 const Tables&, double, int, int, hipStream_t);
 hipError_t launch_fft_c2c_t_d2f(int, const int*, const int64_t*, const FftWork*, int, const double2*, float2*,
                                 const Tables&, double, int, int, hipStream_t);
-hipError_t clean_max_blocks_per_cu(size_t, int*);
-hipError_t launch_clean(const CleanArgs&, int, size_t, hipStream_t);
+hipError_t clean_max_blocks_per_cu(int ppt, bool local, size_t lds, int* nb);
+hipError_t launch_clean(const CleanArgs&, int ppt, bool local, int n_blocks, size_t lds, hipStream_t);
 hipError_t launch_beamfit(const InstDesc*, int, const float*, double*, int*, int*, hipStream_t);
 hipError_t launch_degrid(const InstDesc*, int, int, const float2*, const float*, const float*, const double*,
                          const double2*, const Tables&, int, float2*, hipStream_t);
@@ -116,8 +116,8 @@ struct CleanPlan {
   std::vector<int32_t> niter;
   std::vector<float> thr;
   bool has_thr = false;
-  int G = 0, T = 0, xcd_map = 0, n_blocks = 0;
-  size_t lds = 0;
+  int G = 0, T = 0, xcd_map = 0, n_blocks = 0, ppt = 0, team_req = 0;
+  size_t lds = 0;        // restore staging: the largest chunk in floats
   int64_t total_comp = 0;
   DevBuf team_off, team_imgs, niter_d, thr_d, comp_off, slots, bar, comp_idx, comp_flux, cbeam, rrad;
 };
@@ -578,16 +578,25 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
     const int n = P->n_inst;
     for (int i = 0; i < n; ++i)
       if (prm->niter[i] < 0) fail(MI_ERR_ARG, "niter[%d] < 0", i);
-    int G_min = 1;
-    for (int N : P->n) G_min = std::max(G_min, (N * N) / 32768);
-    if (G_min > 256) fail(MI_ERR_UNSUPPORTED, "CLEAN of N = %d does not fit on-chip (max N = 2048)", P->max_N);
+    int G_min = 1, N_min = 1 << 30;
+    for (int N : P->n) {
+      G_min = std::max(G_min, (N * N) / 32768);     // at most 32 residual pixels per thread
+      N_min = std::min(N_min, N);
+    }
+    const int G_cap = std::min(256, N_min);         // a member's chunk must start on a row
+    if (P->max_N > 1024) fail(MI_ERR_UNSUPPORTED, "CLEAN supports N <= 1024 (got %d)", P->max_N);
+    if (G_min > G_cap) fail(MI_ERR_UNSUPPORTED, "CLEAN team too large for N = %d", N_min);
+    const int req = prm->team_size;
+    if (req != 0 && (!is_pow2(req) || req > 256)) fail(MI_ERR_ARG, "team_size must be 0 or a power of two <= 256");
     // clean plan: team shape, LPT assignment, device copies of niter / thresholds
     uint64_t h = fnv1a(prm->niter, sizeof(int32_t) * n);
+    h = fnv1a(&req, sizeof req, h);
     const bool has_thr = prm->threshold != nullptr;
     if (has_thr) h = fnv1a(prm->threshold, sizeof(float) * n, h ^ 0x9e3779b97f4a7c15ull);
     CleanPlan* C = nullptr;
     auto it = P->cleans.find(h);
-    if (it != P->cleans.end() && std::equal(it->second->niter.begin(), it->second->niter.end(), prm->niter) &&
+    if (it != P->cleans.end() && it->second->team_req == req &&
+        std::equal(it->second->niter.begin(), it->second->niter.end(), prm->niter) &&
         it->second->has_thr == has_thr &&
         (!has_thr || std::equal(it->second->thr.begin(), it->second->thr.end(), prm->threshold))) {
       C = it->second.get();
@@ -595,28 +604,41 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
       if (P->cleans.size() >= 8) P->cleans.erase(P->cleans.begin());
       auto up = std::make_unique<CleanPlan>();
       C = up.get();
+      C->team_req = req;
       C->niter.assign(prm->niter, prm->niter + n);
       C->has_thr = has_thr;
       if (has_thr) C->thr.assign(prm->threshold, prm->threshold + n);
-      // team size: enough workgroups for the largest residual to fit in LDS, then grown
-      // while the chip has idle CUs
+      // Team size: enough workgroups that the largest residual fits in registers (32 pixels
+      // per thread); with many images, small teams on one XCD each (the barrier then stays
+      // in that XCD's L2); a single image gets up to 32 workgroups of one XCD.
+      int G;
+      if (req) {
+        G = std::min(std::max(req, G_min), G_cap);
+      } else {
+        G = G_min;
+        while (G * 2 <= std::min(32, G_cap) && (int64_t)G * 2 * n <= 256) G *= 2;
+      }
+      const bool local = G <= 32;
+      int ppt = 1;
+      while (ppt * 1024 * G < P->max_N * P->max_N) ppt *= 2;
       int per_cu = 0;
-      int G = G_min;
-      size_t lds = (size_t)(P->max_N * P->max_N / G) * sizeof(float);
-      HIPCHK(clean_max_blocks_per_cu(lds, &per_cu));
-      if (per_cu < 1) fail(MI_ERR_UNSUPPORTED, "CLEAN kernel cannot be resident (LDS %zu bytes)", lds);
+      const size_t lds = (size_t)(P->max_N * P->max_N / G) * sizeof(float);
+      HIPCHK(clean_max_blocks_per_cu(ppt, local, lds, &per_cu));
+      if (per_cu < 1) fail(MI_ERR_UNSUPPORTED, "CLEAN kernel cannot be resident");
       const int cap = per_cu * ctx->n_cu;
-      while (G * 2 <= 256 && (int64_t)G * 2 * n <= cap && G * 2 <= (P->max_N * P->max_N) / 1024) G *= 2;
-      lds = (size_t)(P->max_N * P->max_N / G) * sizeof(float);
-      HIPCHK(clean_max_blocks_per_cu(lds, &per_cu));
-      const int cap2 = per_cu * ctx->n_cu;
-      int T = std::min(n, cap2 / G);
-      if (T < 1) fail(MI_ERR_UNSUPPORTED, "CLEAN team of %d workgroups exceeds the device", G);
-      int xcd = 0;
-      if (T >= 8 && G <= 32) { T -= T % 8; xcd = 1; }
+      if (G > cap) fail(MI_ERR_UNSUPPORTED, "CLEAN team of %d workgroups exceeds the device", G);
+      int T_work = std::min(n, cap / G);
+      int T = T_work;
+      if (local) {
+        const int Tmax = cap / G;                     // a multiple of 8 when G <= 32
+        T = std::min(Tmax, ((T_work + 7) / 8) * 8);
+        if (T % 8) { T -= T % 8; T_work = std::min(T_work, T); }
+        if (T < 8) fail(MI_ERR_UNSUPPORTED, "device too small for XCD-local CLEAN teams");
+      }
       C->G = G;
       C->T = T;
-      C->xcd_map = xcd;
+      C->ppt = ppt;
+      C->xcd_map = local ? 1 : 0;
       C->n_blocks = T * G;
       C->lds = lds;
       // LPT: images sorted by N^2 * niter, each to the least-loaded team
@@ -625,7 +647,7 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
       std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         return (double)P->n[a] * P->n[a] * (C->niter[a] + 1) > (double)P->n[b] * P->n[b] * (C->niter[b] + 1);
       });
-      std::vector<double> load(T, 0.0);
+      std::vector<double> load(T_work, 0.0);
       std::vector<std::vector<int>> lists(T);
       for (int i : order) {
         int t = (int)(std::min_element(load.begin(), load.end()) - load.begin());
@@ -665,7 +687,7 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
       cidx = dev_alloc<int>(C->comp_idx, (size_t)std::max<int64_t>(C->total_comp, 1));
       cflx = dev_alloc<double>(C->comp_flux, (size_t)std::max<int64_t>(C->total_comp, 1));
     }
-    HIPCHK(launch_fill_u32(static_cast<unsigned*>(C->bar.p), C->T, 0u, stream));
+    HIPCHK(launch_fill_u32(static_cast<unsigned*>(C->slots.p), (int64_t)C->T * 2 * C->G * 2, 0u, stream));
     CleanArgs A{};
     A.inst = static_cast<const InstDesc*>(P->inst.p);
     A.team_off = static_cast<const int*>(C->team_off.p);
@@ -690,7 +712,7 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
     A.slots = static_cast<unsigned long long*>(C->slots.p);
     A.bar = static_cast<unsigned*>(C->bar.p);
     A.status = status;
-    HIPCHK(launch_clean(A, C->n_blocks, C->lds, stream));
+    HIPCHK(launch_clean(A, C->ppt, C->xcd_map != 0, C->n_blocks, C->lds, stream));
   });
 }
 
