@@ -112,7 +112,8 @@ def grid(prep: Prep, vis, w, beam: bool = False, table=None) -> np.ndarray:
     c, o = (prep.c2, prep.o2) if beam else (prep.c, prep.o)
     k = prep.keep
     c, o, wk = c[k], o[k], w[k]
-    val = np.ones(len(wk), np.complex128) if beam else np.asarray(vis, np.complex64)[k].astype(np.complex128)
+    # FP32 inputs are promoted exactly; FP64 inputs (finite-difference checks) keep their precision
+    val = np.ones(len(wk), np.complex128) if beam else np.asarray(vis).astype(np.complex128)[k]
     half = (W - 1) // 2
     G = np.zeros((P, P), np.complex128)
     d = np.arange(-half, half + 1)

@@ -46,24 +46,28 @@ namespace {
 // changes team placement (all members of a team on one XCD, sharing its L2).
 __device__ __forceinline__ void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// Shared words use agent scope (sc1) in both placements: workgroup-scope (sc0) accesses are
+// not coherent between CUs of one XCD on this GPU outside threadgroup-split mode.
+#define MI_TEAM_SCOPE __HIP_MEMORY_SCOPE_AGENT
+
 template <bool LOCAL>
 __device__ __forceinline__ unsigned long long ld_shared_u64(const unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, MI_TEAM_SCOPE);
 }
 
 template <bool LOCAL>
 __device__ __forceinline__ unsigned ld_shared_u32(const unsigned* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, MI_TEAM_SCOPE);
 }
 
 template <bool LOCAL>
 __device__ __forceinline__ void st_shared_u64(unsigned long long* p, unsigned long long v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, MI_TEAM_SCOPE);
 }
 
 template <bool LOCAL>
 __device__ __forceinline__ void st_shared_u32(unsigned* p, unsigned v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, MI_TEAM_SCOPE);
 }
 
 __device__ __forceinline__ unsigned long long make_key(float r, int idx, int posonly) {
@@ -102,90 +106,61 @@ __device__ __forceinline__ float wave_max_f(float v) {
   return v;
 }
 
-// Workgroup maxima (all threads get the result).
-__device__ float block_max_f(float v, float* red) {
-  v = wave_max_f(v);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  float r = red[0];
-#pragma unroll
-  for (int w = 1; w < CL_WAVES; ++w) r = fmaxf(r, red[w]);
-  __syncthreads();
-  return r;
-}
-
-__device__ unsigned long long block_max_u64(unsigned long long k, unsigned long long* red) {
-  k = wave_max_u64(k);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) red[wave] = k;
-  __syncthreads();
-  unsigned long long r = red[0];
-#pragma unroll
-  for (int w = 1; w < CL_WAVES; ++w) r = red[w] > r ? red[w] : r;
-  __syncthreads();
-  return r;
-}
-
-// Publish this workgroup's key for barrier `seq` and return the maximum over the team's G
-// keys once all of them carry `seq`.  Returns false if the wait timed out.
+// Team exchange, run by wave 0 only: reduce the 16 wave keys in red[0..15] to this
+// workgroup's key, publish it for barrier `seq`, then poll the team's G slots until all
+// carry `seq` and leave their maximum in red[16 + (seq & 1)] (~0 if the wait timed out).
+// `ordered`: wait for this wave's earlier stores (component list) before publishing.
 constexpr unsigned POLL_LIMIT = 1u << 22;
 
 template <bool LOCAL>
-__device__ bool team_exchange(unsigned long long* slots, int G, int member, unsigned seq, unsigned long long key,
-                              unsigned long long* red, unsigned long long& best) {
+__device__ __forceinline__ void team_exchange_wave0(unsigned long long* slots, int G, int member, unsigned seq,
+                                                    unsigned long long* red, bool ordered) {
+  const int lane = threadIdx.x;                       // wave 0
+  unsigned long long wk = lane < CL_WAVES ? red[lane] : 0ull;
+  wk = wave_max_u64(wk);
   const unsigned s7 = seq & 127u;
-  const unsigned long long* sl = slots + (seq & 1u) * G;
-  if (threadIdx.x == 0) {
-    wait_vm();                                     // earlier stores (component list) first
-    st_shared_u64<LOCAL>(const_cast<unsigned long long*>(sl) + member, (key & ~0xFEull) | (s7 << 1));
+  unsigned long long* sl = slots + (seq & 1u) * G;
+  if (lane == 0) {
+    if (ordered) wait_vm();
+    st_shared_u64<LOCAL>(sl + member, (wk & ~0xFEull) | ((unsigned long long)s7 << 1));
   }
-  if (threadIdx.x < 64) {
-    const int lane = threadIdx.x;
-    unsigned long long k = 0ull;
-    for (int m0 = 0; m0 < G; m0 += 64) {
-      const int m = m0 + lane;
-      bool done = m >= G;
-      unsigned spins = 0;
-      unsigned long long v = 0ull;
-      while (true) {
-        if (!done) {
-          v = ld_shared_u64<LOCAL>(sl + m);
-          done = ((unsigned)(v >> 1) & 127u) == s7;
-        }
-        if (__all(done)) break;
-        if (++spins > POLL_LIMIT) {
-          if (lane == 0) red[CL_WAVES] = ~0ull;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
+  unsigned long long k = 0ull;
+  bool timed_out = false;
+  for (int m0 = 0; m0 < G; m0 += 64) {
+    const int m = m0 + lane;
+    bool done = m >= G;
+    unsigned spins = 0;
+    unsigned long long v = 0ull;
+    while (true) {
+      if (!done) {
+        v = ld_shared_u64<LOCAL>(sl + m);
+        done = ((unsigned)(v >> 1) & 127u) == s7;
       }
-      if (done && m < G) k = v > k ? v : k;
+      if (__all(done)) break;
+      if (++spins > POLL_LIMIT) { timed_out = true; break; }
     }
-    k = wave_max_u64(k);
-    if (lane == 0 && red[CL_WAVES] != ~0ull) red[CL_WAVES] = k;
+    if (m < G && done) k = v > k ? v : k;
   }
-  __syncthreads();
-  best = red[CL_WAVES];
-  __syncthreads();
-  if (threadIdx.x == 0) red[CL_WAVES] = 0ull;
-  return best != ~0ull;
+  k = wave_max_u64(k);
+  if (lane == 0) red[CL_WAVES + (seq & 1u)] = timed_out ? ~0ull : k;
 }
 
 }  // namespace
 
-// Residual in registers: thread t of member m owns pixels c0 + k 1024 + t, k < PPT
-// (c0 = m N^2/G).  For N <= 1024 and G <= N, c0 is a row start and 1024 is a multiple of
-// N, so pixel k of a thread sits 2048 k floats further into the beam window than pixel 0:
-// the load address is a uniform (SGPR) base plus one per-thread constant.
+// Residual in registers: thread t of member m owns 4-pixel groups at c0 + 4 (t + 1024 s) + j,
+// s < PPT/4, j < 4 (c0 = m N^2/G).  For N <= 1024 and G <= N, c0 is a row start and a
+// step of 4096 pixels is 4096/N whole rows, i.e. 8192 floats further into the beam window:
+// each group is one 16-byte buffer load at a uniform (SGPR) offset from a fixed per-thread
+// offset.
 template <int PPT, bool LOCAL>
 __global__ void __launch_bounds__(CL_THREADS)
 k_clean(CleanArgs A) {
+  static_assert(PPT % 4 == 0, "4 pixels per load");
+  constexpr int NS = PPT / 4;
   extern __shared__ float Rl[];                       // restore staging (when requested)
-  __shared__ float red_f[CL_WAVES];
-  __shared__ unsigned long long red_k[CL_WAVES + 1];
+  __shared__ unsigned long long red_k[CL_WAVES + 2];
   const int G = A.G;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int team, member;
   if (A.xcd_map) {
     const int x = blockIdx.x & 7, r = blockIdx.x >> 3;
@@ -196,14 +171,12 @@ k_clean(CleanArgs A) {
     member = blockIdx.x % G;
   }
   unsigned long long* slots = A.slots + (size_t)team * 2 * G;
-  if (tid == 0) red_k[CL_WAVES] = 0ull;
   if (LOCAL && tid == 0 && A.status && A.team_off[team] < A.team_off[team + 1]) {
-    // the XCD-local protocol assumes block b runs on XCD b % 8
+    // the XCD-local placement assumes block b runs on XCD b % 8
     unsigned xcc;
     asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
     if ((int)(xcc & 7u) != (int)(blockIdx.x & 7)) atomicOr(&A.status[A.team_imgs[A.team_off[team]]], 32);
   }
-  __syncthreads();
   unsigned seq = 0;
   const float NaN = __uint_as_float(0x7fc00000u);
   const int posonly = A.posonly;
@@ -214,23 +187,29 @@ k_clean(CleanArgs A) {
     const int N = d.N, log2N = d.log2N, twoN = 2 * N;
     const int chunk = (N * N) / G;
     const int c0 = member * chunk;
-    const int kmax = (chunk + 1023) >> 10;            // uniform
-    const bool tvalid = tid < chunk;                  // false only when chunk < 1024
-    const int vt = tvalid ? ((tid >> log2N) * twoN + (tid & (N - 1))) : 0;
-    const unsigned vtb = (unsigned)vt * 4u;          // byte offset, zero-extended
+    const int smax = (chunk + 4095) >> 12;            // uniform
+    const bool tvalid = 4 * tid < chunk;              // false only when chunk < 4096
+    const int t4 = 4 * tid;
+    const unsigned vtb = tvalid ? (unsigned)(((t4 >> log2N) * twoN + (t4 & (N - 1))) * 4) : 0u;
     const int row0 = c0 >> log2N;
     float R[PPT];
     {
-      const float* dsrc = A.dirty + d.img_off + c0 + tid;
+      const float* dsrc = A.dirty + d.img_off + c0 + t4;
 #pragma unroll
-      for (int k = 0; k < PPT; ++k) R[k] = (k < kmax && tvalid) ? dsrc[k << 10] : NaN;
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) R[4 * s + j] = (s < smax && tvalid) ? dsrc[(s << 12) + j] : NaN;
     }
     if (A.model) {
-      double* m = A.model + d.img_off + c0 + tid;
+      double* m = A.model + d.img_off + c0 + t4;
 #pragma unroll
-      for (int k = 0; k < PPT; ++k)
-        if (k < kmax && tvalid) m[k << 10] = 0.0;
+      for (int s = 0; s < NS; ++s)
+        if (s < smax && tvalid)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) m[(s << 12) + j] = 0.0;
+      wait_vm();                                      // zeros land before any model atomic
     }
+    __syncthreads();
     const int niter = A.niter[img];
     const float thr = A.thr ? A.thr[img] : 0.0f;
     const int64_t coff = A.comp_off[img];
@@ -240,59 +219,66 @@ k_clean(CleanArgs A) {
     int it = 0;
     bool aborted = false;
     for (;; ++it) {
-      // apply the pending pick and find the local peak; no per-pixel branches: pixels a
-      // thread does not own hold NaN (fma keeps NaN, fmaxf ignores it) and read a safe
-      // in-window address chosen by a uniform select
-      // raw buffer loads: SGPR resource at the window origin, fixed per-thread VGPR
-      // offset, per-k SGPR offset (8 KB per k); records end at the image's beam end
+      // apply the pending pick and find the local peak.  Pixels a thread does not own hold
+      // NaN (fma keeps NaN, fmaxf ignores it) and read a safe in-window address.
       const int64_t win0 = (int64_t)(N - py + row0) * twoN + (N - px);
       const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
           const_cast<float*>(bimg + win0), 0, (int)((4LL * N * N - win0) * 4), BUFFER_RSRC_WORD3);
-      float best = posonly ? -INFINITY : -1.0f;
-      float bv[PPT];
+      float4 bv[NS];
 #pragma unroll
-      for (int k = 0; k < PPT; ++k)
-        bv[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)vtb, k < kmax ? 8192 * k : 0, 0));
+      for (int s = 0; s < NS; ++s)
+        bv[s] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)vtb,
+                                                                                  s < smax ? 32768 * s : 0, 0));
+      float best = posonly ? -INFINITY : -1.0f;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        R[4 * s + 0] = fmaf(-f, bv[s].x, R[4 * s + 0]);
+        R[4 * s + 1] = fmaf(-f, bv[s].y, R[4 * s + 1]);
+        R[4 * s + 2] = fmaf(-f, bv[s].z, R[4 * s + 2]);
+        R[4 * s + 3] = fmaf(-f, bv[s].w, R[4 * s + 3]);
+      }
       if (posonly) {
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-          R[k] = fmaf(-f, bv[k], R[k]);
-          best = fmaxf(best, R[k]);
-        }
+        for (int k = 0; k < PPT; ++k) best = fmaxf(best, R[k]);
       } else {
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-          R[k] = fmaf(-f, bv[k], R[k]);
-          best = fmaxf(best, fabsf(R[k]));
-        }
+        for (int k = 0; k < PPT; ++k) best = fmaxf(best, fabsf(R[k]));
       }
       if (it == niter) break;
-      const float wmax = block_max_f(best, red_f);
+      // wave-level argmax: lanes holding the wave maximum find their first pixel
+      const float wmax = wave_max_f(best);
       unsigned long long key = 0ull;
       if (best == wmax) {
         int kf = -1;
 #pragma unroll
-        for (int k = PPT - 1; k >= 0; --k)             // lowest k wins: scan downwards
+        for (int k = PPT - 1; k >= 0; --k)
           if ((posonly ? R[k] : fabsf(R[k])) == wmax) kf = k;
         float rv = 0.0f;
 #pragma unroll
         for (int k = 0; k < PPT; ++k)
           if (k == kf) rv = R[k];
-        key = make_key(rv, c0 + (kf << 10) + tid, posonly);
+        key = make_key(rv, c0 + 4 * (tid + 1024 * (kf >> 2)) + (kf & 3), posonly);
       }
-      key = block_max_u64(key, red_k);
-      unsigned long long tkey;
+      key = wave_max_u64(key);
+      if (lane == 0) red_k[wave] = key;
       ++seq;
-      if (!team_exchange<LOCAL>(slots, G, member, seq, key, red_k, tkey)) { aborted = true; break; }
+      __syncthreads();
+      if (wave == 0) team_exchange_wave0<LOCAL>(slots, G, member, seq, red_k, false);
+      __syncthreads();
+      // the team key is the same in every lane: keep it (and all that follows) uniform
+      const unsigned long long tk = red_k[CL_WAVES + (seq & 1u)];
+      const unsigned long long tkey =
+          ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(tk >> 32)) << 32) |
+          (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)tk);
+      if (tkey == ~0ull) { aborted = true; break; }
       int p;
       float val;
       decode_key(tkey, posonly, p, val);
-      p = __builtin_amdgcn_readfirstlane(p);
-      val = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, val)));
       if (!(fabsf(val) > thr)) break;
       const double fd = (double)A.gain * (double)val;
       if (tid == 0) {
-        if (A.model && p >= c0 && p < c0 + chunk) A.model[d.img_off + p] += fd;
+        // fire-and-forget: same-thread atomics to one address apply in program order
+        if (A.model && p >= c0 && p < c0 + chunk) atomicAdd(A.model + d.img_off + p, fd);
         if (member == 0 && A.comp_idx) {
           st_shared_u32<LOCAL>(reinterpret_cast<unsigned*>(A.comp_idx + coff + it), (unsigned)p);
           st_shared_u64<LOCAL>(reinterpret_cast<unsigned long long*>(A.comp_flux + coff + it),
@@ -309,22 +295,30 @@ k_clean(CleanArgs A) {
     }
     if (member == 0 && tid == 0 && A.ncomp) A.ncomp[img] = it;
     {
-      float* ro = A.resid + d.img_off + c0 + tid;
+      float* ro = A.resid + d.img_off + c0 + t4;
 #pragma unroll
-      for (int k = 0; k < PPT; ++k)
-        if (k < kmax && tvalid) ro[k << 10] = R[k];
+      for (int s = 0; s < NS; ++s)
+        if (s < smax && tvalid)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) ro[(s << 12) + j] = R[4 * s + j];
     }
     if (A.restored && A.cbeam) {
-      // every member needs the whole component list
-      unsigned long long dummy;
+      // every member needs the whole component list: one more exchange, ordered after
+      // member 0's component stores
+      if (lane == 0) red_k[wave] = 0ull;
       ++seq;
-      if (!team_exchange<LOCAL>(slots, G, member, seq, 0ull, red_k, dummy)) {
+      __syncthreads();
+      if (wave == 0) team_exchange_wave0<LOCAL>(slots, G, member, seq, red_k, true);
+      __syncthreads();
+      if (red_k[CL_WAVES + (seq & 1u)] == ~0ull) {
         if (tid == 0 && A.status) atomicOr(&A.status[img], 16);
         return;
       }
 #pragma unroll
-      for (int k = 0; k < PPT; ++k)
-        if (k < kmax && tvalid) Rl[(k << 10) + tid] = R[k];
+      for (int s = 0; s < NS; ++s)
+        if (s < smax && tvalid)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) Rl[4 * (tid + 1024 * s) + j] = R[4 * s + j];
       __syncthreads();
       const float ga = (float)A.cbeam[6 * img + 0], gb = (float)A.cbeam[6 * img + 1],
                   gc = (float)A.cbeam[6 * img + 2];
@@ -532,8 +526,6 @@ __global__ void k_degrid(const InstDesc* __restrict__ inst, const float2* __rest
 
 static const void* clean_kernel(int ppt, bool local) {
   switch (ppt) {
-    case 1: return local ? MI_CLEAN_KERNEL(1, true) : MI_CLEAN_KERNEL(1, false);
-    case 2: return local ? MI_CLEAN_KERNEL(2, true) : MI_CLEAN_KERNEL(2, false);
     case 4: return local ? MI_CLEAN_KERNEL(4, true) : MI_CLEAN_KERNEL(4, false);
     case 8: return local ? MI_CLEAN_KERNEL(8, true) : MI_CLEAN_KERNEL(8, false);
     case 16: return local ? MI_CLEAN_KERNEL(16, true) : MI_CLEAN_KERNEL(16, false);

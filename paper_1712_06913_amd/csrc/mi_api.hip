@@ -619,7 +619,7 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
         while (G * 2 <= std::min(32, G_cap) && (int64_t)G * 2 * n <= 256) G *= 2;
       }
       const bool local = G <= 32;
-      int ppt = 1;
+      int ppt = 4;                                  // 4-pixel groups per 16-byte load
       while (ppt * 1024 * G < P->max_N * P->max_N) ppt *= 2;
       int per_cu = 0;
       const size_t lds = (size_t)(P->max_N * P->max_N / G) * sizeof(float);

@@ -1,0 +1,92 @@
+"""Differentiable imaging on the GPU: ImagingOp (vis -> dirty, backward = hand-written
+adjoint) and PredictOp (model image -> vis, backward = unit-weight imager), checked against
+FP64 finite differences of the oracle's loss and by dot-product identities."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint, imager
+from paper_1712_06913_amd import synth
+from tests.gpu_helpers import log, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(wl):
+    require_gpu()
+    from paper_1712_06913_amd import api
+    b = api.Batch.from_workload(wl)
+    vis, uv, w = api.workload_tensors(wl)
+    return api, b, vis, uv, w
+
+
+def test_imaging_gradient_matches_fp64_finite_differences():
+    log("[autograd] FD on the 64^2, 120-baseline subset")
+    from paper_1712_06913_amd import autograd as ag
+    wl = synth.fd_subset()
+    api, b, vis, uv, w = _setup(wl)
+    N, cell, mode = 64, float(wl.cell_rad[0]), int(wl.weight_mode[0])
+    rng = np.random.default_rng(3)
+    target = rng.standard_normal((N, N))
+    v = vis.clone().requires_grad_(True)
+    d = ag.dirty(v, b, uv, w)
+    loss = torch.sum((d.double() - torch.from_numpy(target.ravel()).cuda()) ** 2)
+    loss.backward()
+    g = v.grad.detach().cpu().numpy().astype(np.complex128)
+    v0 = wl.vis.astype(np.complex128)
+
+    def L(vv):
+        img = imager.dirty_image(vv.astype(np.complex128), wl.uv, wl.w, N, cell, mode)
+        return float(np.sum((img - target) ** 2))
+
+    # the loss is quadratic, so central differences are exact up to rounding
+    for t in range(4):
+        dirn = rng.standard_normal(len(v0)) + 1j * rng.standard_normal(len(v0))
+        eps = 1e-3
+        fd = (L(v0 + eps * dirn) - L(v0 - eps * dirn)) / (2 * eps)
+        an = float(np.real(np.sum(np.conj(g) * dirn)))
+        log(f"  dir {t}: fd={fd:.9e} grad.d={an:.9e} rel={abs(fd - an) / abs(fd):.2e}")
+        assert abs(fd - an) <= 1e-5 * abs(fd)
+
+
+def test_imaging_op_backward_is_oracle_adjoint():
+    log("[autograd] backward vs oracle adjoint, mixed batch")
+    from paper_1712_06913_amd import autograd as ag
+    wl = synth.random_instances(41, [64, 128], m_range=(80, 200))
+    api, b, vis, uv, w = _setup(wl)
+    rng = np.random.default_rng(4)
+    y = rng.standard_normal(int(b.img_off[-1])).astype(np.float32)
+    v = vis.clone().requires_grad_(True)
+    d = ag.dirty(v, b, uv, w)
+    (d * torch.from_numpy(y).cuda()).sum().backward()
+    g = v.grad.detach().cpu().numpy()
+    for i in range(wl.n_inst):
+        vi, uvi, wi = wl.instance(i)
+        N = int(wl.n_img[i])
+        yi = y[b.img_off[i]: b.img_off[i + 1]].reshape(N, N).astype(np.float64)
+        ref = adjoint.adjoint(yi, uvi, wi, N, float(wl.cell_rad[i]), int(wl.weight_mode[i]))
+        got = g[wl.vis_offset[i]: wl.vis_offset[i + 1]]
+        assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref)) * np.log2(N)
+
+
+def test_predict_op_forward_backward_dot_product():
+    log("[autograd] predict op: forward vs oracle, <P y, u> = <y, P^T u>")
+    from paper_1712_06913_amd import autograd as ag
+    wl = synth.c5_differentiable(n_chan=2, N=256)
+    api, b, vis, uv, w = _setup(wl)
+    rng = np.random.default_rng(5)
+    y = torch.from_numpy(rng.standard_normal(int(b.img_off[-1])).astype(np.float32)).cuda().requires_grad_(True)
+    u = torch.from_numpy((rng.standard_normal(len(wl.vis)) + 1j * rng.standard_normal(len(wl.vis))).astype(np.complex64)).cuda()
+    p = ag.predict(y, b, uv, w)
+    lhs = torch.sum(p.real.double() * u.real.double() + p.imag.double() * u.imag.double())
+    lhs.backward()
+    rhs = torch.dot(y.detach().double(), y.grad.double())
+    log(f"  <Py,u>={float(lhs):.9e} <y,PTu>={float(rhs):.9e}")
+    assert abs(float(lhs) - float(rhs)) <= 1e-5 * abs(float(lhs))
+    # forward against the oracle prediction for the first instance
+    N = int(wl.n_img[0])
+    vi, uvi, wi = wl.instance(0)
+    ref = adjoint.predict(y.detach()[:N * N].cpu().numpy().reshape(N, N).astype(np.float64), uvi, wi, N,
+                          float(wl.cell_rad[0]))
+    got = p.detach()[: len(vi)].cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref))
