@@ -147,11 +147,11 @@ __device__ __forceinline__ void team_exchange_wave0(unsigned long long* slots, i
 
 }  // namespace
 
-// Residual in registers: thread t of member m owns 4-pixel groups at c0 + 4 (t + 1024 s) + j,
-// s < PPT/4, j < 4 (c0 = m N^2/G).  For N <= 1024 and G <= N, c0 is a row start and a
-// step of 4096 pixels is 4096/N whole rows, i.e. 8192 floats further into the beam window:
-// each group is one 16-byte buffer load at a uniform (SGPR) offset from a fixed per-thread
-// offset.
+// Residual in registers: thread t of member m owns 4-pixel groups at
+// c0 + 4 (t + CL_THREADS s) + j, s < PPT/4, j < 4 (c0 = m N^2/G).  For N <= 1024 and G <= N,
+// c0 is a row start and a step of 4 CL_THREADS = 4096 pixels is 4096/N whole rows, i.e.
+// 8192 floats further into the beam window: each group is one 16-byte buffer load at a
+// uniform (SGPR) offset from a fixed per-thread offset.
 template <int PPT, bool LOCAL>
 __global__ void __launch_bounds__(CL_THREADS)
 k_clean(CleanArgs A) {
@@ -187,8 +187,9 @@ k_clean(CleanArgs A) {
     const int N = d.N, log2N = d.log2N, twoN = 2 * N;
     const int chunk = (N * N) / G;
     const int c0 = member * chunk;
-    const int smax = (chunk + 4095) >> 12;            // uniform
-    const bool tvalid = 4 * tid < chunk;              // false only when chunk < 4096
+    constexpr int STEP = 4 * CL_THREADS;              // pixels per load step
+    const int smax = (chunk + STEP - 1) / STEP;       // uniform
+    const bool tvalid = 4 * tid < chunk;              // false only when chunk < STEP
     const int t4 = 4 * tid;
     const unsigned vtb = tvalid ? (unsigned)(((t4 >> log2N) * twoN + (t4 & (N - 1))) * 4) : 0u;
     const int row0 = c0 >> log2N;
@@ -198,7 +199,7 @@ k_clean(CleanArgs A) {
 #pragma unroll
       for (int s = 0; s < NS; ++s)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) R[4 * s + j] = (s < smax && tvalid) ? dsrc[(s << 12) + j] : NaN;
+        for (int j = 0; j < 4; ++j) R[4 * s + j] = (s < smax && tvalid) ? dsrc[s * STEP + j] : NaN;
     }
     if (A.model) {
       double* m = A.model + d.img_off + c0 + t4;
@@ -206,7 +207,7 @@ k_clean(CleanArgs A) {
       for (int s = 0; s < NS; ++s)
         if (s < smax && tvalid)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) m[(s << 12) + j] = 0.0;
+          for (int j = 0; j < 4; ++j) m[s * STEP + j] = 0.0;
       wait_vm();                                      // zeros land before any model atomic
     }
     __syncthreads();
@@ -227,8 +228,8 @@ k_clean(CleanArgs A) {
       float4 bv[NS];
 #pragma unroll
       for (int s = 0; s < NS; ++s)
-        bv[s] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)vtb,
-                                                                                  s < smax ? 32768 * s : 0, 0));
+        bv[s] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(
+                                               rs, (int)vtb, s < smax ? 2 * STEP * 4 * s : 0, 0));
       float best = posonly ? -INFINITY : -1.0f;
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
@@ -257,7 +258,7 @@ k_clean(CleanArgs A) {
 #pragma unroll
         for (int k = 0; k < PPT; ++k)
           if (k == kf) rv = R[k];
-        key = make_key(rv, c0 + 4 * (tid + 1024 * (kf >> 2)) + (kf & 3), posonly);
+        key = make_key(rv, c0 + 4 * (tid + CL_THREADS * (kf >> 2)) + (kf & 3), posonly);
       }
       key = wave_max_u64(key);
       if (lane == 0) red_k[wave] = key;
@@ -300,7 +301,7 @@ k_clean(CleanArgs A) {
       for (int s = 0; s < NS; ++s)
         if (s < smax && tvalid)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) ro[(s << 12) + j] = R[4 * s + j];
+          for (int j = 0; j < 4; ++j) ro[s * STEP + j] = R[4 * s + j];
     }
     if (A.restored && A.cbeam) {
       // every member needs the whole component list: one more exchange, ordered after
@@ -318,7 +319,7 @@ k_clean(CleanArgs A) {
       for (int s = 0; s < NS; ++s)
         if (s < smax && tvalid)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) Rl[4 * (tid + 1024 * s) + j] = R[4 * s + j];
+          for (int j = 0; j < 4; ++j) Rl[4 * (tid + CL_THREADS * s) + j] = R[4 * s + j];
       __syncthreads();
       const float ga = (float)A.cbeam[6 * img + 0], gb = (float)A.cbeam[6 * img + 1],
                   gc = (float)A.cbeam[6 * img + 2];
