@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--only-steps", action="store_true", help="timed steps only (for profilers)")
     ap.add_argument("--plain-subset", type=int, default=8)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before the steps, copy this many MiB device-to-device with a plain kernel "
+                         "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -114,6 +117,12 @@ def main():
             ev[3].record(stream)
         return res
 
+    if args.calib_copy_mib:
+        src = torch.ones(args.calib_copy_mib * (1 << 18), dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)         # one elementwise kernel: reads and writes calib MiB
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.calib_copy_mib} MiB done")
     for i in range(args.warmup):
         res = step()
         torch.cuda.synchronize()

@@ -61,8 +61,7 @@ enum {
   MI_INST_LOBE_CLIPPED = 2,   /* clean-beam main lobe reached the fit box edge        */
   MI_INST_RESTORE_CLIPPED = 4,/* restoring Gaussian wider than the restore window     */
   MI_INST_TEST_FAILED = 8,    /* forced by MI_TEST_FAIL_INSTANCE (failure-path tests) */
-  MI_INST_ABORTED = 16,       /* a CLEAN team barrier timed out; outputs incomplete     */
-  MI_INST_XCD_MISMATCH = 32   /* a CLEAN workgroup ran off the XCD its team relies on   */
+  MI_INST_ABORTED = 16        /* a CLEAN team barrier timed out; outputs incomplete     */
 };
 
 /* Weighting mode, as Algorithm 1's wgtGrid_kernel: mode 1 = uniform, otherwise natural. */

@@ -134,24 +134,27 @@ def ifft2(data: torch.Tensor, n, offs, device: int = 0):
 
 
 def hogbom_clean(batch: Batch, dirty, beam, niter, gain: float = 0.1, threshold=None, positive_only=False,
-                 restore: bool = True, want_model: bool = True, want_components: bool = True, team_size: int = 0):
-    """mi_hogbom_clean; returns a dict of device tensors."""
+                 restore: bool = True, want_model: bool = True, want_components: bool = True, team_size: int = 0,
+                 out=None):
+    """mi_hogbom_clean; returns a dict of device tensors (reused when `out` is a previous result)."""
     dev = batch.device
     niter = np.ascontiguousarray(niter, dtype=np.int32)
     thr = None if threshold is None else np.ascontiguousarray(threshold, dtype=np.float32)
     nimg = int(batch.img_off[-1])
-    res = {"residual": torch.empty(nimg, dtype=torch.float32, device=dev)}
-    res["model"] = torch.empty(nimg, dtype=torch.float64, device=dev) if want_model else None
     ncomp_total = max(1, int(niter.sum()))
-    if want_components:
-        res["comp_idx"] = torch.full((ncomp_total,), -1, dtype=torch.int32, device=dev)
-        res["comp_flux"] = torch.zeros(ncomp_total, dtype=torch.float64, device=dev)
-    else:
-        res["comp_idx"] = res["comp_flux"] = None
-    res["n_comp"] = torch.zeros(batch.n_inst, dtype=torch.int32, device=dev)
-    res["restored"] = torch.empty(nimg, dtype=torch.float32, device=dev) if restore else None
-    res["cbeam"] = torch.zeros(6 * batch.n_inst, dtype=torch.float64, device=dev) if restore else None
-    res["comp_off"] = np.concatenate([[0], np.cumsum(niter.astype(np.int64))])
+    res = out
+    if res is None:
+        res = {"residual": torch.empty(nimg, dtype=torch.float32, device=dev)}
+        res["model"] = torch.empty(nimg, dtype=torch.float64, device=dev) if want_model else None
+        if want_components:
+            res["comp_idx"] = torch.full((ncomp_total,), -1, dtype=torch.int32, device=dev)
+            res["comp_flux"] = torch.zeros(ncomp_total, dtype=torch.float64, device=dev)
+        else:
+            res["comp_idx"] = res["comp_flux"] = None
+        res["n_comp"] = torch.zeros(batch.n_inst, dtype=torch.int32, device=dev)
+        res["restored"] = torch.empty(nimg, dtype=torch.float32, device=dev) if restore else None
+        res["cbeam"] = torch.zeros(6 * batch.n_inst, dtype=torch.float64, device=dev) if restore else None
+        res["comp_off"] = np.concatenate([[0], np.cumsum(niter.astype(np.int64))])
     prm = nat.MiCleanParams(float(gain), niter.ctypes.data, None if thr is None else thr.ctypes.data,
                             1 if positive_only else 0, int(team_size))
     nat.check(batch.ctx, nat.lib().mi_hogbom_clean(

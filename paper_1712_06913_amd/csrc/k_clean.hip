@@ -171,12 +171,6 @@ k_clean(CleanArgs A) {
     member = blockIdx.x % G;
   }
   unsigned long long* slots = A.slots + (size_t)team * 2 * G;
-  if (LOCAL && tid == 0 && A.status && A.team_off[team] < A.team_off[team + 1]) {
-    // the XCD-local placement assumes block b runs on XCD b % 8
-    unsigned xcc;
-    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
-    if ((int)(xcc & 7u) != (int)(blockIdx.x & 7)) atomicOr(&A.status[A.team_imgs[A.team_off[team]]], 32);
-  }
   unsigned seq = 0;
   const float NaN = __uint_as_float(0x7fc00000u);
   const int posonly = A.posonly;

@@ -1,0 +1,118 @@
+"""Batched imaging step: dirty image + beam -> CLEAN + restore -> adjoint of the residual.
+
+`ImagingPipeline` owns persistent device buffers for one batch descriptor so a step makes
+no allocation, and can replay the step from a captured HIP graph (torch.cuda.CUDAGraph).
+`autotune_team_size` picks the CLEAN team size (workgroups per image) for a batch shape by
+timing a short proxy run of every candidate; choices are cached by shape key.  (The
+oversampling factor is not a tuning knob: it is part of the method's definition.)
+"""
+from __future__ import annotations
+
+import time
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+import torch
+
+from . import api
+
+_TEAM_CACHE: Dict[Tuple, int] = {}
+
+
+def shape_key(batch: api.Batch, niter) -> Tuple:
+    sizes, counts = np.unique(batch.n_img, return_counts=True)
+    return (tuple(int(s) for s in sizes), tuple(int(c) for c in counts), int(np.max(niter)) // 500)
+
+
+def team_candidates(batch: api.Batch):
+    n_max, n_min = int(batch.n_img.max()), int(batch.n_img.min())
+    g_min = max(1, n_max * n_max // 32768)
+    g_cap = min(256, n_min)
+    out, g = [0], g_min
+    while g <= g_cap:
+        out.append(g)
+        g *= 2
+    return out
+
+
+def autotune_team_size(batch: api.Batch, dirty, beam, niter, gain=0.1, proxy_iters=200, reps=2) -> int:
+    """Fastest CLEAN team size (0 = the library's default policy) for this batch shape."""
+    key = shape_key(batch, niter)
+    if key in _TEAM_CACHE:
+        return _TEAM_CACHE[key]
+    proxy = np.minimum(np.asarray(niter, np.int32), proxy_iters)
+    best, best_t = 0, float("inf")
+    for ts in team_candidates(batch):
+        try:
+            api.hogbom_clean(batch, dirty, beam, proxy, gain=gain, restore=False, team_size=ts)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                api.hogbom_clean(batch, dirty, beam, proxy, gain=gain, restore=False, team_size=ts)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / reps
+        except Exception:       # a candidate the device cannot host
+            continue
+        if t < best_t:
+            best, best_t = ts, t
+    _TEAM_CACHE[key] = best
+    return best
+
+
+class ImagingPipeline:
+    """One batch descriptor, persistent buffers, eager or graph-replayed steps."""
+
+    def __init__(self, wl, device="cuda:0", team_size: int = 0, restore: bool = True, adjoint: bool = True):
+        self.dev = torch.device(device)
+        self.wl = wl
+        self.batch = api.Batch.from_workload(wl, self.dev)
+        self.vis, self.uv, self.w = api.workload_tensors(wl, self.dev)
+        b = self.batch
+        self.niter = np.ascontiguousarray(wl.niter, np.int32)
+        self.gain = float(wl.gain)
+        self.team_size = team_size
+        self.restore = restore
+        self.adjoint = adjoint
+        nimg, nbeam = int(b.img_off[-1]), int(b.beam_off[-1])
+        self.dirty = torch.empty(nimg, dtype=torch.float32, device=self.dev)
+        self.beam = torch.empty(nbeam, dtype=torch.float32, device=self.dev)
+        self.b0 = torch.empty(2 * b.n_inst, dtype=torch.float64, device=self.dev)
+        self.adj = torch.empty(int(wl.vis_offset[-1]), dtype=torch.complex64, device=self.dev)
+        self.res = None
+        self.graph: Optional[torch.cuda.CUDAGraph] = None
+
+    def step(self):
+        b = self.batch
+        api.dirty_image(b, self.vis, self.uv, self.w, beam=True, out=self.dirty, beam_out=self.beam, b0_out=self.b0)
+        self.res = api.hogbom_clean(b, self.dirty, self.beam, self.niter, gain=self.gain, restore=self.restore,
+                                    team_size=self.team_size, out=self.res)
+        if self.adjoint:
+            api.degrid(b, self.res["residual"], self.uv, self.w, adjoint=True, out=self.adj)
+        return self.res
+
+    def tune(self):
+        """Pick the CLEAN team size with the autotuner (runs the imaging stage once)."""
+        b = self.batch
+        api.dirty_image(b, self.vis, self.uv, self.w, beam=True, out=self.dirty, beam_out=self.beam, b0_out=self.b0)
+        self.team_size = autotune_team_size(b, self.dirty, self.beam, self.niter, self.gain)
+        return self.team_size
+
+    def capture(self):
+        """Warm up (plans, workspaces) and capture one step into a HIP graph."""
+        self.step()
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream(self.dev)
+        s.wait_stream(torch.cuda.current_stream(self.dev))
+        with torch.cuda.stream(s):
+            self.step()
+        torch.cuda.current_stream(self.dev).wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step()
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+        return self.res

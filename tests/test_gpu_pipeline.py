@@ -1,0 +1,98 @@
+"""Batched execution on the GPU: a mixed-size, uneven batch (image sizes 256/512/1024,
+200-1770 baselines with random flags, mixed weighting, per-instance niter) through one
+launch per stage; HIP-graph replay of the whole step against the eager result; the CLEAN
+team-size autotuner."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import clean, imager
+from paper_1712_06913_amd import synth
+from tests.gpu_helpers import log, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _c4_slice(n=10, niter_cap=300):
+    wl = synth.c4_uneven(n)
+    wl.niter = np.minimum(wl.niter, niter_cap).astype(np.int32)
+    return wl
+
+
+def test_mixed_batch_matches_oracle():
+    log("[pipeline] C4 slice: mixed N, uneven M, mixed weighting")
+    require_gpu()
+    from paper_1712_06913_amd import pipeline
+    wl = _c4_slice(8, niter_cap=200)
+    pl = pipeline.ImagingPipeline(wl)
+    res = pl.step()
+    torch.cuda.synchronize()
+    b = pl.batch
+    dirty = b.split(pl.dirty)
+    beams = b.split(pl.beam, beam=True)
+    resid = b.split(res["residual"])
+    nc = res["n_comp"].cpu().numpy()
+    ci, cf = res["comp_idx"].cpu().numpy(), res["comp_flux"].cpu().numpy()
+    off = res["comp_off"]
+    for i in range(wl.n_inst):
+        v, uv, w = wl.instance(i)
+        N, cell, mode = int(wl.n_img[i]), float(wl.cell_rad[i]), int(wl.weight_mode[i])
+        ref = imager.dirty_image(v, uv, w, N, cell, mode)
+        refb = imager.dirty_beam(uv, w, N, cell, mode)
+        peak = np.max(np.abs(ref))
+        d = dirty[i].cpu().numpy()
+        bm = beams[i].cpu().numpy()
+        log(f"  inst {i} N={N} M={len(v)} mode={mode} dirty err/peak={np.max(np.abs(d - ref)) / peak:.2e}")
+        assert np.max(np.abs(d - ref)) <= 1e-4 * peak
+        assert np.max(np.abs(bm - refb)) <= 1e-4
+        if N <= 512:   # the FP64 CLEAN replay of 1024^2 maps is slow on the host
+            n = int(nc[i])
+            ok, bad, R, _ = clean.replay(d.astype(np.float64), bm.astype(np.float64), ci[off[i]: off[i] + n],
+                                         cf[off[i]: off[i] + n])
+            assert ok, f"instance {i}: pick {bad} rejected"
+            assert np.max(np.abs(resid[i].cpu().numpy() - R)) <= 1e-4 * np.max(np.abs(d))
+
+
+def test_graph_replay_matches_eager():
+    log("[pipeline] HIP graph capture and replay of a whole step")
+    require_gpu()
+    from paper_1712_06913_amd import pipeline
+    wl = _c4_slice(10, niter_cap=300)
+    pl = pipeline.ImagingPipeline(wl)
+    res = pl.step()
+    torch.cuda.synchronize()
+    eager = {k: (v.clone() if torch.is_tensor(v) else v) for k, v in res.items()}
+    eager_dirty, eager_adj = pl.dirty.clone(), pl.adj.clone()
+    pl.capture()
+    scratch = torch.randn(1 << 20, device="cuda")
+    for r in range(3):
+        pl.dirty.fill_(0.0)
+        pl.res["residual"].fill_(0.0)
+        pl.replay()
+        torch.cuda.synchronize()
+        scratch.mul_(1.0001)                     # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(pl.res["n_comp"], eager["n_comp"]), f"replay {r}"
+        assert torch.equal(pl.res["comp_idx"], eager["comp_idx"]), f"replay {r}"
+        for name, a, b in (("dirty", pl.dirty, eager_dirty), ("residual", pl.res["residual"], eager["residual"]),
+                           ("restored", pl.res["restored"], eager["restored"]), ("adjoint", pl.adj, eager_adj)):
+            err = float((a - b).abs().max())
+            scale = float(b.abs().max())
+            log(f"  replay {r} {name}: max |diff| / max = {err / scale:.1e}")
+            assert err <= 1e-6 * scale, f"replay {r} {name}"
+
+
+def test_autotuner_picks_a_working_team_size():
+    log("[pipeline] CLEAN team-size autotuner")
+    require_gpu()
+    from paper_1712_06913_amd import pipeline
+    wl = synth.c3_muser2(chans=list(range(0, 520, 40)), niter=300)
+    pl = pipeline.ImagingPipeline(wl, adjoint=False)
+    ts = pl.tune()
+    log(f"  chose team size {ts} from {pipeline.team_candidates(pl.batch)}")
+    assert ts in pipeline.team_candidates(pl.batch)
+    res = pl.step()
+    torch.cuda.synchronize()
+    st = pl.batch.status.cpu().numpy()
+    assert not np.any(st & 16), f"aborted instances: {st}"
+    assert np.all(res["n_comp"].cpu().numpy() == 300)
