@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--only-steps", action="store_true", help="timed steps only (for profilers)")
     ap.add_argument("--plain-subset", type=int, default=8)
+    ap.add_argument("--team-size", type=int, default=0,
+                    help="CLEAN workgroups per image (0: the library's policy)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the steps, copy this many MiB device-to-device with a plain kernel "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -109,7 +111,7 @@ def main():
         api.dirty_image(b, vis, uv, w, beam=True, out=dirty, beam_out=beam, b0_out=b0)
         if ev is not None:
             ev[1].record(stream)
-        res = api.hogbom_clean(b, dirty, beam, niter, gain=wl.gain, restore=True)
+        res = api.hogbom_clean(b, dirty, beam, niter, gain=wl.gain, restore=True, team_size=args.team_size)
         if ev is not None:
             ev[2].record(stream)
         api.degrid(b, res["residual"], uv, w, adjoint=True, out=adj)
@@ -178,7 +180,8 @@ def main():
         "dtype": "f32 (grid/FFT f64)", "data": "synthetic",
         "config": {"workload": wl.name, "n_inst": n_inst, "N": sorted(set(int(x) for x in b.n_img)),
                    "visibilities": int(wl.vis_offset[-1]), "niter_total": int(niter.sum()),
-                   "gain": wl.gain, "weighting": "natural" if not wl.weight_mode.any() else "mixed/uniform"},
+                   "gain": wl.gain, "weighting": "natural" if not wl.weight_mode.any() else "mixed/uniform",
+                   "clean_team_size": args.team_size or "library policy"},
         "stage_ms": {"dirty_image_and_beam": img_ms, "clean_restore": clean_ms, "adjoint": adj_ms,
                      "gridding_only": grid_ms},
         "gridded_vis_per_s": kept / (grid_ms * 1e-3),

@@ -93,31 +93,49 @@ __device__ __forceinline__ void decode_key(unsigned long long key, int posonly, 
   }
 }
 
+// Wave-wide maximum of a 32-bit unsigned value, returned uniform: DPP steps within each
+// row of 16 lanes (quad swaps, half-row and row mirrors), then the four row results.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false));   // [1,0,3,2]
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false));   // [2,3,0,1]
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xF, 0xF, false));  // half mirror
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xF, 0xF, false));  // row mirror
+  const unsigned r0 = (unsigned)__builtin_amdgcn_readlane((int)v, 0);
+  const unsigned r1 = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+  const unsigned r2 = (unsigned)__builtin_amdgcn_readlane((int)v, 32);
+  const unsigned r3 = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+  return max(max(r0, r1), max(r2, r3));
+}
+
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-  for (int o = 32; o > 0; o >>= 1) {
-    unsigned long long t = __shfl_xor(v, o);
-    v = t > v ? t : v;
-  }
-  return v;
+  const unsigned hi = wave_max_u32((unsigned)(v >> 32));
+  const unsigned lo = wave_max_u32((unsigned)(v >> 32) == hi ? (unsigned)v : 0u);
+  return ((unsigned long long)hi << 32) | lo;
 }
 
-__device__ __forceinline__ float wave_max_f(float v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-  return v;
+// Order-preserving 32-bit key of a peak candidate: |r| bits (all pixels) or the signed
+// float's total order (positive-only picks).  Empty lanes give the smallest keys.
+__device__ __forceinline__ unsigned value_key(float r, int posonly) {
+  const unsigned b = __float_as_uint(r);
+  if (posonly) return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+  return (b & 0x80000000u) ? 0u : b;                  // r = |R| >= 0, or -1 when empty
 }
 
-// Team exchange, run by wave 0 only: reduce the 16 wave keys in red[0..15] to this
-// workgroup's key, publish it for barrier `seq`, then poll the team's G slots until all
-// carry `seq` and leave their maximum in red[16 + (seq & 1)] (~0 if the wait timed out).
-// `ordered`: wait for this wave's earlier stores (component list) before publishing.
+__device__ __forceinline__ float key_value(unsigned k32, int posonly) {
+  if (posonly) return __uint_as_float((k32 & 0x80000000u) ? (k32 & 0x7fffffffu) : ~k32);
+  return __uint_as_float(k32);
+}
+
+// Team exchange, run by one whole wave with its workgroup key wk (uniform): publish it for
+// barrier `seq`, poll the team's G slots until all carry `seq`, and leave their maximum in
+// *out (~0 if the wait timed out).  `ordered`: wait for this wave's earlier stores
+// (component list) before publishing.
 constexpr unsigned POLL_LIMIT = 1u << 22;
 
 template <bool LOCAL>
-__device__ __forceinline__ void team_exchange_wave0(unsigned long long* slots, int G, int member, unsigned seq,
-                                                    unsigned long long* red, bool ordered) {
-  const int lane = threadIdx.x;                       // wave 0
-  unsigned long long wk = lane < CL_WAVES ? red[lane] : 0ull;
-  wk = wave_max_u64(wk);
+__device__ __forceinline__ void team_exchange(unsigned long long* slots, int G, int member, unsigned seq,
+                                              unsigned long long wk, unsigned long long* out, bool ordered) {
+  const int lane = threadIdx.x & 63;
   const unsigned s7 = seq & 127u;
   unsigned long long* sl = slots + (seq & 1u) * G;
   if (lane == 0) {
@@ -142,7 +160,7 @@ __device__ __forceinline__ void team_exchange_wave0(unsigned long long* slots, i
     if (m < G && done) k = v > k ? v : k;
   }
   k = wave_max_u64(k);
-  if (lane == 0) red[CL_WAVES + (seq & 1u)] = timed_out ? ~0ull : k;
+  if (lane == 0) *out = timed_out ? ~0ull : k;
 }
 
 }  // namespace
@@ -157,8 +175,10 @@ __global__ void __launch_bounds__(CL_THREADS)
 k_clean(CleanArgs A) {
   static_assert(PPT % 4 == 0, "4 pixels per load");
   constexpr int NS = PPT / 4;
+  constexpr int LB = NS < 8 ? NS : 8;
   extern __shared__ float Rl[];                       // restore staging (when requested)
-  __shared__ unsigned long long red_k[CL_WAVES + 2];
+  __shared__ unsigned long long red_k[CL_WAVES + 2];  // [0..1] team key by parity, [2..] wave keys
+  __shared__ unsigned red_v[CL_WAVES];                // wave peak-value keys
   const int G = A.G;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int team, member;
@@ -215,22 +235,27 @@ k_clean(CleanArgs A) {
     bool aborted = false;
     for (;; ++it) {
       // apply the pending pick and find the local peak.  Pixels a thread does not own hold
-      // NaN (fma keeps NaN, fmaxf ignores it) and read a safe in-window address.
+      // NaN (fma keeps NaN, fmaxf ignores it); their loads either stay inside this image's
+      // beam or lie past the resource's range, which returns zero.
       const int64_t win0 = (int64_t)(N - py + row0) * twoN + (N - px);
       const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
           const_cast<float*>(bimg + win0), 0, (int)((4LL * N * N - win0) * 4), BUFFER_RSRC_WORD3);
-      float4 bv[NS];
-#pragma unroll
-      for (int s = 0; s < NS; ++s)
-        bv[s] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(
-                                               rs, (int)vtb, s < smax ? 2 * STEP * 4 * s : 0, 0));
       float best = posonly ? -INFINITY : -1.0f;
+      // loads in batches of at most 8 x 16 bytes, so PPT = 64 stays within 128 VGPRs
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        R[4 * s + 0] = fmaf(-f, bv[s].x, R[4 * s + 0]);
-        R[4 * s + 1] = fmaf(-f, bv[s].y, R[4 * s + 1]);
-        R[4 * s + 2] = fmaf(-f, bv[s].z, R[4 * s + 2]);
-        R[4 * s + 3] = fmaf(-f, bv[s].w, R[4 * s + 3]);
+      for (int s0 = 0; s0 < NS; s0 += LB) {
+        float4 bv[LB];
+#pragma unroll
+        for (int s = 0; s < LB; ++s)
+          bv[s] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                 rs, (int)vtb, 2 * STEP * 4 * (s0 + s), 0));
+#pragma unroll
+        for (int s = 0; s < LB; ++s) {
+          R[4 * (s0 + s) + 0] = fmaf(-f, bv[s].x, R[4 * (s0 + s) + 0]);
+          R[4 * (s0 + s) + 1] = fmaf(-f, bv[s].y, R[4 * (s0 + s) + 1]);
+          R[4 * (s0 + s) + 2] = fmaf(-f, bv[s].z, R[4 * (s0 + s) + 2]);
+          R[4 * (s0 + s) + 3] = fmaf(-f, bv[s].w, R[4 * (s0 + s) + 3]);
+        }
       }
       if (posonly) {
 #pragma unroll
@@ -240,28 +265,54 @@ k_clean(CleanArgs A) {
         for (int k = 0; k < PPT; ++k) best = fmaxf(best, fabsf(R[k]));
       }
       if (it == niter) break;
-      // wave-level argmax: lanes holding the wave maximum find their first pixel
-      const float wmax = wave_max_f(best);
-      unsigned long long key = 0ull;
-      if (best == wmax) {
-        int kf = -1;
-#pragma unroll
-        for (int k = PPT - 1; k >= 0; --k)
-          if ((posonly ? R[k] : fabsf(R[k])) == wmax) kf = k;
-        float rv = 0.0f;
-#pragma unroll
-        for (int k = 0; k < PPT; ++k)
-          if (k == kf) rv = R[k];
-        key = make_key(rv, c0 + 4 * (tid + CL_THREADS * (kf >> 2)) + (kf & 3), posonly);
-      }
-      key = wave_max_u64(key);
-      if (lane == 0) red_k[wave] = key;
+      // peak value: wave maxima of the 32-bit value keys, then the workgroup maximum
+      const unsigned wk32 = wave_max_u32(value_key(best, posonly));
+      if (lane == 0) red_v[wave] = wk32;
       ++seq;
       __syncthreads();
-      if (wave == 0) team_exchange_wave0<LOCAL>(slots, G, member, seq, red_k, false);
+      const unsigned lv = lane < CL_WAVES ? red_v[lane] : 0u;
+      const unsigned wg32 = wave_max_u32(lv);
+      const int n_tied = __popcll(__ballot(lane < CL_WAVES && lv == wg32));
+      // only a wave holding the workgroup maximum locates it: the first 4-pixel group s in
+      // which some lane matches, the lowest such lane, the lowest pixel in its group
+      unsigned long long key = 0ull;
+      if (wk32 == wg32) {
+        const float wv = key_value(wg32, posonly);
+        bool found = false;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          if (!found && s < smax) {
+            unsigned long long mj[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) mj[j] = __ballot((posonly ? R[4 * s + j] : fabsf(R[4 * s + j])) == wv);
+            const unsigned long long m = mj[0] | mj[1] | mj[2] | mj[3];
+            if (m) {
+              found = true;
+              const int L = __builtin_ctzll(m);
+              const int j = ((mj[0] >> L) & 1ull) ? 0 : ((mj[1] >> L) & 1ull) ? 1 : ((mj[2] >> L) & 1ull) ? 2 : 3;
+              const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(R[4 * s + 0]), L));
+              const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(R[4 * s + 1]), L));
+              const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(R[4 * s + 2]), L));
+              const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(R[4 * s + 3]), L));
+              const float rv = j == 0 ? r0 : j == 1 ? r1 : j == 2 ? r2 : r3;
+              key = make_key(rv, c0 + 4 * (64 * wave + L + CL_THREADS * s) + j, posonly);
+            }
+          }
+        }
+      }
+      if (n_tied == 1) {
+        if (wk32 == wg32) team_exchange<LOCAL>(slots, G, member, seq, key, &red_k[seq & 1u], false);
+      } else {                                        // several waves hold the maximum
+        if (lane == 0) red_k[2 + wave] = key;
+        __syncthreads();
+        if (wave == 0) {
+          const unsigned long long wk = wave_max_u64(lane < CL_WAVES ? red_k[2 + lane] : 0ull);
+          team_exchange<LOCAL>(slots, G, member, seq, wk, &red_k[seq & 1u], false);
+        }
+      }
       __syncthreads();
       // the team key is the same in every lane: keep it (and all that follows) uniform
-      const unsigned long long tk = red_k[CL_WAVES + (seq & 1u)];
+      const unsigned long long tk = red_k[seq & 1u];
       const unsigned long long tkey =
           ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(tk >> 32)) << 32) |
           (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)tk);
@@ -300,46 +351,53 @@ k_clean(CleanArgs A) {
     if (A.restored && A.cbeam) {
       // every member needs the whole component list: one more exchange, ordered after
       // member 0's component stores
-      if (lane == 0) red_k[wave] = 0ull;
       ++seq;
       __syncthreads();
-      if (wave == 0) team_exchange_wave0<LOCAL>(slots, G, member, seq, red_k, true);
+      if (wave == 0) team_exchange<LOCAL>(slots, G, member, seq, 0ull, &red_k[seq & 1u], true);
       __syncthreads();
-      if (red_k[CL_WAVES + (seq & 1u)] == ~0ull) {
+      if (red_k[seq & 1u] == ~0ull) {
         if (tid == 0 && A.status) atomicOr(&A.status[img], 16);
         return;
       }
-#pragma unroll
-      for (int s = 0; s < NS; ++s)
-        if (s < smax && tvalid)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) Rl[4 * (tid + CL_THREADS * s) + j] = R[4 * s + j];
-      __syncthreads();
       const float ga = (float)A.cbeam[6 * img + 0], gb = (float)A.cbeam[6 * img + 1],
                   gc = (float)A.cbeam[6 * img + 2];
       const int rr = A.rrad[img];
       const int side = 2 * rr + 1;
-      const int row_hi = (c0 + chunk - 1) >> log2N;
-      for (int i = 0; i < it; ++i) {
-        const int p = (int)ld_shared_u32<LOCAL>(reinterpret_cast<const unsigned*>(A.comp_idx + coff + i));
-        const int cy = p >> log2N, cx = p & (N - 1);
-        if (cy + rr < row0 || cy - rr > row_hi) continue;
-        const float fc = (float)__longlong_as_double(
-            (long long)ld_shared_u64<LOCAL>(reinterpret_cast<const unsigned long long*>(A.comp_flux + coff + i)));
-        for (int w = tid; w < side * side; w += CL_THREADS) {
-          const int dy = w / side - rr, dx = w % side - rr;
-          const int y = cy + dy, x = cx + dx;
-          if (y < 0 || y >= N || x < 0 || x >= N) continue;
-          const int g = (y << log2N) + x;
-          if (g < c0 || g >= c0 + chunk) continue;
-          const float e = (float)dx * (ga * (float)dx + gb * (float)dy) + gc * (float)dy * (float)dy;
-          atomicAdd(&Rl[g - c0], fc * expf(-e));
+      // the chunk goes through LDS in parts of sub pixels (sub a multiple of STEP or the
+      // whole chunk); each part rescans the component list
+      const int sub = chunk < A.sub_px ? chunk : A.sub_px;
+      for (int p0 = 0; p0 < chunk; p0 += sub) {
+        const int g_lo = c0 + p0, g_hi = g_lo + sub;   // this part: pixels [g_lo, g_hi)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int q = 4 * (tid + CL_THREADS * s);     // chunk-local index of the group
+          if (s < smax && tvalid && q >= p0 && q < p0 + sub)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) Rl[q - p0 + j] = R[4 * s + j];
         }
+        __syncthreads();
+        const int row_lo = g_lo >> log2N, row_hi = (g_hi - 1) >> log2N;
+        for (int i = 0; i < it; ++i) {
+          const int p = (int)ld_shared_u32<LOCAL>(reinterpret_cast<const unsigned*>(A.comp_idx + coff + i));
+          const int cy = p >> log2N, cx = p & (N - 1);
+          if (cy + rr < row_lo || cy - rr > row_hi) continue;
+          const float fc = (float)__longlong_as_double(
+              (long long)ld_shared_u64<LOCAL>(reinterpret_cast<const unsigned long long*>(A.comp_flux + coff + i)));
+          for (int w = tid; w < side * side; w += CL_THREADS) {
+            const int dy = w / side - rr, dx = w % side - rr;
+            const int y = cy + dy, x = cx + dx;
+            if (y < 0 || y >= N || x < 0 || x >= N) continue;
+            const int g = (y << log2N) + x;
+            if (g < g_lo || g >= g_hi) continue;
+            const float e = (float)dx * (ga * (float)dx + gb * (float)dy) + gc * (float)dy * (float)dy;
+            atomicAdd(&Rl[g - g_lo], fc * expf(-e));
+          }
+        }
+        __syncthreads();
+        float* rs = A.restored + d.img_off + g_lo;
+        for (int q = tid; q < sub; q += CL_THREADS) rs[q] = Rl[q];
+        __syncthreads();
       }
-      __syncthreads();
-      float* rs = A.restored + d.img_off + c0;
-      for (int q = tid; q < chunk; q += CL_THREADS) rs[q] = Rl[q];
-      __syncthreads();
     }
   }
 }
@@ -469,7 +527,7 @@ k_beamfit(const InstDesc* __restrict__ inst, const float* __restrict__ beam, dou
 
 // Degrid (prediction / adjoint): one thread per visibility of instance blockIdx.y; FP64
 // tap sums over the FP64 forward spectrum (same cancellation argument as the imager).
-__global__ void k_degrid(const InstDesc* __restrict__ inst, const float2* __restrict__ uv,
+__global__ void __launch_bounds__(256) k_degrid(const InstDesc* __restrict__ inst, const float2* __restrict__ uv,
                          const float* __restrict__ w_in, const float* __restrict__ wts,
                          const double* __restrict__ b0, const double2* __restrict__ fgrid, Tables T,
                          int adjoint, float2* __restrict__ out) {
@@ -525,6 +583,7 @@ static const void* clean_kernel(int ppt, bool local) {
     case 8: return local ? MI_CLEAN_KERNEL(8, true) : MI_CLEAN_KERNEL(8, false);
     case 16: return local ? MI_CLEAN_KERNEL(16, true) : MI_CLEAN_KERNEL(16, false);
     case 32: return local ? MI_CLEAN_KERNEL(32, true) : MI_CLEAN_KERNEL(32, false);
+    case 64: return local ? MI_CLEAN_KERNEL(64, true) : MI_CLEAN_KERNEL(64, false);
     default: return nullptr;
   }
 }

@@ -74,13 +74,18 @@ template <> __device__ __forceinline__ void small_dft<8>(double2* x, double s) {
   x[7] = csub(e[3], o3);
 }
 
+// LDS index with one padding element per 8: strided butterfly stores of 16-byte elements
+// otherwise land on the same banks.
+__device__ __forceinline__ int pd(int i) { return i + (i >> 3); }
+
 // One Stockham radix-R pass over nl lines of P points held in LDS (line stride P).
 // L = product of the radices already applied.  Butterfly b of a line reads x[b + m P/R]
-// and writes y[(b/L) L R + b%L + q L] after twiddling by exp(s 2 pi i m (b%L) / (L R)).
+// and writes y[(b/L) L R + b%L + q L] after twiddling by w^m, w = exp(s 2 pi i (b%L)/(L R));
+// w comes from the FP64 table and its powers by recurrence.
 template <int R, int ELEMS, int THREADS>
 __device__ __forceinline__ void stockham_pass(double2* buf, int log2P, int log2L, int nl, double s,
                                               const double2* __restrict__ tw) {
-  constexpr int BPT = ELEMS / THREADS / R;
+  constexpr int BPT = (ELEMS / THREADS / R) > 0 ? ELEMS / THREADS / R : 1;
   constexpr int LOG2R = R == 8 ? 3 : (R == 4 ? 2 : 1);
   const int log2nb = log2P - LOG2R;
   const int nb = 1 << log2nb;
@@ -93,9 +98,9 @@ __device__ __forceinline__ void stockham_pass(double2* buf, int log2P, int log2L
     const int b = threadIdx.x + q * THREADS;
     if (b < total) {
       const int line = b >> log2nb, bb = b & (nb - 1);
-      const double2* src = buf + (line << log2P) + bb;
+      const int base = (line << log2P) + bb;
 #pragma unroll
-      for (int m = 0; m < R; ++m) x[q][m] = src[m << log2nb];
+      for (int m = 0; m < R; ++m) x[q][m] = buf[pd(base + (m << log2nb))];
     }
   }
   __syncthreads();
@@ -106,17 +111,20 @@ __device__ __forceinline__ void stockham_pass(double2* buf, int log2P, int log2L
       const int line = b >> log2nb, bb = b & (nb - 1);
       const int j = bb & (L - 1), blk = bb >> log2L;
       if (L > 1) {
+        double2 w1 = tw[j << tw_shift];
+        w1.y *= s;
+        double2 w = w1;
+        x[q][1] = cmul(x[q][1], w);
 #pragma unroll
-        for (int m = 1; m < R; ++m) {
-          double2 w = tw[(m * j) << tw_shift];
-          w.y *= s;
+        for (int m = 2; m < R; ++m) {
+          w = cmul(w, w1);
           x[q][m] = cmul(x[q][m], w);
         }
       }
       small_dft<R>(x[q], s);
-      double2* dst = buf + (line << log2P) + (blk << (log2L + LOG2R)) + j;
+      const int base = (line << log2P) + (blk << (log2L + LOG2R)) + j;
 #pragma unroll
-      for (int m = 0; m < R; ++m) dst[m << log2L] = x[q][m];
+      for (int m = 0; m < R; ++m) buf[pd(base + (m << log2L))] = x[q][m];
     }
   }
   __syncthreads();
@@ -144,58 +152,77 @@ __device__ __forceinline__ int lines_per_block(int P) {
   return nl > P / 2 ? P / 2 : nl;
 }
 
+// Rows per workgroup of the real-valued passes: two rows share one complex FFT.
+template <int ELEMS>
+__device__ __forceinline__ int rows_per_block(int P) {
+  const int ny = 2 * ELEMS / P;
+  return ny > P ? P : ny;
+}
+
+constexpr int LDS_PADDED(int elems) { return elems + elems / 8; }
+// Two 512-thread workgroups of the small block share a CU (LDS 2 x 72 KB), which needs
+// 4 waves per SIMD, i.e. at most 128 VGPRs.
+#define FFT_WAVES_PER_EU(ELEMS) ((ELEMS) <= 4096 ? 4 : 2)
+
 }  // namespace
 
 // Pass A (inverse): half-grid lines -> FFT along v -> contiguous block Yb[b][y][l].
 template <int ELEMS, int THREADS>
-__global__ void __launch_bounds__(THREADS)
+__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES_PER_EU(ELEMS))))
 k_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int beam,
         double2* __restrict__ grid, Tables T) {
-  __shared__ double2 buf[ELEMS];
+  __shared__ double2 buf[LDS_PADDED(ELEMS)];
   const FftWork wk = work[blockIdx.x];
   const InstDesc d = inst[wk.inst];
   const int P = beam ? 2 * d.N : d.N, log2P = ilog2(P);
   const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
   double2* blk = grid + (beam ? d.gb_off : d.gd_off) + (int64_t)wk.first * P;   // block start
   const int n = nl * P;
-  for (int q = threadIdx.x; q < n; q += THREADS) buf[q] = blk[q];
+  for (int q = threadIdx.x; q < n; q += THREADS) buf[pd(q)] = blk[q];
   __syncthreads();
   lds_fft<ELEMS, THREADS>(buf, log2P, nl, +1.0, T.twiddle);
   for (int q = threadIdx.x; q < n; q += THREADS) {
     const int y = q >> log2nl, l = q & (nl - 1);
-    blk[q] = buf[(l << log2P) + y];
+    blk[q] = buf[pd((l << log2P) + y)];
   }
 }
 
-// Pass B (inverse, complex-to-real): rows y0..y0+ny-1 of the image.
+// Pass B (inverse, complex-to-real): rows y0..y0+ny-1 of the image, two rows per complex
+// line: Z = X1 + i X2 with X1, X2 Hermitian along u, so Re IDFT(Z) and Im IDFT(Z) are the
+// two real rows.
 template <int ELEMS, int THREADS>
-__global__ void __launch_bounds__(THREADS)
+__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES_PER_EU(ELEMS))))
 k_fft_b_c2r(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int beam,
             const double2* __restrict__ yb, const double* __restrict__ b0, Tables T,
             float* __restrict__ out) {
-  __shared__ double2 buf[ELEMS];
+  __shared__ double2 buf[LDS_PADDED(ELEMS)];
   const FftWork wk = work[blockIdx.x];
   const InstDesc d = inst[wk.inst];
   const int P = beam ? 2 * d.N : d.N, log2P = ilog2(P), h = P / 2;
   const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
-  const int ny = nl;
+  const int ny = rows_per_block<ELEMS>(P), nz = ny / 2;
   const int y0 = wk.first;
   const double2* src = yb + (beam ? d.gb_off : d.gd_off);
   // element (line k', row y) of the blocked layout: (k'/nl) nl P + y nl + k' % nl
   const int nblk = h / nl;
-  const int per_blk = ny * nl;
+  const int per_blk = nz * nl;
   for (int q = threadIdx.x; q < nblk * per_blk; q += THREADS) {
     const int b = q / per_blk, r = q - b * per_blk;
-    const int yl = r >> log2nl, l = r & (nl - 1);
-    const double2 v = src[(int64_t)b * nl * P + (int64_t)(y0 + yl) * nl + l];
+    const int zl = r >> log2nl, l = r & (nl - 1);
+    const int64_t e = (int64_t)b * nl * P + (int64_t)(y0 + 2 * zl) * nl + l;
+    const double2 v1 = src[e], v2 = src[e + nl];
     const int k = b * nl + l + 1;          // u frequency index 1..P/2
-    double2* row = buf + (yl << log2P);
-    row[k] = v;
-    if (k < h) row[P - k] = make_double2(v.x, -v.y);
+    const int row = zl << log2P;
+    if (k < h) {
+      buf[pd(row + k)] = make_double2(v1.x - v2.y, v1.y + v2.x);
+      buf[pd(row + P - k)] = make_double2(v1.x + v2.y, v2.x - v1.y);
+    } else {
+      buf[pd(row + k)] = make_double2(v1.x, v2.x);   // u = 0 column: real by symmetry
+    }
   }
-  for (int yl = threadIdx.x; yl < ny; yl += THREADS) buf[yl << log2P] = make_double2(0.0, 0.0);
+  for (int zl = threadIdx.x; zl < nz; zl += THREADS) buf[pd(zl << log2P)] = make_double2(0.0, 0.0);
   __syncthreads();
-  lds_fft<ELEMS, THREADS>(buf, log2P, ny, +1.0, T.twiddle);
+  lds_fft<ELEMS, THREADS>(buf, log2P, nz, +1.0, T.twiddle);
   const double bd = b0[2 * wk.inst + (beam ? 1 : 0)];
   const double inv_b0 = bd > 0.0 ? 1.0 / bd : 0.0;
   const double* ic = T.inv_corr + (P - 64);
@@ -205,50 +232,61 @@ k_fft_b_c2r(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
     const int y = y0 + yl;
     double s = ic[x] * (ic[y] * inv_b0);
     if ((x + y) & 1) s = -s;
-    o[q] = (float)(buf[q].x * s);
+    const double2 z = buf[pd(((yl >> 1) << log2P) + x)];
+    o[q] = (float)(((yl & 1) ? z.y : z.x) * s);
   }
 }
 
 // Adjoint pass B^T: image rows -> pre-correction and (-1)^(x+y) -> forward FFT along x ->
-// keep u frequencies 1..P/2 -> blocked layout.
+// keep u frequencies 1..P/2 -> blocked layout.  Two real rows per complex line, separated
+// after the transform by X1 = (Z[k] + conj Z[-k]) / 2, X2 = (Z[k] - conj Z[-k]) / 2i.
 template <int ELEMS, int THREADS>
-__global__ void __launch_bounds__(THREADS)
+__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES_PER_EU(ELEMS))))
 k_fft_b_r2c(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
             const float* __restrict__ img, Tables T, double2* __restrict__ yb) {
-  __shared__ double2 buf[ELEMS];
+  __shared__ double2 buf[LDS_PADDED(ELEMS)];
   const FftWork wk = work[blockIdx.x];
   const InstDesc d = inst[wk.inst];
   const int P = d.N, log2P = ilog2(P), h = P / 2;
   const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
-  const int ny = nl;
+  const int ny = rows_per_block<ELEMS>(P), nz = ny / 2;
   const int y0 = wk.first;
   const double* ic = T.inv_corr + (P - 64);
   const float* src = img + d.img_off + (int64_t)y0 * P;
-  for (int q = threadIdx.x; q < ny * P; q += THREADS) {
-    const int yl = q >> log2P, x = q & (P - 1);
-    const int y = y0 + yl;
-    double s = ic[x] * ic[y];
+  for (int q = threadIdx.x; q < nz * P; q += THREADS) {
+    const int zl = q >> log2P, x = q & (P - 1);
+    const int y = y0 + 2 * zl;
+    double s = ic[x] * ic[y], s2 = ic[x] * ic[y + 1];
     if ((x + y) & 1) s = -s;
-    buf[q] = make_double2((double)src[q] * s, 0.0);
+    else s2 = -s2;
+    const float* r0 = src + ((int64_t)(2 * zl) << log2P) + x;
+    buf[pd(q)] = make_double2((double)r0[0] * s, (double)r0[P] * s2);
   }
   __syncthreads();
-  lds_fft<ELEMS, THREADS>(buf, log2P, ny, -1.0, T.twiddle);
+  lds_fft<ELEMS, THREADS>(buf, log2P, nz, -1.0, T.twiddle);
   double2* dst = yb + d.gd_off;
-  const int nblk = h / nl, per_blk = ny * nl;
+  const int nblk = h / nl, per_blk = nz * nl;
   for (int q = threadIdx.x; q < nblk * per_blk; q += THREADS) {
     const int b = q / per_blk, r = q - b * per_blk;
-    const int yl = r >> log2nl, l = r & (nl - 1);
+    const int zl = r >> log2nl, l = r & (nl - 1);
     const int k = b * nl + l + 1;
-    dst[(int64_t)b * nl * P + (int64_t)(y0 + yl) * nl + l] = buf[(yl << log2P) + k];
+    const double2 A = buf[pd((zl << log2P) + k)];
+    const double2 B = buf[pd((zl << log2P) + ((P - k) & (P - 1)))];
+    // X1 = (A + conj B) / 2,  X2 = -i (A - conj B) / 2
+    const double2 x1 = make_double2(0.5 * (A.x + B.x), 0.5 * (A.y - B.y));
+    const double2 x2 = make_double2(0.5 * (A.y + B.y), -0.5 * (A.x - B.x));
+    const int64_t e = (int64_t)b * nl * P + (int64_t)(y0 + 2 * zl) * nl + l;
+    dst[e] = x1;
+    dst[e + nl] = x2;
   }
 }
 
 // Adjoint pass A^T: blocked layout -> forward FFT along v -> (-1)^(i+j) -> half grid lines.
 template <int ELEMS, int THREADS>
-__global__ void __launch_bounds__(THREADS)
+__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES_PER_EU(ELEMS))))
 k_fft_a_fwd(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, Tables T,
             double2* __restrict__ grid) {
-  __shared__ double2 buf[ELEMS];
+  __shared__ double2 buf[LDS_PADDED(ELEMS)];
   const FftWork wk = work[blockIdx.x];
   const InstDesc d = inst[wk.inst];
   const int P = d.N, log2P = ilog2(P);
@@ -257,13 +295,13 @@ k_fft_a_fwd(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
   const int n = nl * P;
   for (int q = threadIdx.x; q < n; q += THREADS) {
     const int y = q >> log2nl, l = q & (nl - 1);
-    buf[(l << log2P) + y] = blk[q];
+    buf[pd((l << log2P) + y)] = blk[q];
   }
   __syncthreads();
   lds_fft<ELEMS, THREADS>(buf, log2P, nl, -1.0, T.twiddle);
   for (int q = threadIdx.x; q < n; q += THREADS) {
     const int l = q >> log2P, j = q & (P - 1);
-    double2 v = buf[q];
+    double2 v = buf[pd(q)];
     if (((wk.first + l + 1) + j) & 1) { v.x = -v.x; v.y = -v.y; }
     blk[q] = v;
   }
@@ -273,10 +311,10 @@ k_fft_a_fwd(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
 // src lines of length P (stride P), nl lines per block; dst[y * P + line].
 // pre: multiply input (line, n) by (-1)^(line+n); post: output (y, line) by (-1)^(y+line).
 template <int ELEMS, int THREADS, class TIn, class TOut>
-__global__ void __launch_bounds__(THREADS)
+__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES_PER_EU(ELEMS))))
 k_fft_c2c_t(const int* __restrict__ n_arr, const int64_t* __restrict__ offs, const FftWork* __restrict__ work,
             const TIn* __restrict__ src, TOut* __restrict__ dst, Tables T, double s, int pre, int post) {
-  __shared__ double2 buf[ELEMS];
+  __shared__ double2 buf[LDS_PADDED(ELEMS)];
   const FftWork wk = work[blockIdx.x];
   const int P = n_arr[wk.inst], log2P = ilog2(P);
   int nl = ELEMS / P;
@@ -289,14 +327,14 @@ k_fft_c2c_t(const int* __restrict__ n_arr, const int64_t* __restrict__ offs, con
     const TIn v = in[q];
     double2 d = make_double2((double)v.x, (double)v.y);
     if (pre && (((q >> log2P) + wk.first + (q & (P - 1))) & 1)) { d.x = -d.x; d.y = -d.y; }
-    buf[q] = d;
+    buf[pd(q)] = d;
   }
   __syncthreads();
   lds_fft<ELEMS, THREADS>(buf, log2P, nl, s, T.twiddle);
   TOut* out = dst + off;
   for (int q = threadIdx.x; q < n; q += THREADS) {
     const int y = q >> log2nl, l = q & (nl - 1);
-    double2 v = buf[(l << log2P) + y];
+    double2 v = buf[pd((l << log2P) + y)];
     const int line = wk.first + l;
     if (post && ((y + line) & 1)) { v.x = -v.x; v.y = -v.y; }
     TOut o;
@@ -306,14 +344,15 @@ k_fft_c2c_t(const int* __restrict__ n_arr, const int64_t* __restrict__ offs, con
   }
 }
 
-// ---- host launchers.  elems selects the LDS block: 4096 complex doubles (64 KB, 256
-// threads) or 8192 (128 KB, 512 threads, needed only for P = 8192).
+// ---- host launchers.  elems selects the LDS block: 4096 complex doubles (72 KB with
+// padding, 512 threads, two workgroups per CU) or 8192 (144 KB, 512 threads, needed only
+// for P = 8192).
 #define MI_FFT_DISPATCH(KERNEL, ...)                                                              \
   do {                                                                                            \
     if (elems == 8192)                                                                            \
       hipLaunchKernelGGL((KERNEL<8192, 512>), dim3(n_work), dim3(512), 0, st, __VA_ARGS__);       \
     else                                                                                          \
-      hipLaunchKernelGGL((KERNEL<4096, 256>), dim3(n_work), dim3(256), 0, st, __VA_ARGS__);       \
+      hipLaunchKernelGGL((KERNEL<4096, 512>), dim3(n_work), dim3(512), 0, st, __VA_ARGS__);       \
   } while (0)
 
 hipError_t launch_fft_a(int elems, const InstDesc* inst, const FftWork* work, int n_work, int beam, double2* grid,
@@ -348,7 +387,7 @@ hipError_t launch_fft_c2c_t_f2d(int elems, const int* n_arr, const int64_t* offs
     hipLaunchKernelGGL((k_fft_c2c_t<8192, 512, float2, double2>), dim3(n_work), dim3(512), 0, st, n_arr, offs, work,
                        src, dst, T, s, pre, post);
   else
-    hipLaunchKernelGGL((k_fft_c2c_t<4096, 256, float2, double2>), dim3(n_work), dim3(256), 0, st, n_arr, offs, work,
+    hipLaunchKernelGGL((k_fft_c2c_t<4096, 512, float2, double2>), dim3(n_work), dim3(512), 0, st, n_arr, offs, work,
                        src, dst, T, s, pre, post);
   return hipGetLastError();
 }
@@ -360,7 +399,7 @@ hipError_t launch_fft_c2c_t_d2f(int elems, const int* n_arr, const int64_t* offs
     hipLaunchKernelGGL((k_fft_c2c_t<8192, 512, double2, float2>), dim3(n_work), dim3(512), 0, st, n_arr, offs, work,
                        src, dst, T, s, pre, post);
   else
-    hipLaunchKernelGGL((k_fft_c2c_t<4096, 256, double2, float2>), dim3(n_work), dim3(256), 0, st, n_arr, offs, work,
+    hipLaunchKernelGGL((k_fft_c2c_t<4096, 512, double2, float2>), dim3(n_work), dim3(512), 0, st, n_arr, offs, work,
                        src, dst, T, s, pre, post);
   return hipGetLastError();
 }

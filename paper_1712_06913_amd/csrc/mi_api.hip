@@ -60,6 +60,11 @@ int fft_lines_per_block_host(int P, int elems) {
   int nl = elems / P;
   return nl > P / 2 ? P / 2 : nl;
 }
+// Image rows per workgroup of the real-valued passes (two rows per complex line).
+int fft_rows_per_block_host(int P, int elems) {
+  int ny = 2 * elems / P;
+  return ny > P ? P : ny;
+}
 
 // --------------------------------------------------------------------------------------
 struct DevBuf {
@@ -116,7 +121,7 @@ struct CleanPlan {
   std::vector<int32_t> niter;
   std::vector<float> thr;
   bool has_thr = false;
-  int G = 0, T = 0, xcd_map = 0, n_blocks = 0, ppt = 0, team_req = 0;
+  int G = 0, T = 0, xcd_map = 0, n_blocks = 0, ppt = 0, team_req = 0, sub_px = 0;
   size_t lds = 0;        // restore staging: the largest chunk in floats
   int64_t total_comp = 0;
   DevBuf team_off, team_imgs, niter_d, thr_d, comp_off, slots, bar, comp_idx, comp_flux, cbeam, rrad;
@@ -255,10 +260,11 @@ Plan* get_plan(mi_ctx* ctx, const mi_batch* b) {
     for (int t = 0; t < ntd; ++t) tile_inst_d.push_back(i);
     for (int t = 0; t < ntb; ++t) tile_inst_b.push_back(i);
     const int nld = fft_lines_per_block_host(N, P->elems_d), nlb = fft_lines_per_block_host(2 * N, P->elems_b);
+    const int nyd = fft_rows_per_block_host(N, P->elems_d), nyb = fft_rows_per_block_host(2 * N, P->elems_b);
     for (int l = 0; l < N / 2; l += nld) wa_d.push_back({i, l});
-    for (int y = 0; y < N; y += nld) wb_d.push_back({i, y});
+    for (int y = 0; y < N; y += nyd) wb_d.push_back({i, y});
     for (int l = 0; l < N; l += nlb) wa_b.push_back({i, l});
-    for (int y = 0; y < 2 * N; y += nlb) wb_b.push_back({i, y});
+    for (int y = 0; y < 2 * N; y += nyb) wb_b.push_back({i, y});
     P->max_N = std::max(P->max_N, N);
     P->max_nvis = std::max(P->max_nvis, d.n_vis);
   }
@@ -580,7 +586,7 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
       if (prm->niter[i] < 0) fail(MI_ERR_ARG, "niter[%d] < 0", i);
     int G_min = 1, N_min = 1 << 30;
     for (int N : P->n) {
-      G_min = std::max(G_min, (N * N) / 32768);     // at most 32 residual pixels per thread
+      G_min = std::max(G_min, (N * N) / 65536);     // at most 64 residual pixels per thread
       N_min = std::min(N_min, N);
     }
     const int G_cap = std::min(256, N_min);         // a member's chunk must start on a row
@@ -608,9 +614,10 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
       C->niter.assign(prm->niter, prm->niter + n);
       C->has_thr = has_thr;
       if (has_thr) C->thr.assign(prm->threshold, prm->threshold + n);
-      // Team size: enough workgroups that the largest residual fits in registers (32 pixels
-      // per thread); with many images, small teams on one XCD each (the barrier then stays
-      // in that XCD's L2); a single image gets up to 32 workgroups of one XCD.
+      // Team size: enough workgroups that the largest residual fits in registers (64 pixels
+      // per thread); with many images, the smallest such teams, several per XCD, so one
+      // team's exchange overlaps another's beam traffic; a single image gets up to 32
+      // workgroups of one XCD.
       int G;
       if (req) {
         G = std::min(std::max(req, G_min), G_cap);
@@ -622,7 +629,8 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
       int ppt = 4;                                  // 4-pixel groups per 16-byte load
       while (ppt * 1024 * G < P->max_N * P->max_N) ppt *= 2;
       int per_cu = 0;
-      const size_t lds = (size_t)(P->max_N * P->max_N / G) * sizeof(float);
+      const int sub_px = std::min(P->max_N * P->max_N / G, CLEAN_RESTORE_SUB_PX);
+      const size_t lds = (size_t)sub_px * sizeof(float);
       HIPCHK(clean_max_blocks_per_cu(ppt, local, lds, &per_cu));
       if (per_cu < 1) fail(MI_ERR_UNSUPPORTED, "CLEAN kernel cannot be resident");
       const int cap = per_cu * ctx->n_cu;
@@ -641,6 +649,7 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
       C->xcd_map = local ? 1 : 0;
       C->n_blocks = T * G;
       C->lds = lds;
+      C->sub_px = sub_px;
       // LPT: images sorted by N^2 * niter, each to the least-loaded team
       std::vector<int> order(n);
       for (int i = 0; i < n; ++i) order[i] = i;
@@ -694,6 +703,7 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
     A.team_imgs = static_cast<const int*>(C->team_imgs.p);
     A.G = C->G;
     A.xcd_map = C->xcd_map;
+    A.sub_px = C->sub_px;
     A.dirty = dirty;
     A.beam = beam;
     A.niter = static_cast<const int*>(C->niter_d.p);

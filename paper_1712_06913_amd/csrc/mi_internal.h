@@ -26,6 +26,7 @@ constexpr int ENT_PER_VIS = 8;
 // FFT kernels stage 4096 complex doubles in LDS per workgroup (8192 for P = 8192).
 constexpr int FFT_ELEMS_SMALL = 4096;
 constexpr int FFT_ELEMS_LARGE = 8192;
+constexpr int CLEAN_RESTORE_SUB_PX = 32768;   // restore staging: 128 KB of LDS
 
 // Per-instance descriptor, built on the host when a plan is created.
 struct InstDesc {
@@ -80,6 +81,7 @@ struct CleanArgs {
   double* comp_flux;
   int* ncomp;              // may be null
   float* restored;         // may be null
+  int sub_px;              // restore: residual pixels staged in LDS per pass (power of two)
   unsigned long long* slots;  // per team: 2 x G keys
   unsigned* bar;           // per team barrier counter (zero at launch)
   int* status;             // may be null

@@ -26,7 +26,7 @@ def shape_key(batch: api.Batch, niter) -> Tuple:
 
 def team_candidates(batch: api.Batch):
     n_max, n_min = int(batch.n_img.max()), int(batch.n_img.min())
-    g_min = max(1, n_max * n_max // 32768)
+    g_min = max(1, n_max * n_max // 65536)
     g_cap = min(256, n_min)
     out, g = [0], g_min
     while g <= g_cap:

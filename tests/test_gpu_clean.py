@@ -26,21 +26,21 @@ def _inputs(wl):
     return dirty, beams
 
 
-def _run(wl, niter, gain=0.1, threshold=None, positive_only=False, restore=True):
+def _run(wl, niter, gain=0.1, threshold=None, positive_only=False, restore=True, team_size=0, inputs=None):
     require_gpu()
     from paper_1712_06913_amd import api
-    dirty, beams = _inputs(wl)
+    dirty, beams = inputs if inputs is not None else _inputs(wl)
     b = api.Batch.from_workload(wl)
     d_t = torch.from_numpy(np.concatenate([x.ravel() for x in dirty])).cuda()
     b_t = torch.from_numpy(np.concatenate([x.ravel() for x in beams])).cuda()
     res = api.hogbom_clean(b, d_t, b_t, niter, gain=gain, threshold=threshold, positive_only=positive_only,
-                           restore=restore)
+                           restore=restore, team_size=team_size)
     torch.cuda.synchronize()
     return b, dirty, beams, res
 
 
-def _check(wl, niter, gain=0.1, threshold=None, positive_only=False, exact=False):
-    b, dirty, beams, res = _run(wl, niter, gain, threshold, positive_only)
+def _check(wl, niter, gain=0.1, threshold=None, positive_only=False, exact=False, team_size=0, inputs=None):
+    b, dirty, beams, res = _run(wl, niter, gain, threshold, positive_only, team_size=team_size, inputs=inputs)
     resid = b.split(res["residual"])
     model = b.split(res["model"])
     restored = b.split(res["restored"])
@@ -124,3 +124,20 @@ def test_clean_c2_slice_512():
     log("[clean] C2 slice: 2 instances at 512^2, 300 iterations")
     wl = synth.c2_muser1_batch(n_chan=2, n_snap=1)
     _check(wl, np.array([300, 300], np.int32))
+
+
+def test_clean_1024_team_sizes_agree_and_replay():
+    log("[clean] 1024^2: teams of 16 (64 px/thread, restore staged in two parts) and 32")
+    wl = synth.c3_muser2(chans=[7], niter=150)
+    inputs = _inputs(wl)
+    niter = np.array([150], np.int32)
+    _check(wl, niter, team_size=16, inputs=inputs)
+    outs = []
+    for ts in (16, 32):
+        _, _, _, res = _run(wl, niter, team_size=ts, inputs=inputs)
+        outs.append({k: (v.cpu().numpy() if torch.is_tensor(v) else v) for k, v in res.items()})
+    a, c = outs
+    assert np.array_equal(a["n_comp"], c["n_comp"]) and np.array_equal(a["comp_idx"], c["comp_idx"])
+    # the same fma sequence per pixel whatever the team shape: bit-identical residuals
+    assert np.array_equal(a["residual"], c["residual"])
+    assert np.max(np.abs(a["restored"] - c["restored"])) <= 1e-6 * np.max(np.abs(inputs[0][0]))
