@@ -21,6 +21,8 @@
 // main lobe (4-connected region around (N, N) with beam > 0.35) by FP64 least squares on
 // ln(beam); k_clean then adds each component times that Gaussian (truncated where it
 // drops below 1e-12) to its LDS chunk after the loop, and writes the restored image.
+#include <algorithm>
+
 #include "mi_internal.h"
 
 namespace mi {
@@ -163,6 +165,38 @@ __device__ __forceinline__ void team_exchange(unsigned long long* slots, int G, 
   if (lane == 0) *out = timed_out ? ~0ull : k;
 }
 
+// Window subtraction R -= f beam[window].  Group g of a thread covers 4 pixels of one row;
+// groups g < K read the point-mirrored beam row (highest address first, so the 16-byte
+// load's components come reversed), the others the direct row.  Offsets live in the VGPR
+// operand, which the buffer range check covers: a group past the image's range reads
+// zeros.  A scheduling barrier between batches keeps at most LB loads in flight, which
+// bounds the registers next to the PPT residual values.
+template <int NS, int LB>
+__device__ __forceinline__ void sub_window(float* R, __amdgpu_buffer_rsrc_t rs, unsigned vd, unsigned vm, int K,
+                                           float f) {
+  constexpr unsigned GSTEP = 2u * 4u * CL_THREADS * 4u;   // bytes between load steps (2 STEP floats)
+#pragma unroll
+  for (int s0 = 0; s0 < NS; s0 += LB) {
+    float4 bv[LB];
+#pragma unroll
+    for (int s = 0; s < LB; ++s) {
+      const int g = s0 + s;
+      const unsigned vo = g < K ? vm - GSTEP * g : vd + GSTEP * g;
+      bv[s] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)vo, 0, 0));
+    }
+#pragma unroll
+    for (int s = 0; s < LB; ++s) {
+      const int g = s0 + s;
+      const bool m = g < K;
+      R[4 * g + 0] = fmaf(-f, m ? bv[s].w : bv[s].x, R[4 * g + 0]);
+      R[4 * g + 1] = fmaf(-f, m ? bv[s].z : bv[s].y, R[4 * g + 1]);
+      R[4 * g + 2] = fmaf(-f, m ? bv[s].y : bv[s].z, R[4 * g + 2]);
+      R[4 * g + 3] = fmaf(-f, m ? bv[s].x : bv[s].w, R[4 * g + 3]);
+    }
+    if (s0 + LB < NS) __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 }  // namespace
 
 // Residual in registers: thread t of member m owns 4-pixel groups at
@@ -229,6 +263,14 @@ k_clean(CleanArgs A) {
     const float thr = A.thr ? A.thr[img] : 0.0f;
     const int64_t coff = A.comp_off[img];
     const float* bimg = A.beam + d.beam_off;
+    // one resource over this image's beam; offsets are bytes from its first pixel
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(bimg), 0,
+                                                                        16 * N * N, BUFFER_RSRC_WORD3);
+    // mirrored reads need the beam exactly symmetric and each wave's 256 pixels of a load
+    // step inside one row (N >= 256), so the choice is uniform per wave and step
+    const bool sym = N >= 256 && A.asym[img] == 0;
+    const int yw = row0 + __builtin_amdgcn_readfirstlane(t4 >> log2N);   // this wave's row at step 0
+    const int RS = STEP >> log2N, log2RS = 12 - log2N;   // rows per load step (STEP = 2^12)
     float f = 0.0f;                                   // pending pick (none yet)
     int py = N / 2, px = N / 2;
     int it = 0;
@@ -237,26 +279,17 @@ k_clean(CleanArgs A) {
       // apply the pending pick and find the local peak.  Pixels a thread does not own hold
       // NaN (fma keeps NaN, fmaxf ignores it); their loads either stay inside this image's
       // beam or lie past the resource's range, which returns zero.
-      const int64_t win0 = (int64_t)(N - py + row0) * twoN + (N - px);
-      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-          const_cast<float*>(bimg + win0), 0, (int)((4LL * N * N - win0) * 4), BUFFER_RSRC_WORD3);
+      // group s of this thread: row y = yw + s RS (+ lane row for N < 256), column x.
+      // Direct: beam[y - py + N][x - px + N ..]; mirrored (rows y < py of a symmetric beam):
+      // beam[N + py - y][N + px - x - 3 ..] read as one 16-byte load, components reversed.
+      const unsigned vd = (unsigned)(((N - py + row0) * twoN + (N - px)) * 4) + vtb;
+      const unsigned vm = (unsigned)(((N + py - row0) * twoN + (N + px - 3)) * 4) - vtb;
+      // groups s < K lie in rows y < py: uniform per wave (one row per wave and step)
+      int K = 0;
+      if (sym && py > yw) K = min(NS, (py - yw + RS - 1) >> log2RS);
+      K = __builtin_amdgcn_readfirstlane(K);
+      sub_window<NS, LB>(R, rs, vd, vm, K, f);
       float best = posonly ? -INFINITY : -1.0f;
-      // loads in batches of at most 8 x 16 bytes, so PPT = 64 stays within 128 VGPRs
-#pragma unroll
-      for (int s0 = 0; s0 < NS; s0 += LB) {
-        float4 bv[LB];
-#pragma unroll
-        for (int s = 0; s < LB; ++s)
-          bv[s] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(
-                                                 rs, (int)vtb, 2 * STEP * 4 * (s0 + s), 0));
-#pragma unroll
-        for (int s = 0; s < LB; ++s) {
-          R[4 * (s0 + s) + 0] = fmaf(-f, bv[s].x, R[4 * (s0 + s) + 0]);
-          R[4 * (s0 + s) + 1] = fmaf(-f, bv[s].y, R[4 * (s0 + s) + 1]);
-          R[4 * (s0 + s) + 2] = fmaf(-f, bv[s].z, R[4 * (s0 + s) + 2]);
-          R[4 * (s0 + s) + 3] = fmaf(-f, bv[s].w, R[4 * (s0 + s) + 3]);
-        }
-      }
       if (posonly) {
 #pragma unroll
         for (int k = 0; k < PPT; ++k) best = fmaxf(best, R[k]);
@@ -400,6 +433,40 @@ k_clean(CleanArgs A) {
       }
     }
   }
+}
+
+// The beam of Hermitian-completed visibilities is point-symmetric about (N, N):
+// B[N + a][N + b] = B[N - a][N - b].  k_beam_symmetrize makes that exact in float32 by
+// copying the half a < 0 (and a = 0, b < 0) onto its mirror; k_beam_symcheck flags
+// instances whose beam is not exactly symmetric over the rows and columns 1..2N-1 that
+// CLEAN windows read.  Both cover, per instance, the mirror pixels (r, c) with r > N, or
+// r = N and c > N, and 1 <= c <= 2N-1.
+__global__ void __launch_bounds__(256)
+k_beam_symmetrize(const InstDesc* __restrict__ inst, float* __restrict__ beam) {
+  const InstDesc d = inst[blockIdx.y];
+  const int N = d.N, twoN = 2 * N;
+  float* B = beam + d.beam_off;
+  const int64_t npair = (int64_t)N * twoN;                 // rows N..2N-1, columns 0..2N-1
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < npair; q += (int64_t)gridDim.x * 256) {
+    const int r = N + (int)(q / twoN), c = (int)(q % twoN);
+    if (c == 0 || (r == N && c <= N)) continue;
+    B[(int64_t)r * twoN + c] = B[(int64_t)(twoN - r) * twoN + (twoN - c)];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_beam_symcheck(const InstDesc* __restrict__ inst, const float* __restrict__ beam, int* __restrict__ asym) {
+  const InstDesc d = inst[blockIdx.y];
+  const int N = d.N, twoN = 2 * N;
+  const unsigned* B = reinterpret_cast<const unsigned*>(beam + d.beam_off);
+  const int64_t npair = (int64_t)N * twoN;
+  bool bad = false;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < npair; q += (int64_t)gridDim.x * 256) {
+    const int r = N + (int)(q / twoN), c = (int)(q % twoN);
+    if (c == 0 || (r == N && c <= N)) continue;
+    bad |= B[(int64_t)r * twoN + c] != B[(int64_t)(twoN - r) * twoN + (twoN - c)];
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&asym[blockIdx.y], 1);
 }
 
 // Clean-beam fit: one workgroup per instance.
@@ -605,6 +672,21 @@ hipError_t launch_clean(const CleanArgs& A, int ppt, bool local, int n_blocks, s
 hipError_t launch_beamfit(const InstDesc* inst, int n_inst, const float* beam, double* cbeam, int* rrad,
                           int* status, hipStream_t st) {
   hipLaunchKernelGGL(k_beamfit, dim3(n_inst), dim3(CL_THREADS), 0, st, inst, beam, cbeam, rrad, status);
+  return hipGetLastError();
+}
+
+static int sym_blocks(int max_N) { return std::max(1, std::min(256, max_N * max_N / 4096)); }
+
+hipError_t launch_beam_symmetrize(const InstDesc* inst, int n_inst, int max_N, float* beam, hipStream_t st) {
+  if (n_inst <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_beam_symmetrize, dim3(sym_blocks(max_N), n_inst), dim3(256), 0, st, inst, beam);
+  return hipGetLastError();
+}
+
+hipError_t launch_beam_symcheck(const InstDesc* inst, int n_inst, int max_N, const float* beam, int* asym,
+                                hipStream_t st) {
+  if (n_inst <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_beam_symcheck, dim3(sym_blocks(max_N), n_inst), dim3(256), 0, st, inst, beam, asym);
   return hipGetLastError();
 }
 

@@ -50,6 +50,8 @@ hipError_t launch_fft_c2c_t_d2f(int, const int*, const int64_t*, const FftWork*,
 hipError_t clean_max_blocks_per_cu(int ppt, bool local, size_t lds, int* nb);
 hipError_t launch_clean(const CleanArgs&, int ppt, bool local, int n_blocks, size_t lds, hipStream_t);
 hipError_t launch_beamfit(const InstDesc*, int, const float*, double*, int*, int*, hipStream_t);
+hipError_t launch_beam_symcheck(const InstDesc*, int, int, const float*, int*, hipStream_t);
+hipError_t launch_beam_symmetrize(const InstDesc*, int, int, float*, hipStream_t);
 hipError_t launch_degrid(const InstDesc*, int, int, const float2*, const float*, const float*, const double*,
                          const double2*, const Tables&, int, float2*, hipStream_t);
 
@@ -124,7 +126,7 @@ struct CleanPlan {
   int G = 0, T = 0, xcd_map = 0, n_blocks = 0, ppt = 0, team_req = 0, sub_px = 0;
   size_t lds = 0;        // restore staging: the largest chunk in floats
   int64_t total_comp = 0;
-  DevBuf team_off, team_imgs, niter_d, thr_d, comp_off, slots, bar, comp_idx, comp_flux, cbeam, rrad;
+  DevBuf team_off, team_imgs, niter_d, thr_d, comp_off, slots, asym, comp_idx, comp_flux, cbeam, rrad;
 };
 
 struct Plan {
@@ -338,6 +340,7 @@ void run_image(mi_ctx* ctx, Plan* P, bool beam, float* out, hipStream_t st) {
     HIPCHK(launch_fft_a(P->elems_b, inst, static_cast<const FftWork*>(P->wa_b.p), P->n_wa_b, 1, g, ctx->T, st));
     HIPCHK(launch_fft_b_c2r(P->elems_b, inst, static_cast<const FftWork*>(P->wb_b.p), P->n_wb_b, 1, g, b0, ctx->T,
                             out, st));
+    HIPCHK(launch_beam_symmetrize(inst, P->n_inst, P->max_N, out, st));
   }
 }
 
@@ -678,7 +681,6 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
       if (has_thr) upload(C->thr_d, C->thr);
       upload(C->comp_off, coff);
       dev_alloc<unsigned long long>(C->slots, (size_t)T * 2 * G);
-      dev_alloc<unsigned>(C->bar, T);
       P->cleans[h] = std::move(up);
     }
     int* status = batch->status;
@@ -697,6 +699,10 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
       cflx = dev_alloc<double>(C->comp_flux, (size_t)std::max<int64_t>(C->total_comp, 1));
     }
     HIPCHK(launch_fill_u32(static_cast<unsigned*>(C->slots.p), (int64_t)C->T * 2 * C->G * 2, 0u, stream));
+    // beams that are exactly point-symmetric let CLEAN read half its window mirrored
+    int* asym = dev_alloc<int>(C->asym, n);
+    HIPCHK(launch_fill_u32(reinterpret_cast<unsigned*>(asym), n, 0u, stream));
+    HIPCHK(launch_beam_symcheck(static_cast<const InstDesc*>(P->inst.p), n, P->max_N, beam, asym, stream));
     CleanArgs A{};
     A.inst = static_cast<const InstDesc*>(P->inst.p);
     A.team_off = static_cast<const int*>(C->team_off.p);
@@ -720,7 +726,7 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
     A.ncomp = n_comp_out;
     A.restored = restored_out;
     A.slots = static_cast<unsigned long long*>(C->slots.p);
-    A.bar = static_cast<unsigned*>(C->bar.p);
+    A.asym = asym;
     A.status = status;
     HIPCHK(launch_clean(A, C->ppt, C->xcd_map != 0, C->n_blocks, C->lds, stream));
   });

@@ -83,7 +83,7 @@ struct CleanArgs {
   float* restored;         // may be null
   int sub_px;              // restore: residual pixels staged in LDS per pass (power of two)
   unsigned long long* slots;  // per team: 2 x G keys
-  unsigned* bar;           // per team barrier counter (zero at launch)
+  const int* asym;         // per instance: nonzero unless the beam is exactly point-symmetric
   int* status;             // may be null
 };
 

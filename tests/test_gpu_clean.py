@@ -126,18 +126,33 @@ def test_clean_c2_slice_512():
     _check(wl, np.array([300, 300], np.int32))
 
 
+def _symmetrized(B):
+    """Copy the half with rows < N (and row N, columns < N) onto its point mirror about (N, N)."""
+    n2 = B.shape[0]
+    N = n2 // 2
+    S = B.copy()
+    S[N + 1:, 1:] = B[N - 1:0:-1, n2 - 1:0:-1]
+    S[N, N + 1:] = B[N, N - 1:0:-1]
+    return S
+
+
 def test_clean_1024_team_sizes_agree_and_replay():
-    log("[clean] 1024^2: teams of 16 (64 px/thread, restore staged in two parts) and 32")
+    log("[clean] 1024^2: teams of 16 (64 px/thread, restore staged in two parts) and 32; "
+        "mirrored beam reads for an exactly symmetric beam, direct reads otherwise")
     wl = synth.c3_muser2(chans=[7], niter=150)
-    inputs = _inputs(wl)
+    dirty, beams = _inputs(wl)
+    sym = [_symmetrized(beams[0])]
+    asym = [sym[0].copy()]
+    asym[0][1, 1] += 1e-3                      # one pixel breaks the symmetry: direct reads
     niter = np.array([150], np.int32)
-    _check(wl, niter, team_size=16, inputs=inputs)
+    for bm in (sym, asym):
+        _check(wl, niter, team_size=16, inputs=(dirty, bm))
     outs = []
     for ts in (16, 32):
-        _, _, _, res = _run(wl, niter, team_size=ts, inputs=inputs)
+        _, _, _, res = _run(wl, niter, team_size=ts, inputs=(dirty, sym))
         outs.append({k: (v.cpu().numpy() if torch.is_tensor(v) else v) for k, v in res.items()})
     a, c = outs
     assert np.array_equal(a["n_comp"], c["n_comp"]) and np.array_equal(a["comp_idx"], c["comp_idx"])
     # the same fma sequence per pixel whatever the team shape: bit-identical residuals
     assert np.array_equal(a["residual"], c["residual"])
-    assert np.max(np.abs(a["restored"] - c["restored"])) <= 1e-6 * np.max(np.abs(inputs[0][0]))
+    assert np.max(np.abs(a["restored"] - c["restored"])) <= 1e-6 * np.max(np.abs(dirty[0]))

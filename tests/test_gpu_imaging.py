@@ -123,3 +123,17 @@ def test_ifft2_matches_centred_dft():
         ref = imager.ifft2_centred(a.astype(np.complex64).astype(np.complex128))
         got = out[o: o + P * P].reshape(P, P)
         assert np.max(np.abs(got - ref)) <= 2e-6 * np.max(np.abs(ref)) * np.log2(P)
+
+
+def test_beam_is_exactly_point_symmetric():
+    log("[imaging] library beams are bitwise point-symmetric about (N, N)")
+    require_gpu()
+    from paper_1712_06913_amd import api
+    wl = synth.random_instances(31, [64, 256, 512], m_range=(150, 400))
+    b = api.Batch.from_workload(wl)
+    vis, uv, w = api.workload_tensors(wl)
+    beams = b.split(api.dirty_beam(b, uv, w), beam=True)
+    for i in range(wl.n_inst):
+        N = int(wl.n_img[i])
+        B = beams[i].cpu().numpy().view(np.uint32).reshape(2 * N, 2 * N)
+        assert np.array_equal(B[1:, 1:], B[:0:-1, :0:-1]), f"instance {i} (N={N})"
