@@ -177,6 +177,18 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
 mi_status mi_degrid(mi_ctx* ctx, const mi_batch* batch, const float* image, const float* uv,
                     const float* w_in, int adjoint, mi_c64* vis_out, hipStream_t stream);
 
+/* ---- kernel timing (measurement hook, not part of the imaging path) ----------------
+ * mi_profile_begin: from now on, every mi_hogbom_clean call records a pair of HIP events
+ *   on its stream around its Hogbom kernel launch (the beam fit, symmetry check and fills
+ *   before it are outside the pair).  Do not enable it while a stream is being captured
+ *   into a graph.  Clears earlier records.
+ * mi_profile_end: waits for the recorded events, writes up to `cap` kernel durations in
+ *   milliseconds (oldest first) to the host array ms_out, the number recorded to *n_out
+ *   (may exceed cap), and stops recording.  MI_ERR_ARG for a NULL ms_out with cap > 0 or a
+ *   NULL n_out.                                                                      */
+mi_status mi_profile_begin(mi_ctx* ctx);
+mi_status mi_profile_end(mi_ctx* ctx, float* ms_out, int32_t cap, int32_t* n_out);
+
 #ifdef __cplusplus
 }
 #endif

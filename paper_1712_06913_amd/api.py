@@ -172,3 +172,18 @@ def degrid(batch: Batch, image, uv, w, adjoint: bool = False, out=None):
     nat.check(batch.ctx, nat.lib().mi_degrid(batch.ctx, batch.c, _ptr(image), _ptr(uv), _ptr(w),
                                              1 if adjoint else 0, _ptr(out), _stream(dev)))
     return out
+
+
+def profile_begin(device: int = 0):
+    """mi_profile_begin: record HIP events around every following Hogbom kernel launch."""
+    ctx = context(device)
+    nat.check(ctx, nat.lib().mi_profile_begin(ctx))
+
+
+def profile_end(device: int = 0, cap: int = 1024):
+    """mi_profile_end: the recorded Hogbom kernel durations in milliseconds (oldest first)."""
+    ctx = context(device)
+    buf = (ctypes.c_float * cap)()
+    n = ctypes.c_int32()
+    nat.check(ctx, nat.lib().mi_profile_end(ctx, buf, cap, ctypes.byref(n)))
+    return [float(buf[i]) for i in range(min(n.value, cap))]

@@ -171,6 +171,16 @@ struct mi_ctx {
   mi::DevBuf ifft_scratch;
   int fail_inst = -1;
   int n_cu = 256;
+  // kernel timing: event pairs around Hogbom launches while profiling is on
+  bool profiling = false;
+  size_t prof_used = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
+  ~mi_ctx() {
+    for (auto& e : prof_ev) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+  }
 };
 
 namespace mi {
@@ -425,6 +435,31 @@ mi_status mi_ctx_destroy(mi_ctx* ctx) {
   (void)hipDeviceSynchronize();
   delete ctx;
   return MI_OK;
+}
+
+mi_status mi_profile_begin(mi_ctx* ctx) {
+  return guard(ctx, [&] {
+    ctx->profiling = true;
+    ctx->prof_used = 0;
+  });
+}
+
+mi_status mi_profile_end(mi_ctx* ctx, float* ms_out, int32_t cap, int32_t* n_out) {
+  return guard(ctx, [&] {
+    need(n_out, "n_out");
+    if (cap > 0) need(ms_out, "ms_out");
+    HIPCHK(hipSetDevice(ctx->device));
+    const size_t n = ctx->prof_used;
+    for (size_t i = 0; i < n && (int64_t)i < cap; ++i) {
+      HIPCHK(hipEventSynchronize(ctx->prof_ev[i].second));
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, ctx->prof_ev[i].first, ctx->prof_ev[i].second));
+      ms_out[i] = ms;
+    }
+    *n_out = (int32_t)n;
+    ctx->profiling = false;
+    ctx->prof_used = 0;
+  });
 }
 
 mi_status mi_grid(mi_ctx* ctx, const mi_batch* batch, const mi_c64* vis, const float* uv, const float* w_in,
@@ -728,7 +763,21 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
     A.slots = static_cast<unsigned long long*>(C->slots.p);
     A.asym = asym;
     A.status = status;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->profiling) {
+      if (ctx->prof_used == ctx->prof_ev.size()) {
+        std::pair<hipEvent_t, hipEvent_t> e{};
+        HIPCHK(hipEventCreate(&e.first));
+        HIPCHK(hipEventCreate(&e.second));
+        ctx->prof_ev.push_back(e);
+      }
+      e0 = ctx->prof_ev[ctx->prof_used].first;
+      e1 = ctx->prof_ev[ctx->prof_used].second;
+      ++ctx->prof_used;
+      HIPCHK(hipEventRecord(e0, stream));
+    }
     HIPCHK(launch_clean(A, C->ppt, C->xcd_map != 0, C->n_blocks, C->lds, stream));
+    if (e1) HIPCHK(hipEventRecord(e1, stream));
   });
 }
 

@@ -156,3 +156,17 @@ def test_clean_1024_team_sizes_agree_and_replay():
     # the same fma sequence per pixel whatever the team shape: bit-identical residuals
     assert np.array_equal(a["residual"], c["residual"])
     assert np.max(np.abs(a["restored"] - c["restored"])) <= 1e-6 * np.max(np.abs(dirty[0]))
+
+
+def test_profile_hook_times_each_hogbom_launch():
+    log("[clean] mi_profile_begin / mi_profile_end record one duration per Hogbom launch")
+    require_gpu()
+    from paper_1712_06913_amd import api
+    wl = synth.random_instances(24, [128, 64], m_range=(100, 200))
+    inputs = _inputs(wl)
+    api.profile_begin()
+    for _ in range(3):
+        _run(wl, np.array([40, 40], np.int32), inputs=inputs, restore=False)
+    ms = api.profile_end()
+    assert len(ms) == 3 and all(t > 0.0 for t in ms), ms
+    assert api.profile_end() == []            # recording stopped and cleared
