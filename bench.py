@@ -219,6 +219,15 @@ def main():
     torch.cuda.synchronize()
     grid_ms = ge[0].elapsed_time(ge[1]) / reps
 
+    # sky / disk levels of the dirty maps (histogram + mixture fit; not part of the step)
+    levels, mu_a, _ = api.gmm_levels(b, dirty)
+    ge[0].record(stream)
+    for _ in range(reps):
+        api.gmm_levels(b, dirty, levels=levels.view(-1), mu_a=mu_a)
+    ge[1].record(stream)
+    torch.cuda.synchronize()
+    gmm_ms = ge[0].elapsed_time(ge[1]) / reps
+
     # roofline of the dominant kernel (k_clean): algorithmic bytes = per iteration the
     # beam window (4 N^2 bytes; the residual stays in LDS) plus once per image the dirty
     # map in, residual + restored out (3 x 4 N^2) and the FP64 model out (8 N^2)
@@ -245,7 +254,8 @@ def main():
                    "gain": wl.gain, "weighting": "natural" if not wl.weight_mode.any() else "mixed/uniform",
                    "clean_team_size": args.team_size or "library policy"},
         "stage_ms": {"dirty_image_and_beam": img_ms, "clean_restore": clean_ms, "adjoint": adj_ms,
-                     "gridding_only": grid_ms},
+                     "gridding_only": grid_ms, "gmm_levels": gmm_ms},
+        "gmm_levels_read_GBps": float(np.sum(8.0 * N2)) / (gmm_ms * 1e-3) / 1e9,
         "gridded_vis_per_s": kept / (grid_ms * 1e-3),
         "kept_visibilities": kept,
         "components_total": int(n_comp.sum()),

@@ -94,6 +94,8 @@ typedef struct {
   int32_t team_size;           /* workgroups per image (power of two); 0 = automatic.
                                   Values up to 32 keep an image on one XCD; larger teams
                                   spread one image over several XCDs (the "plain" path) */
+  const float* threshold_dev;  /* device, n_inst, or NULL: thresholds read on the device
+                                  (e.g. mu_a from mi_gmm_levels); overrides `threshold` */
 } mi_clean_params;
 
 /* Create / destroy a context on HIP device `device`.  The context owns plans,
@@ -160,7 +162,7 @@ mi_status mi_dirty_beam(mi_ctx* ctx, const mi_batch* batch, const float* uv,
  *   c dy^2)) in pixels, FWHM major and minor axes (pixels), position angle (radians,
  *   major axis from +x towards +y, in [0, pi)).
  * The whole loop runs inside one persistent launch: each image is owned by a team of
- * workgroups that keeps the residual in LDS.                                          */
+ * workgroups that keeps the residual in registers.                                    */
 mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty,
                           const float* beam, const mi_clean_params* params,
                           float* residual_out, double* model_out, int32_t* comp_idx,
@@ -176,6 +178,22 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
  *   Visibilities that are not kept get 0.                                            */
 mi_status mi_degrid(mi_ctx* ctx, const mi_batch* batch, const float* image, const float* uv,
                     const float* w_in, int adjoint, mi_c64* vis_out, hipStream_t stream);
+
+/* Sky and disk levels of maps (Sec. 4.1): the finite pixel values of each N*N map are put
+ * into n_bins equal ranges between their minimum and maximum (bin = floor((x - lo) /
+ * (hi - lo) * n_bins), last bin closed) and a two-component Gaussian mixture is fitted
+ * to the histogram by n_iter expectation-maximisation steps (FP64; started at the
+ * histogram's median and 90th percentile).  The fainter component is the sky (a), the
+ * other the disk (b); Algorithm 1 cleans while the peak exceeds mu_a.
+ *   images: float32 N*N per instance (e.g. dirty maps from mi_dirty_image).
+ *   levels_out (device): double [n_inst][6] = mu_a, sigma_a, weight_a, mu_b, sigma_b,
+ *   weight_b; a constant map gives (v, 0, 1, v, 0, 0).
+ *   mu_a_out, mu_b_out (device, optional): float [n_inst], ready to pass as
+ *   mi_clean_params.threshold_dev.
+ *   n_bins in [2, 4096] (the paper uses 2000); n_iter in [0, 100000].                */
+mi_status mi_gmm_levels(mi_ctx* ctx, const mi_batch* batch, const float* images, int32_t n_bins,
+                        int32_t n_iter, double* levels_out, float* mu_a_out, float* mu_b_out,
+                        hipStream_t stream);
 
 /* ---- kernel timing (measurement hook, not part of the imaging path) ----------------
  * mi_profile_begin: from now on, every mi_hogbom_clean call records a pair of HIP events

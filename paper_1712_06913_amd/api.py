@@ -136,10 +136,19 @@ def ifft2(data: torch.Tensor, n, offs, device: int = 0):
 def hogbom_clean(batch: Batch, dirty, beam, niter, gain: float = 0.1, threshold=None, positive_only=False,
                  restore: bool = True, want_model: bool = True, want_components: bool = True, team_size: int = 0,
                  out=None):
-    """mi_hogbom_clean; returns a dict of device tensors (reused when `out` is a previous result)."""
+    """mi_hogbom_clean; returns a dict of device tensors (reused when `out` is a previous result).
+
+    `threshold`: None, a host array (one per instance), or a float32 device tensor (read on
+    the device, e.g. the mu_a of gmm_levels)."""
     dev = batch.device
     niter = np.ascontiguousarray(niter, dtype=np.int32)
-    thr = None if threshold is None else np.ascontiguousarray(threshold, dtype=np.float32)
+    thr_dev = None
+    if torch.is_tensor(threshold) and threshold.is_cuda:
+        if threshold.dtype != torch.float32 or threshold.numel() != batch.n_inst:
+            raise ValueError("device thresholds must be float32, one per instance")
+        thr_dev, thr = threshold.contiguous(), None
+    else:
+        thr = None if threshold is None else np.ascontiguousarray(threshold, dtype=np.float32)
     nimg = int(batch.img_off[-1])
     ncomp_total = max(1, int(niter.sum()))
     res = out
@@ -156,7 +165,8 @@ def hogbom_clean(batch: Batch, dirty, beam, niter, gain: float = 0.1, threshold=
         res["cbeam"] = torch.zeros(6 * batch.n_inst, dtype=torch.float64, device=dev) if restore else None
         res["comp_off"] = np.concatenate([[0], np.cumsum(niter.astype(np.int64))])
     prm = nat.MiCleanParams(float(gain), niter.ctypes.data, None if thr is None else thr.ctypes.data,
-                            1 if positive_only else 0, int(team_size))
+                            1 if positive_only else 0, int(team_size),
+                            None if thr_dev is None else thr_dev.data_ptr())
     nat.check(batch.ctx, nat.lib().mi_hogbom_clean(
         batch.ctx, batch.c, _ptr(dirty), _ptr(beam), ctypes.byref(prm), _ptr(res["residual"]), _ptr(res["model"]),
         _ptr(res["comp_idx"]), _ptr(res["comp_flux"]), _ptr(res["n_comp"]), _ptr(res["restored"]),
@@ -172,6 +182,18 @@ def degrid(batch: Batch, image, uv, w, adjoint: bool = False, out=None):
     nat.check(batch.ctx, nat.lib().mi_degrid(batch.ctx, batch.c, _ptr(image), _ptr(uv), _ptr(w),
                                              1 if adjoint else 0, _ptr(out), _stream(dev)))
     return out
+
+
+def gmm_levels(batch: Batch, images, n_bins: int = 2000, n_iter: int = 500, levels=None, mu_a=None, mu_b=None):
+    """mi_gmm_levels: (levels [n_inst, 6] float64, mu_a float32 [n_inst], mu_b float32 [n_inst])."""
+    dev = batch.device
+    n = batch.n_inst
+    levels = torch.empty(6 * n, dtype=torch.float64, device=dev) if levels is None else levels
+    mu_a = torch.empty(n, dtype=torch.float32, device=dev) if mu_a is None else mu_a
+    mu_b = torch.empty(n, dtype=torch.float32, device=dev) if mu_b is None else mu_b
+    nat.check(batch.ctx, nat.lib().mi_gmm_levels(batch.ctx, batch.c, _ptr(images), int(n_bins), int(n_iter),
+                                                 _ptr(levels), _ptr(mu_a), _ptr(mu_b), _stream(dev)))
+    return levels.view(n, 6), mu_a, mu_b
 
 
 def profile_begin(device: int = 0):

@@ -50,6 +50,7 @@ hipError_t launch_fft_c2c_t_d2f(int, const int*, const int64_t*, const FftWork*,
 hipError_t clean_max_blocks_per_cu(int ppt, bool local, size_t lds, int* nb);
 hipError_t launch_clean(const CleanArgs&, int ppt, bool local, int n_blocks, size_t lds, hipStream_t);
 hipError_t launch_beamfit(const InstDesc*, int, const float*, double*, int*, int*, hipStream_t);
+hipError_t launch_gmm(const InstDesc*, int, const float*, int, int, double*, float*, float*, hipStream_t);
 hipError_t launch_beam_symcheck(const InstDesc*, int, int, const float*, int*, hipStream_t);
 hipError_t launch_beam_symmetrize(const InstDesc*, int, int, float*, hipStream_t);
 hipError_t launch_degrid(const InstDesc*, int, int, const float2*, const float*, const float*, const double*,
@@ -123,10 +124,12 @@ struct CleanPlan {
   std::vector<int32_t> niter;
   std::vector<float> thr;
   bool has_thr = false;
-  int G = 0, T = 0, xcd_map = 0, n_blocks = 0, ppt = 0, team_req = 0, sub_px = 0;
-  size_t lds = 0;        // restore staging: the largest chunk in floats
+  int T = 0, local = 1, n_blocks = 0, ppt = 0, team_req = 0, sub_px = 0;
+  int64_t n_slots = 0;
+  size_t lds = 0;        // restore staging: sub_px floats
   int64_t total_comp = 0;
-  DevBuf team_off, team_imgs, niter_d, thr_d, comp_off, slots, asym, comp_idx, comp_flux, cbeam, rrad;
+  DevBuf team_off, team_imgs, blk, team_G, team_slot, niter_d, thr_d, comp_off, slots, asym, comp_idx,
+      comp_flux, cbeam, rrad;
 };
 
 struct Plan {
@@ -354,6 +357,150 @@ void run_image(mi_ctx* ctx, Plan* P, bool beam, float* out, hipStream_t st) {
   }
 }
 
+// CLEAN schedule for one batch.  Every image size N gets its own team size G(N), the
+// smallest that keeps each member's chunk N^2/G within 64 residual pixels per thread (so
+// all members of a mixed batch carry the same load), or the requested team size scaled by
+// (N / N_max)^2.  Teams per size class: one at least, one per image at most; the rest of
+// the device goes to the class with the most CLEAN iterations per team.  Teams of up to
+// 32 workgroups are packed onto XCDs first-fit in decreasing size (exact for power-of-two
+// sizes); images go to the least-loaded team of their class in decreasing niter (LPT).
+void build_clean_schedule(mi_ctx* ctx, Plan* P, CleanPlan* C, int req) {
+  const int n = P->n_inst;
+  std::vector<int> sizes(P->n.begin(), P->n.end());
+  std::sort(sizes.begin(), sizes.end(), std::greater<int>());
+  sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+  const int n_max = sizes[0];
+  struct Cls { int N, G, T, cap; std::vector<int> imgs; double work; };
+  std::vector<Cls> cls;
+  for (int N : sizes) {
+    Cls c{};
+    c.N = N;
+    const int g_min = std::max(1, (N * N) / 65536);
+    c.cap = std::min(256, N);                     // a member's chunk must start on a row
+    if (g_min > c.cap) fail(MI_ERR_UNSUPPORTED, "CLEAN team too large for N = %d", N);
+    int g = g_min;
+    if (req) {
+      const int64_t scaled = std::max<int64_t>(1, (int64_t)req * N * N / ((int64_t)n_max * n_max));
+      g = 1;
+      while ((int64_t)g * 2 <= scaled) g *= 2;
+      g = std::min(std::max(g, g_min), c.cap);
+    }
+    c.G = g;
+    c.work = 0.0;
+    for (int i = 0; i < n; ++i)
+      if (P->n[i] == N) {
+        c.imgs.push_back(i);
+        c.work += (double)C->niter[i] + 1.0;
+      }
+    cls.push_back(c);
+  }
+  // a single size without a request: more workgroups per image when there are few images
+  if (!req && cls.size() == 1) {
+    Cls& c = cls[0];
+    while (c.G * 2 <= std::min(32, c.cap) && (int64_t)c.G * 2 * (int64_t)c.imgs.size() <= 256) c.G *= 2;
+  }
+  bool local = true;
+  int ppt = 4;
+  int64_t max_chunk = 1;
+  for (const Cls& c : cls) {
+    local = local && c.G <= 32;
+    while ((int64_t)ppt * 1024 * c.G < (int64_t)c.N * c.N) ppt *= 2;
+    max_chunk = std::max<int64_t>(max_chunk, (int64_t)c.N * c.N / c.G);
+  }
+  const int sub_px = (int)std::min<int64_t>(max_chunk, CLEAN_RESTORE_SUB_PX);
+  const size_t lds = (size_t)sub_px * sizeof(float);
+  int per_cu = 0;
+  HIPCHK(clean_max_blocks_per_cu(ppt, local, lds, &per_cu));
+  if (per_cu < 1) fail(MI_ERR_UNSUPPORTED, "CLEAN kernel cannot be resident");
+  int cap = per_cu * ctx->n_cu;
+  if (local) cap -= cap % 8;
+  // teams per class
+  int used = 0;
+  for (Cls& c : cls) { c.T = 1; used += c.G; }
+  if (used > cap) fail(MI_ERR_UNSUPPORTED, "CLEAN teams (%d workgroups) exceed the device (%d)", used, cap);
+  for (;;) {
+    int best = -1;
+    double best_load = -1.0;
+    for (int k = 0; k < (int)cls.size(); ++k) {
+      const Cls& c = cls[k];
+      if (c.T >= (int)c.imgs.size() || used + c.G > cap) continue;
+      const double load = c.work / c.T;
+      if (load > best_load) { best_load = load; best = k; }
+    }
+    if (best < 0) break;
+    cls[best].T += 1;
+    used += cls[best].G;
+  }
+  // teams in decreasing size (classes are in decreasing N, hence non-increasing G)
+  std::vector<int> team_G, team_cls;
+  for (int k = 0; k < (int)cls.size(); ++k)
+    for (int t = 0; t < cls[k].T; ++t) { team_G.push_back(cls[k].G); team_cls.push_back(k); }
+  const int T = (int)team_G.size();
+  std::vector<int2> blk;
+  if (local) {
+    const int per_xcd = cap / 8;
+    std::vector<int> fill(8, 0), team_x(T), team_r(T);
+    for (int t = 0; t < T; ++t) {
+      int x = 0;
+      while (x < 8 && fill[x] + team_G[t] > per_xcd) ++x;
+      if (x == 8) fail(MI_ERR_UNSUPPORTED, "CLEAN teams do not fit the XCDs");
+      team_x[t] = x;
+      team_r[t] = fill[x];
+      fill[x] += team_G[t];
+    }
+    const int rows = *std::max_element(fill.begin(), fill.end());
+    blk.assign((size_t)8 * rows, make_int2(-1, 0));
+    for (int t = 0; t < T; ++t)
+      for (int m = 0; m < team_G[t]; ++m) blk[(size_t)team_x[t] + 8 * (team_r[t] + m)] = make_int2(t, m);
+  } else {
+    for (int t = 0; t < T; ++t)
+      for (int m = 0; m < team_G[t]; ++m) blk.push_back(make_int2(t, m));
+  }
+  // LPT within each class
+  std::vector<std::vector<int>> lists(T);
+  int first = 0;
+  for (int k = 0; k < (int)cls.size(); ++k) {
+    std::vector<int> order = cls[k].imgs;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return C->niter[a] > C->niter[b]; });
+    std::vector<double> load(cls[k].T, 0.0);
+    for (int i : order) {
+      const int t = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      lists[first + t].push_back(i);
+      load[t] += (double)C->niter[i] + 1.0;
+    }
+    first += cls[k].T;
+  }
+  std::vector<int> toff(T + 1, 0), timgs;
+  std::vector<int64_t> tslot(T, 0);
+  int64_t ns = 0;
+  for (int t = 0; t < T; ++t) {
+    toff[t + 1] = toff[t] + (int)lists[t].size();
+    timgs.insert(timgs.end(), lists[t].begin(), lists[t].end());
+    tslot[t] = ns;
+    ns += 2 * (int64_t)team_G[t];
+  }
+  std::vector<int64_t> coff(n);
+  int64_t sum = 0;
+  for (int i = 0; i < n; ++i) { coff[i] = sum; sum += C->niter[i]; }
+  C->total_comp = sum;
+  C->T = T;
+  C->local = local ? 1 : 0;
+  C->ppt = ppt;
+  C->n_blocks = (int)blk.size();
+  C->lds = lds;
+  C->sub_px = sub_px;
+  C->n_slots = ns;
+  upload(C->team_off, toff);
+  upload(C->team_imgs, timgs);
+  upload(C->blk, blk);
+  upload(C->team_G, team_G);
+  upload(C->team_slot, tslot);
+  upload(C->niter_d, C->niter);
+  if (C->has_thr) upload(C->thr_d, C->thr);
+  upload(C->comp_off, coff);
+  dev_alloc<unsigned long long>(C->slots, (size_t)ns);
+}
+
 void copy_b0(Plan* P, double* b0_out, hipStream_t st) {
   if (b0_out)
     HIPCHK(hipMemcpyAsync(b0_out, P->b0.p, sizeof(double) * 2 * P->n_inst, hipMemcpyDeviceToDevice, st));
@@ -435,6 +582,20 @@ mi_status mi_ctx_destroy(mi_ctx* ctx) {
   (void)hipDeviceSynchronize();
   delete ctx;
   return MI_OK;
+}
+
+mi_status mi_gmm_levels(mi_ctx* ctx, const mi_batch* batch, const float* images, int32_t n_bins, int32_t n_iter,
+                        double* levels_out, float* mu_a_out, float* mu_b_out, hipStream_t stream) {
+  return guard(ctx, [&] {
+    need(images, "images");
+    need(levels_out, "levels_out");
+    if (n_bins < 2 || n_bins > 4096) fail(MI_ERR_ARG, "n_bins must be in [2, 4096] (got %d)", n_bins);
+    if (n_iter < 0 || n_iter > 100000) fail(MI_ERR_ARG, "n_iter must be in [0, 100000] (got %d)", n_iter);
+    HIPCHK(hipSetDevice(ctx->device));
+    Plan* P = get_plan(ctx, batch);
+    HIPCHK(launch_gmm(static_cast<const InstDesc*>(P->inst.p), P->n_inst, images, n_bins, n_iter, levels_out,
+                      mu_a_out, mu_b_out, stream));
+  });
 }
 
 mi_status mi_profile_begin(mi_ctx* ctx) {
@@ -622,20 +783,13 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
     const int n = P->n_inst;
     for (int i = 0; i < n; ++i)
       if (prm->niter[i] < 0) fail(MI_ERR_ARG, "niter[%d] < 0", i);
-    int G_min = 1, N_min = 1 << 30;
-    for (int N : P->n) {
-      G_min = std::max(G_min, (N * N) / 65536);     // at most 64 residual pixels per thread
-      N_min = std::min(N_min, N);
-    }
-    const int G_cap = std::min(256, N_min);         // a member's chunk must start on a row
     if (P->max_N > 1024) fail(MI_ERR_UNSUPPORTED, "CLEAN supports N <= 1024 (got %d)", P->max_N);
-    if (G_min > G_cap) fail(MI_ERR_UNSUPPORTED, "CLEAN team too large for N = %d", N_min);
     const int req = prm->team_size;
     if (req != 0 && (!is_pow2(req) || req > 256)) fail(MI_ERR_ARG, "team_size must be 0 or a power of two <= 256");
-    // clean plan: team shape, LPT assignment, device copies of niter / thresholds
+    // clean plan: team shapes, XCD packing, LPT assignment, device copies of niter / thresholds
     uint64_t h = fnv1a(prm->niter, sizeof(int32_t) * n);
     h = fnv1a(&req, sizeof req, h);
-    const bool has_thr = prm->threshold != nullptr;
+    const bool has_thr = prm->threshold != nullptr && prm->threshold_dev == nullptr;
     if (has_thr) h = fnv1a(prm->threshold, sizeof(float) * n, h ^ 0x9e3779b97f4a7c15ull);
     CleanPlan* C = nullptr;
     auto it = P->cleans.find(h);
@@ -652,70 +806,7 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
       C->niter.assign(prm->niter, prm->niter + n);
       C->has_thr = has_thr;
       if (has_thr) C->thr.assign(prm->threshold, prm->threshold + n);
-      // Team size: enough workgroups that the largest residual fits in registers (64 pixels
-      // per thread); with many images, the smallest such teams, several per XCD, so one
-      // team's exchange overlaps another's beam traffic; a single image gets up to 32
-      // workgroups of one XCD.
-      int G;
-      if (req) {
-        G = std::min(std::max(req, G_min), G_cap);
-      } else {
-        G = G_min;
-        while (G * 2 <= std::min(32, G_cap) && (int64_t)G * 2 * n <= 256) G *= 2;
-      }
-      const bool local = G <= 32;
-      int ppt = 4;                                  // 4-pixel groups per 16-byte load
-      while (ppt * 1024 * G < P->max_N * P->max_N) ppt *= 2;
-      int per_cu = 0;
-      const int sub_px = std::min(P->max_N * P->max_N / G, CLEAN_RESTORE_SUB_PX);
-      const size_t lds = (size_t)sub_px * sizeof(float);
-      HIPCHK(clean_max_blocks_per_cu(ppt, local, lds, &per_cu));
-      if (per_cu < 1) fail(MI_ERR_UNSUPPORTED, "CLEAN kernel cannot be resident");
-      const int cap = per_cu * ctx->n_cu;
-      if (G > cap) fail(MI_ERR_UNSUPPORTED, "CLEAN team of %d workgroups exceeds the device", G);
-      int T_work = std::min(n, cap / G);
-      int T = T_work;
-      if (local) {
-        const int Tmax = cap / G;                     // a multiple of 8 when G <= 32
-        T = std::min(Tmax, ((T_work + 7) / 8) * 8);
-        if (T % 8) { T -= T % 8; T_work = std::min(T_work, T); }
-        if (T < 8) fail(MI_ERR_UNSUPPORTED, "device too small for XCD-local CLEAN teams");
-      }
-      C->G = G;
-      C->T = T;
-      C->ppt = ppt;
-      C->xcd_map = local ? 1 : 0;
-      C->n_blocks = T * G;
-      C->lds = lds;
-      C->sub_px = sub_px;
-      // LPT: images sorted by N^2 * niter, each to the least-loaded team
-      std::vector<int> order(n);
-      for (int i = 0; i < n; ++i) order[i] = i;
-      std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return (double)P->n[a] * P->n[a] * (C->niter[a] + 1) > (double)P->n[b] * P->n[b] * (C->niter[b] + 1);
-      });
-      std::vector<double> load(T_work, 0.0);
-      std::vector<std::vector<int>> lists(T);
-      for (int i : order) {
-        int t = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        lists[t].push_back(i);
-        load[t] += (double)P->n[i] * P->n[i] * (C->niter[i] + 1);
-      }
-      std::vector<int> toff(T + 1, 0), timgs;
-      for (int t = 0; t < T; ++t) {
-        toff[t + 1] = toff[t] + (int)lists[t].size();
-        timgs.insert(timgs.end(), lists[t].begin(), lists[t].end());
-      }
-      std::vector<int64_t> coff(n);
-      int64_t s = 0;
-      for (int i = 0; i < n; ++i) { coff[i] = s; s += C->niter[i]; }
-      C->total_comp = s;
-      upload(C->team_off, toff);
-      upload(C->team_imgs, timgs);
-      upload(C->niter_d, C->niter);
-      if (has_thr) upload(C->thr_d, C->thr);
-      upload(C->comp_off, coff);
-      dev_alloc<unsigned long long>(C->slots, (size_t)T * 2 * G);
+      build_clean_schedule(ctx, P, C, req);
       P->cleans[h] = std::move(up);
     }
     int* status = batch->status;
@@ -733,7 +824,7 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
       cidx = dev_alloc<int>(C->comp_idx, (size_t)std::max<int64_t>(C->total_comp, 1));
       cflx = dev_alloc<double>(C->comp_flux, (size_t)std::max<int64_t>(C->total_comp, 1));
     }
-    HIPCHK(launch_fill_u32(static_cast<unsigned*>(C->slots.p), (int64_t)C->T * 2 * C->G * 2, 0u, stream));
+    HIPCHK(launch_fill_u32(static_cast<unsigned*>(C->slots.p), C->n_slots * 2, 0u, stream));
     // beams that are exactly point-symmetric let CLEAN read half its window mirrored
     int* asym = dev_alloc<int>(C->asym, n);
     HIPCHK(launch_fill_u32(reinterpret_cast<unsigned*>(asym), n, 0u, stream));
@@ -742,13 +833,14 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
     A.inst = static_cast<const InstDesc*>(P->inst.p);
     A.team_off = static_cast<const int*>(C->team_off.p);
     A.team_imgs = static_cast<const int*>(C->team_imgs.p);
-    A.G = C->G;
-    A.xcd_map = C->xcd_map;
+    A.blk = static_cast<const int2*>(C->blk.p);
+    A.team_G = static_cast<const int*>(C->team_G.p);
+    A.team_slot = static_cast<const int64_t*>(C->team_slot.p);
     A.sub_px = C->sub_px;
     A.dirty = dirty;
     A.beam = beam;
     A.niter = static_cast<const int*>(C->niter_d.p);
-    A.thr = has_thr ? static_cast<const float*>(C->thr_d.p) : nullptr;
+    A.thr = prm->threshold_dev ? prm->threshold_dev : (has_thr ? static_cast<const float*>(C->thr_d.p) : nullptr);
     A.gain = prm->gain;
     A.posonly = prm->positive_only ? 1 : 0;
     A.cbeam = restore ? cbeam : nullptr;
@@ -776,7 +868,7 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
       ++ctx->prof_used;
       HIPCHK(hipEventRecord(e0, stream));
     }
-    HIPCHK(launch_clean(A, C->ppt, C->xcd_map != 0, C->n_blocks, C->lds, stream));
+    HIPCHK(launch_clean(A, C->ppt, C->local != 0, C->n_blocks, C->lds, stream));
     if (e1) HIPCHK(hipEventRecord(e1, stream));
   });
 }

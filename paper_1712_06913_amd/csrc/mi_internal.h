@@ -64,8 +64,9 @@ struct CleanArgs {
   const InstDesc* inst;
   const int* team_off;     // CSR of images per team
   const int* team_imgs;
-  int G;                   // workgroups per team
-  int xcd_map;             // 1: team members share an XCD (block b -> XCD b % 8)
+  const int2* blk;         // per block: (team, member); team < 0: idle block
+  const int* team_G;       // workgroups per team
+  const int64_t* team_slot;  // first exchange slot of each team (2 G slots per team)
   const float* dirty;
   const float* beam;
   const int* niter;

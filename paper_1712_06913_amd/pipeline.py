@@ -2,6 +2,8 @@
 
 `ImagingPipeline` owns persistent device buffers for one batch descriptor so a step makes
 no allocation, and can replay the step from a captured HIP graph (torch.cuda.CUDAGraph).
+With threshold="gmm_sky" the step also fits the sky / disk levels of every dirty map
+(Sec. 4.1) and CLEAN stops at the sky level mu_a read on the device (Algorithm 1).
 `autotune_team_size` picks the CLEAN team size (workgroups per image) for a batch shape by
 timing a short proxy run of every candidate; choices are cached by shape key.  (The
 oversampling factor is not a tuning knob: it is part of the method's definition.)
@@ -62,7 +64,8 @@ def autotune_team_size(batch: api.Batch, dirty, beam, niter, gain=0.1, proxy_ite
 class ImagingPipeline:
     """One batch descriptor, persistent buffers, eager or graph-replayed steps."""
 
-    def __init__(self, wl, device="cuda:0", team_size: int = 0, restore: bool = True, adjoint: bool = True):
+    def __init__(self, wl, device="cuda:0", team_size: int = 0, restore: bool = True, adjoint: bool = True,
+                 threshold=None, positive_only: bool = False):
         self.dev = torch.device(device)
         self.wl = wl
         self.batch = api.Batch.from_workload(wl, self.dev)
@@ -78,13 +81,25 @@ class ImagingPipeline:
         self.beam = torch.empty(nbeam, dtype=torch.float32, device=self.dev)
         self.b0 = torch.empty(2 * b.n_inst, dtype=torch.float64, device=self.dev)
         self.adj = torch.empty(int(wl.vis_offset[-1]), dtype=torch.complex64, device=self.dev)
+        self.threshold = threshold
+        self.positive_only = positive_only
+        self.levels = torch.empty(6 * b.n_inst, dtype=torch.float64, device=self.dev)
+        self.mu_a = torch.empty(b.n_inst, dtype=torch.float32, device=self.dev)
+        self.mu_b = torch.empty(b.n_inst, dtype=torch.float32, device=self.dev)
         self.res = None
         self.graph: Optional[torch.cuda.CUDAGraph] = None
 
     def step(self):
         b = self.batch
         api.dirty_image(b, self.vis, self.uv, self.w, beam=True, out=self.dirty, beam_out=self.beam, b0_out=self.b0)
-        self.res = api.hogbom_clean(b, self.dirty, self.beam, self.niter, gain=self.gain, restore=self.restore,
+        thr = self.threshold
+        if isinstance(thr, str):
+            if thr != "gmm_sky":
+                raise ValueError(f"unknown threshold rule {thr!r}")
+            api.gmm_levels(b, self.dirty, levels=self.levels, mu_a=self.mu_a, mu_b=self.mu_b)
+            thr = self.mu_a
+        self.res = api.hogbom_clean(b, self.dirty, self.beam, self.niter, gain=self.gain, threshold=thr,
+                                    positive_only=self.positive_only, restore=self.restore,
                                     team_size=self.team_size, out=self.res)
         if self.adjoint:
             api.degrid(b, self.res["residual"], self.uv, self.w, adjoint=True, out=self.adj)

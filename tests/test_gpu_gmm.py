@@ -1,0 +1,108 @@
+"""GPU parity of the sky / disk levels (histogram + Gaussian mixture, Sec. 4.1) against the
+FP64 oracle, and CLEAN stopping at a threshold read on the device (Sec. 4.2-4.3)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import clean, gmm, imager
+from paper_1712_06913_amd import synth
+from tests.gpu_helpers import log, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _dirty_maps(wl):
+    out = []
+    for i in range(wl.n_inst):
+        v, uv, w = wl.instance(i)
+        N, cell, mode = int(wl.n_img[i]), float(wl.cell_rad[i]), int(wl.weight_mode[i])
+        out.append(imager.dirty_image(v, uv, w, N, cell, mode).astype(np.float32))
+    return out
+
+
+def _compare(levels_gpu, maps):
+    for i, m in enumerate(maps):
+        ref = gmm.levels(m)
+        got = levels_gpu[i]
+        span = float(np.nanmax(np.where(np.isfinite(m), m, np.nan)) - np.nanmin(np.where(np.isfinite(m), m, np.nan))) \
+            if np.isfinite(m).any() else 1.0
+        span = span if span > 0 else 1.0
+        log(f"  inst {i}: mu_a {got[0]:.6e}/{ref[0]:.6e} mu_b {got[3]:.6e}/{ref[3]:.6e} pi_b {got[5]:.4f}/{ref[5]:.4f}")
+        for k in (0, 3):                                     # means, relative to the value range
+            assert abs(got[k] - ref[k]) <= 1e-8 * span
+        for k in (1, 4):                                     # standard deviations
+            assert abs(got[k] - ref[k]) <= 1e-7 * max(ref[k], 1e-12 * span) + 1e-12 * span
+        for k in (2, 5):                                     # weights
+            assert abs(got[k] - ref[k]) <= 1e-8
+
+
+def test_levels_match_oracle_on_dirty_maps_and_edge_cases():
+    log("[gmm] levels of mixed-size dirty maps, a constant map and a map with non-finite pixels")
+    require_gpu()
+    from paper_1712_06913_amd import api
+    wl = synth.random_instances(51, [64, 256, 128, 64], m_range=(150, 400))
+    maps = _dirty_maps(wl)
+    maps[3] = np.full((64, 64), 0.125, np.float32)               # constant map
+    maps[2] = maps[2].copy()
+    maps[2][3, 5] = np.nan                                       # not counted
+    maps[2][7, 1] = np.inf
+    b = api.Batch.from_workload(wl)
+    imgs = torch.from_numpy(np.concatenate([m.ravel() for m in maps])).cuda()
+    levels, mu_a, mu_b = api.gmm_levels(b, imgs)
+    torch.cuda.synchronize()
+    L = levels.cpu().numpy()
+    _compare(L, maps)
+    assert np.array_equal(mu_a.cpu().numpy(), L[:, 0].astype(np.float32))
+    assert np.array_equal(mu_b.cpu().numpy(), L[:, 3].astype(np.float32))
+    assert tuple(L[3]) == (0.125, 0.0, 1.0, 0.125, 0.0, 0.0)
+
+
+def test_levels_match_oracle_on_c1_and_c3_maps():
+    log("[gmm] levels of the C1 map and two C3 channels at 1024^2")
+    require_gpu()
+    from paper_1712_06913_amd import api
+    for wl in (synth.c1_snapshot(), synth.c3_muser2(chans=[0, 300])):
+        maps = _dirty_maps(wl)
+        b = api.Batch.from_workload(wl)
+        imgs = torch.from_numpy(np.concatenate([m.ravel() for m in maps])).cuda()
+        levels, _, _ = api.gmm_levels(b, imgs)
+        torch.cuda.synchronize()
+        _compare(levels.cpu().numpy(), maps)
+
+
+def test_clean_stops_at_a_device_threshold_from_the_levels():
+    log("[gmm] CLEAN with a threshold read on the device, derived from the disk level mu_b")
+    require_gpu()
+    from paper_1712_06913_amd import api
+    wl = synth.random_instances(52, [128, 64], m_range=(200, 300))
+    maps = _dirty_maps(wl)
+    beams = []
+    for i in range(wl.n_inst):
+        v, uv, w = wl.instance(i)
+        beams.append(imager.dirty_beam(uv, w, int(wl.n_img[i]), float(wl.cell_rad[i]),
+                                       int(wl.weight_mode[i])).astype(np.float32))
+    b = api.Batch.from_workload(wl)
+    d_t = torch.from_numpy(np.concatenate([m.ravel() for m in maps])).cuda()
+    b_t = torch.from_numpy(np.concatenate([x.ravel() for x in beams])).cuda()
+    levels, _, mu_b = api.gmm_levels(b, d_t)
+    # pre-clean style stop (Sec. 4.2 cleans down to the disk level; on these small synthetic
+    # maps the disk level itself takes more than the iteration cap, so stop halfway between
+    # it and the peak); positive_only: Algorithm 1 compares the peak brightness
+    peaks = torch.tensor([float(m.max()) for m in maps], dtype=torch.float32, device="cuda")
+    thr_dev = (0.5 * (mu_b + peaks)).contiguous()
+    niter = np.array([3000, 3000], np.int32)
+    res = api.hogbom_clean(b, d_t, b_t, niter, threshold=thr_dev, positive_only=True, restore=False)
+    torch.cuda.synchronize()
+    thr = thr_dev.cpu().numpy()
+    nc = res["n_comp"].cpu().numpy()
+    ci, cf = res["comp_idx"].cpu().numpy(), res["comp_flux"].cpu().numpy()
+    off = res["comp_off"]
+    for i in range(wl.n_inst):
+        n = int(nc[i])
+        ok, bad, R, _ = clean.replay(maps[i].astype(np.float64), beams[i].astype(np.float64),
+                                     ci[off[i]: off[i] + n], cf[off[i]: off[i] + n], threshold=float(thr[i]),
+                                     positive_only=True)
+        log(f"  inst {i}: threshold {thr[i]:.4e}, {n} components, next peak {np.max(R):.4e}")
+        assert ok, f"instance {i}: pick {bad} rejected"
+        assert 0 < n < int(niter[i])
+        assert np.max(R) <= thr[i] + 1e-5 * np.max(np.abs(maps[i]))

@@ -96,3 +96,33 @@ def test_autotuner_picks_a_working_team_size():
     st = pl.batch.status.cpu().numpy()
     assert not np.any(st & 16), f"aborted instances: {st}"
     assert np.all(res["n_comp"].cpu().numpy() == 300)
+
+
+def test_gmm_sky_threshold_step_and_graph_replay():
+    log("[pipeline] step with the GMM sky level as CLEAN threshold, eager vs graph replay")
+    require_gpu()
+    from paper_1712_06913_amd import pipeline
+    from oracle import gmm
+    wl = _c4_slice(6, niter_cap=400)
+    pl = pipeline.ImagingPipeline(wl, threshold="gmm_sky", adjoint=False)
+    res = pl.step()
+    torch.cuda.synchronize()
+    # levels of the step's own dirty maps match the oracle's fit of them
+    maps = pl.batch.split(pl.dirty)
+    L = pl.levels.view(-1, 6).cpu().numpy()
+    for i, m in enumerate(maps):
+        ref = gmm.levels(m.cpu().numpy())
+        span = float(m.max() - m.min())
+        assert abs(L[i, 0] - ref[0]) <= 1e-8 * span and abs(L[i, 3] - ref[3]) <= 1e-8 * span
+    eager_n = res["n_comp"].clone()
+    eager_r = res["residual"].clone()
+    pl.capture()
+    # the gridder's FP64 LDS accumulation order varies between runs, so maps agree to
+    # rounding, not bit for bit (as in the eager-vs-replay test above)
+    for r in range(2):
+        pl.res["residual"].fill_(0.0)
+        pl.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(pl.res["n_comp"], eager_n), f"replay {r}"
+        err = float((pl.res["residual"] - eager_r).abs().max())
+        assert err <= 1e-6 * float(eager_r.abs().max()), f"replay {r}: {err}"
