@@ -132,7 +132,7 @@ __device__ __forceinline__ void stockham_pass(double2* buf, int log2P, int log2L
 
 // Full length-P FFT (sign s) of nl lines in LDS; nl * P <= ELEMS.
 template <int ELEMS, int THREADS>
-__device__ void lds_fft(double2* buf, int log2P, int nl, double s, const double2* __restrict__ tw) {
+__device__ __forceinline__ void lds_fft(double2* buf, int log2P, int nl, double s, const double2* __restrict__ tw) {
   int done = 0, rem = log2P;
   while (rem > 0) {
     const int r = (rem == 4 || rem == 2) ? 2 : (rem == 1 ? 1 : 3);

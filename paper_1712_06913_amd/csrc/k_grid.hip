@@ -198,9 +198,14 @@ k_bin(const InstDesc* __restrict__ inst, const float2* __restrict__ uv, const fl
   }
 }
 
-// One tile of TK x TJ cells per iteration of a grid-stride loop.  Accumulation is FP64
-// (the grid correction later amplifies grid rounding by up to ~1e6 in the map corners).
+// Tiles of TK x TJ cells, GRID_CHUNK consecutive tiles per workgroup (their metadata
+// staged in LDS, so a run of empty tiles is a stream of stores with no dependent global
+// loads).  A non-empty tile stages up to GRID_EB of its samples' parameters in LDS, then
+// spreads (sample, tap row) pairs over all threads; accumulation is FP64 in LDS (the grid
+// correction later amplifies grid rounding by up to ~1e6 in the map corners).
 constexpr int GRID_THREADS = 256;
+constexpr int GRID_CHUNK = 32;
+constexpr int GRID_EB = 256;
 
 template <class OutT>
 __global__ void __launch_bounds__(GRID_THREADS)
@@ -211,19 +216,31 @@ k_grid(const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst, int
        OutT* __restrict__ grid, int modulate) {
   __shared__ double2 acc[TK * TJ];
   __shared__ double tab[TAB_LEN];
+  __shared__ int m_inst[GRID_CHUNK], m_start[GRID_CHUNK], m_cnt[GRID_CHUNK];
+  __shared__ int s_kp[GRID_EB], s_j[GRID_EB], s_ou[GRID_EB], s_ov[GRID_EB];
+  __shared__ double s_wr[GRID_EB], s_wi[GRID_EB];
   const int tid = threadIdx.x;
+  const int g0 = blockIdx.x * GRID_CHUNK;
+  if (g0 >= n_tiles) return;
+  const int gn = min(GRID_CHUNK, n_tiles - g0);
   for (int t = tid; t < TAB_LEN; t += GRID_THREADS) tab[t] = T.tab[t];
+  for (int t = tid; t < gn; t += GRID_THREADS) {
+    m_inst[t] = tile_inst[g0 + t];
+    m_start[t] = tstart[g0 + t];
+    m_cnt[t] = tcount[g0 + t];
+  }
   __syncthreads();
 
-  for (int g = blockIdx.x; g < n_tiles; g += gridDim.x) {
-    const int i = tile_inst[g];
+  for (int tt = 0; tt < gn; ++tt) {
+    const int g = g0 + tt;
+    const int i = __builtin_amdgcn_readfirstlane(m_inst[tt]);
     const InstDesc d = inst[i];
     const int N = d.N, P = beam ? 2 * N : N, h = P / 2;
     const int t = g - (beam ? d.tile_base_b : d.tile_base_d);
     const int ntj = P / TJ;
     const int k0 = (t / ntj) * TK, j0 = (t % ntj) * TJ;
     OutT* out = grid + (beam ? d.gb_off : d.gd_off) + (int64_t)k0 * P + j0;
-    const int n = tcount[g];
+    const int n = __builtin_amdgcn_readfirstlane(m_cnt[tt]);
 
     if (n == 0) {  // empty tile: plain zero fill
       for (int q = tid; q < TK * TJ; q += GRID_THREADS) {
@@ -235,30 +252,40 @@ k_grid(const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst, int
       continue;
     }
     for (int q = tid; q < TK * TJ; q += GRID_THREADS) acc[q] = make_double2(0.0, 0.0);
-    __syncthreads();
-
-    const int st = tstart[g];
-    for (int e = tid; e < n; e += GRID_THREADS) {
-      const int en = ent[st + e];
-      const int k = en >> 1;
-      const bool mirror = en & 1;
-      const int64_t vi = d.vis_off + k;
-      const float2 q = uv[vi];
-      const Sample s = prep_sample(q.x, q.y, w_in[vi], d.scale, N);
-      int cu = beam ? s.cu2 : s.cu, cv = beam ? s.cv2 : s.cv;
-      int ou = beam ? s.ou2 : s.ou, ov = beam ? s.ov2 : s.ov;
-      float2 v = beam ? make_float2(1.f, 0.f) : vis[vi];
-      if (mirror) { cu = -cu; cv = -cv; ou = -ou; ov = -ov; v.y = -v.y; }
-      const double w = (double)wts[vi];
-      const double wr = w * (double)v.x, wim = w * (double)v.y;
-#pragma unroll
-      for (int du = -HALF_W; du <= HALF_W; ++du) {
-        const int kp = cu + du + h - 1;
+    const int st = m_start[tt];
+    for (int e0 = 0; e0 < n; e0 += GRID_EB) {
+      const int ne = min(GRID_EB, n - e0);
+      __syncthreads();                                 // acc zeroed / previous stage consumed
+      if (tid < ne) {
+        const int en = ent[st + e0 + tid];
+        const int k = en >> 1;
+        const bool mirror = en & 1;
+        const int64_t vi = d.vis_off + k;
+        const float2 q = uv[vi];
+        const Sample sm = prep_sample(q.x, q.y, w_in[vi], d.scale, N);
+        int cu = beam ? sm.cu2 : sm.cu, cv = beam ? sm.cv2 : sm.cv;
+        int ou = beam ? sm.ou2 : sm.ou, ov = beam ? sm.ov2 : sm.ov;
+        float2 v = beam ? make_float2(1.f, 0.f) : vis[vi];
+        if (mirror) { cu = -cu; cv = -cv; ou = -ou; ov = -ov; v.y = -v.y; }
+        const double w = (double)wts[vi];
+        s_kp[tid] = cu + h - 1;
+        s_j[tid] = cv + h;
+        s_ou[tid] = ou;
+        s_ov[tid] = ov;
+        s_wr[tid] = w * (double)v.x;
+        s_wi[tid] = w * (double)v.y;
+      }
+      __syncthreads();
+      for (int wi = tid; wi < ne * W; wi += GRID_THREADS) {
+        const int e = wi / W, du = wi - e * W - HALF_W;
+        const int kp = s_kp[e] + du;
         if (kp < k0 || kp >= k0 + TK || kp > h - 1) continue;
-        const double tu = tab[du * OS - ou + TAB_CENTRE];
+        const double tu = tab[du * OS - s_ou[e] + TAB_CENTRE];
+        const int jb = s_j[e], ov = s_ov[e];
+        const double wr = s_wr[e], wim = s_wi[e];
 #pragma unroll
         for (int dv = -HALF_W; dv <= HALF_W; ++dv) {
-          const int j = cv + dv + h;
+          const int j = jb + dv;
           if (j < j0 || j >= j0 + TJ) continue;
           const double kk = tu * tab[dv * OS - ov + TAB_CENTRE];
           double* a = reinterpret_cast<double*>(&acc[(kp - k0) * TJ + (j - j0)]);
@@ -325,7 +352,7 @@ hipError_t launch_grid_t(const InstDesc* inst, const int* tile_inst, int n_tiles
                          const float2* uv, const float* w_in, const float* wts, const int* ent, const int* tstart,
                          const int* tcount, const Tables& T, OutT* grid, int modulate, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  int blocks = n_tiles < 8192 ? n_tiles : 8192;
+  const int blocks = (n_tiles + GRID_CHUNK - 1) / GRID_CHUNK;
   hipLaunchKernelGGL((k_grid<OutT>), dim3(blocks), dim3(GRID_THREADS), 0, st, inst, tile_inst, n_tiles, beam, vis,
                      uv, w_in, wts, ent, tstart, tcount, T, grid, modulate);
   return hipGetLastError();
