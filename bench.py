@@ -87,8 +87,7 @@ def measured_traffic(workload, team_size):
     try:
         if vals["kernel_source_sha256"] != kernel_source_hash():
             return None
-        return (float(vals["k_clean_fetch_kib"]) * 1024.0 * float(vals["fetch_scale"]) +
-                float(vals["k_clean_write_kib"]) * 1024.0 * float(vals["write_scale"]))
+        return float(vals["k_clean_read_bytes"]) + float(vals["k_clean_write_bytes"])
     except (KeyError, ValueError):
         return None
 
@@ -239,7 +238,7 @@ def main():
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_clean",
             "kernel_ms": kernel_ms, "kernel_launches_timed": len(kernel_times), "algorithmic_bytes": clean_bytes,
-            "traffic_unit": "HBM-side bytes per launch (FETCH_SIZE x 2 + WRITE_SIZE, KiB x 1024)",
+            "traffic_unit": "HBM-side bytes per launch (L2 read and write requests by size)",
             "traffic_over_algorithmic": (traffic / clean_bytes) if traffic else None}
 
     out = {
