@@ -11,4 +11,7 @@ Parity status per function (see each module header for the pins):
   clean.hogbom / clean.replay                    pinned (closed forms, CLEAN identity)
   clean.fit_clean_beam / clean.restore           pinned (exact Gaussian beam, empty model)
   adjoint.predict / adjoint.adjoint              pinned (dot-product identity, brute-force transpose)
+  gmm.histogram / gmm.em_fit / gmm.levels        pinned (exact binning, closed-form moments, monotone EM, known mixture)
+  centering.correlate / peak_offset / disk_offset / phase_correct
+                                                 pinned (direct-sum correlation, whole-pixel shifts, point-source phase)
 """

@@ -90,6 +90,7 @@ class Sky:
     radius: float                    # disk radius (rad); total disk flux is 1
     gauss: np.ndarray                # (3, 4): peak brightness, sigma (rad), l0, m0
     limb: float = 0.0                # limb-brightening coefficient a in B(1 + a rho^2/R^2)
+    centre: tuple = (0.0, 0.0)       # (l, m) of the disk centre (rad): the whole sky is displaced
 
     @property
     def b_disk(self) -> float:
@@ -142,6 +143,9 @@ def sky_vis(sky: Sky, u: np.ndarray, v: np.ndarray) -> np.ndarray:
         vis = vis + limb_vis(q, sky.radius, sky.limb, sky.b_disk)
     for peak, sigma, l0, m0 in sky.gauss:
         vis = vis + gauss_vis(u, v, peak, sigma, l0, m0)
+    lc, mc = sky.centre
+    if lc != 0.0 or mc != 0.0:                   # the sky displaced as a whole
+        vis = vis * np.exp(-2j * math.pi * (u * lc + v * mc))
     return vis
 
 
@@ -166,6 +170,7 @@ class Workload:
     niter: np.ndarray          # int32 [n]
     freq_hz: np.ndarray        # float64 [n]
     gain: float = 0.1
+    sky_centre: Optional[np.ndarray] = None   # float64 [n, 2]: true (l, m) of the disk centre (rad)
 
     @property
     def n_inst(self) -> int:
@@ -189,7 +194,8 @@ class Workload:
             w=cat(2, np.float32).astype(np.float32),
             vis_offset=off, n_img=self.n_img[idx].copy(), cell_rad=self.cell_rad[idx].copy(),
             weight_mode=self.weight_mode[idx].copy(), niter=self.niter[idx].copy(),
-            freq_hz=self.freq_hz[idx].copy(), gain=self.gain)
+            freq_hz=self.freq_hz[idx].copy(), gain=self.gain,
+            sky_centre=None if self.sky_centre is None else self.sky_centre[idx].copy())
 
 
 def _instance_vis(bl_en, freq_hz, ha_rad, sky, noise_seed, dec_rad=math.radians(20.0)):
@@ -301,6 +307,29 @@ def fd_subset() -> Workload:
     # small grid: widen the field so the inner baselines fit (cell 1/(N dl) with dl = FOV/N)
     return _assemble("fd_subset_64", [dict(vis=vis, uv=uv, w=np.ones(len(vis), np.float32),
                                            N=64, mode=0, niter=0, freq=f)])
+
+
+def offset_disk(seed: int = 7, n: int = 6, sizes=(256, 512), max_offset_px: float = 24.0,
+                niter: int = 3000) -> Workload:
+    """Displaced-disk instances for the disk-centering step: MUSER-II-like array, channels
+    over 2-15 GHz, the whole sky (disk, limb, sources) shifted by a random offset of up to
+    `max_offset_px` pixels in each axis (a phase / pointing error); natural weighting."""
+    rng = np.random.default_rng(seed)
+    bl = baselines(muser2_array())
+    items, centres = [], []
+    for k in range(n):
+        N = int(sizes[k % len(sizes)])
+        c = int(rng.integers(0, 520))
+        f = (2.0125 + 0.025 * c) * 1e9
+        cell = FOV_RAD / N
+        off = rng.uniform(-max_offset_px, max_offset_px, 2) * cell
+        sky = dataclasses.replace(make_sky(3, limb=limb_coefficient(f)), centre=(float(off[0]), float(off[1])))
+        vis, uv = _instance_vis(bl, f, 0.0, sky, 2000 + k)
+        items.append(dict(vis=vis, uv=uv, w=np.ones(len(vis), np.float32), N=N, mode=0, niter=niter, freq=f))
+        centres.append(off)
+    wl = _assemble(f"offset_disk_{n}", items)
+    wl.sky_centre = np.array(centres, np.float64)
+    return wl
 
 
 def random_instances(seed: int, sizes, m_range=(1, 300), uniform_frac=0.5, fill=0.8) -> Workload:
