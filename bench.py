@@ -49,6 +49,11 @@ def parse():
     return ap.parse_args()
 
 
+def synth_arcmin():
+    from paper_1712_06913_amd import synth
+    return synth.ARCMIN
+
+
 def make_workload(name):
     from paper_1712_06913_amd import synth
     if name == "c1":
@@ -227,6 +232,16 @@ def main():
     torch.cuda.synchronize()
     gmm_ms = ge[0].elapsed_time(ge[1]) / reps
 
+    # disk offsets by correlation with the solar disk (not part of the step)
+    radius = 16.0 * synth_arcmin() / b.cell_rad
+    offs = api.disk_offsets(b, dirty, radius)
+    ge[0].record(stream)
+    for _ in range(reps):
+        api.disk_offsets(b, dirty, radius, out=offs.view(-1))
+    ge[1].record(stream)
+    torch.cuda.synchronize()
+    center_ms = ge[0].elapsed_time(ge[1]) / reps
+
     # roofline of the dominant kernel (k_clean): algorithmic bytes = per iteration the
     # beam window (4 N^2 bytes; the residual stays in LDS) plus once per image the dirty
     # map in, residual + restored out (3 x 4 N^2) and the FP64 model out (8 N^2)
@@ -253,7 +268,7 @@ def main():
                    "gain": wl.gain, "weighting": "natural" if not wl.weight_mode.any() else "mixed/uniform",
                    "clean_team_size": args.team_size or "library policy"},
         "stage_ms": {"dirty_image_and_beam": img_ms, "clean_restore": clean_ms, "adjoint": adj_ms,
-                     "gridding_only": grid_ms, "gmm_levels": gmm_ms},
+                     "gridding_only": grid_ms, "gmm_levels": gmm_ms, "disk_offsets": center_ms},
         "gmm_levels_read_GBps": float(np.sum(8.0 * N2)) / (gmm_ms * 1e-3) / 1e9,
         "gridded_vis_per_s": kept / (grid_ms * 1e-3),
         "kept_visibilities": kept,

@@ -195,6 +195,22 @@ mi_status mi_gmm_levels(mi_ctx* ctx, const mi_batch* batch, const float* images,
                         int32_t n_iter, double* levels_out, float* mu_a_out, float* mu_b_out,
                         hipStream_t stream);
 
+/* Disk centering (Sec. 4.2): offset of the solar disk in each map from the field centre.
+ * Each N*N map (typically cleaned down to the disk level mu_b of mi_gmm_levels, which
+ * removes the active regions) is correlated circularly with a uniform disk of radius
+ * radius_px[i] pixels centred on pixel (N/2, N/2) (FP64 DFTs); the largest correlation
+ * value (ties: lowest linear index) is refined per axis by a parabola through it and its
+ * neighbours.  radius_px: host, n_inst, > 0.  offsets_out (device): double [n_inst][2] =
+ * (dl, dm) in radians (+x, +y = increasing pixel index).                          */
+mi_status mi_disk_offsets(mi_ctx* ctx, const mi_batch* batch, const float* images, const double* radius_px,
+                          double* offsets_out, hipStream_t stream);
+
+/* Phase correction (Sec. 4.2, Algorithm 1): vis[k] *= exp(+2 pi i (u_k dl + v_k dm)) in
+ * place (FP64 phase), which moves a disk at (dl, dm) to the centre of the next image.
+ * offsets (device): double [n_inst][2], e.g. from mi_disk_offsets.                    */
+mi_status mi_phase_shift(mi_ctx* ctx, const mi_batch* batch, mi_c64* vis, const float* uv,
+                         const double* offsets, hipStream_t stream);
+
 /* ---- kernel timing (measurement hook, not part of the imaging path) ----------------
  * mi_profile_begin: from now on, every mi_hogbom_clean call records a pair of HIP events
  *   on its stream around its Hogbom kernel launch (the beam fit, symmetry check and fills

@@ -15,7 +15,8 @@ MI_LAYOUT_FULL, MI_LAYOUT_HALF = 0, 1
 
 # every entry point declared in include/mi.h
 EXPORTS = ("mi_ctx_create", "mi_ctx_destroy", "mi_last_error", "mi_version", "mi_grid", "mi_ifft2",
-           "mi_dirty_image", "mi_dirty_beam", "mi_hogbom_clean", "mi_degrid", "mi_gmm_levels", "mi_profile_begin", "mi_profile_end")
+           "mi_dirty_image", "mi_dirty_beam", "mi_hogbom_clean", "mi_degrid", "mi_gmm_levels", "mi_disk_offsets", "mi_phase_shift", "mi_profile_begin",
+           "mi_profile_end")
 
 
 class MiBatch(ctypes.Structure):

@@ -196,6 +196,24 @@ def gmm_levels(batch: Batch, images, n_bins: int = 2000, n_iter: int = 500, leve
     return levels.view(n, 6), mu_a, mu_b
 
 
+def disk_offsets(batch: Batch, images, radius_px, out=None):
+    """mi_disk_offsets: (n_inst, 2) float64 device tensor of (dl, dm) in radians."""
+    dev = batch.device
+    r = np.ascontiguousarray(radius_px, dtype=np.float64)
+    out = torch.empty(2 * batch.n_inst, dtype=torch.float64, device=dev) if out is None else out
+    nat.check(batch.ctx, nat.lib().mi_disk_offsets(batch.ctx, batch.c, _ptr(images), r.ctypes.data_as(ctypes.c_void_p),
+                                                   _ptr(out), _stream(dev)))
+    return out.view(batch.n_inst, 2)
+
+
+def phase_shift(batch: Batch, vis, uv, offsets):
+    """mi_phase_shift: vis *= exp(+2 pi i (u dl + v dm)) in place; offsets (n_inst, 2) float64 on the device."""
+    dev = batch.device
+    nat.check(batch.ctx, nat.lib().mi_phase_shift(batch.ctx, batch.c, _ptr(vis), _ptr(uv), _ptr(offsets.contiguous()),
+                                                  _stream(dev)))
+    return vis
+
+
 def profile_begin(device: int = 0):
     """mi_profile_begin: record HIP events around every following Hogbom kernel launch."""
     ctx = context(device)

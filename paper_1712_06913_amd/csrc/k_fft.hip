@@ -391,6 +391,18 @@ hipError_t launch_fft_c2c_t_f2d(int elems, const int* n_arr, const int64_t* offs
                        src, dst, T, s, pre, post);
   return hipGetLastError();
 }
+hipError_t launch_fft_c2c_t_d2d(int elems, const int* n_arr, const int64_t* offs, const FftWork* work, int n_work,
+                                const double2* src, double2* dst, const Tables& T, double s, int pre, int post,
+                                hipStream_t st) {
+  if (n_work <= 0) return hipSuccess;
+  if (elems == 8192)
+    hipLaunchKernelGGL((k_fft_c2c_t<8192, 512, double2, double2>), dim3(n_work), dim3(512), 0, st, n_arr, offs, work,
+                       src, dst, T, s, pre, post);
+  else
+    hipLaunchKernelGGL((k_fft_c2c_t<4096, 512, double2, double2>), dim3(n_work), dim3(512), 0, st, n_arr, offs, work,
+                       src, dst, T, s, pre, post);
+  return hipGetLastError();
+}
 hipError_t launch_fft_c2c_t_d2f(int elems, const int* n_arr, const int64_t* offs, const FftWork* work, int n_work,
                                 const double2* src, float2* dst, const Tables& T, double s, int pre, int post,
                                 hipStream_t st) {

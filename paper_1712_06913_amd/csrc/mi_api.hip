@@ -51,6 +51,12 @@ hipError_t clean_max_blocks_per_cu(int ppt, bool local, size_t lds, int* nb);
 hipError_t launch_clean(const CleanArgs&, int ppt, bool local, int n_blocks, size_t lds, hipStream_t);
 hipError_t launch_beamfit(const InstDesc*, int, const float*, double*, int*, int*, hipStream_t);
 hipError_t launch_gmm(const InstDesc*, int, const float*, int, int, double*, float*, float*, hipStream_t);
+hipError_t launch_fft_c2c_t_d2d(int, const int*, const int64_t*, const FftWork*, int, const double2*, double2*,
+                                const Tables&, double, int, int, hipStream_t);
+hipError_t launch_corr_prep(const InstDesc*, int, int, const float*, const double*, double2*, double2*, hipStream_t);
+hipError_t launch_corr_mul(double2*, const double2*, int64_t, hipStream_t);
+hipError_t launch_corr_peak(const InstDesc*, int, const double2*, double*, hipStream_t);
+hipError_t launch_phase_shift(const InstDesc*, int, int, float2*, const float2*, const double*, hipStream_t);
 hipError_t launch_beam_symcheck(const InstDesc*, int, int, const float*, int*, hipStream_t);
 hipError_t launch_beam_symmetrize(const InstDesc*, int, int, float*, hipStream_t);
 hipError_t launch_degrid(const InstDesc*, int, int, const float2*, const float*, const float*, const double*,
@@ -151,6 +157,10 @@ struct Plan {
   // workspace
   DevBuf wts, b0, nkept, cnt, ent_d, ent_b, ts_d, tc_d, ts_b, tc_b, gd, gb, status_ws, full_off;
   std::map<uint64_t, std::unique_ptr<CleanPlan>> cleans;
+  // disk centering: radii (host copy for change detection), 2-D transform work list, buffers
+  std::vector<double> radius;
+  int corr_elems = 0, corr_nwork = 0;
+  DevBuf radius_d, corr_n, corr_offs, corr_work, corr_x, corr_d, corr_s, offsets_ws;
 };
 
 struct IfftPlan {
@@ -595,6 +605,72 @@ mi_status mi_gmm_levels(mi_ctx* ctx, const mi_batch* batch, const float* images,
     Plan* P = get_plan(ctx, batch);
     HIPCHK(launch_gmm(static_cast<const InstDesc*>(P->inst.p), P->n_inst, images, n_bins, n_iter, levels_out,
                       mu_a_out, mu_b_out, stream));
+  });
+}
+
+mi_status mi_disk_offsets(mi_ctx* ctx, const mi_batch* batch, const float* images, const double* radius_px,
+                          double* offsets_out, hipStream_t stream) {
+  return guard(ctx, [&] {
+    need(images, "images");
+    need(radius_px, "radius_px");
+    need(offsets_out, "offsets_out");
+    HIPCHK(hipSetDevice(ctx->device));
+    Plan* P = get_plan(ctx, batch);
+    const int n = P->n_inst;
+    for (int i = 0; i < n; ++i)
+      if (!(radius_px[i] > 0.0) || !(radius_px[i] < 1e6)) fail(MI_ERR_ARG, "radius_px[%d] must be positive", i);
+    if (P->radius.size() != (size_t)n || !std::equal(P->radius.begin(), P->radius.end(), radius_px)) {
+      P->radius.assign(radius_px, radius_px + n);
+      upload(P->radius_d, P->radius);
+    }
+    if (!P->corr_work.p) {                              // 2-D transform plan over the packed maps
+      std::vector<int32_t> nn(P->n.begin(), P->n.end());
+      std::vector<int64_t> offs(n);
+      std::vector<FftWork> work;
+      P->corr_elems = fft_elems_for(P->max_N);
+      for (int i = 0; i < n; ++i) {
+        offs[i] = P->h_inst[i].img_off;
+        int nl = P->corr_elems / nn[i];
+        if (nl > nn[i]) nl = nn[i];
+        for (int l = 0; l < nn[i]; l += nl) work.push_back({i, l});
+      }
+      P->corr_nwork = (int)work.size();
+      upload(P->corr_n, nn);
+      upload(P->corr_offs, offs);
+      upload(P->corr_work, work);
+    }
+    const int64_t total = P->total_img;
+    double2* X = dev_alloc<double2>(P->corr_x, total);
+    double2* D = dev_alloc<double2>(P->corr_d, total);
+    double2* S = dev_alloc<double2>(P->corr_s, total);
+    const InstDesc* inst = static_cast<const InstDesc*>(P->inst.p);
+    const int* nd = static_cast<const int*>(P->corr_n.p);
+    const int64_t* od = static_cast<const int64_t*>(P->corr_offs.p);
+    const FftWork* wk = static_cast<const FftWork*>(P->corr_work.p);
+    const int e = P->corr_elems, nw = P->corr_nwork;
+    HIPCHK(launch_corr_prep(inst, n, P->max_N, images, static_cast<const double*>(P->radius_d.p), X, D, stream));
+    // forward 2-D DFTs (two line passes with transposed writes), plain (no centring)
+    HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, nw, X, S, ctx->T, -1.0, 0, 0, stream));
+    HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, nw, S, X, ctx->T, -1.0, 0, 0, stream));
+    HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, nw, D, S, ctx->T, -1.0, 0, 0, stream));
+    HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, nw, S, D, ctx->T, -1.0, 0, 0, stream));
+    HIPCHK(launch_corr_mul(X, D, total, stream));
+    HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, nw, X, S, ctx->T, +1.0, 0, 0, stream));
+    HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, nw, S, X, ctx->T, +1.0, 0, 0, stream));
+    HIPCHK(launch_corr_peak(inst, n, X, offsets_out, stream));
+  });
+}
+
+mi_status mi_phase_shift(mi_ctx* ctx, const mi_batch* batch, mi_c64* vis, const float* uv, const double* offsets,
+                         hipStream_t stream) {
+  return guard(ctx, [&] {
+    need(vis, "vis");
+    need(uv, "uv");
+    need(offsets, "offsets");
+    HIPCHK(hipSetDevice(ctx->device));
+    Plan* P = get_plan(ctx, batch);
+    HIPCHK(launch_phase_shift(static_cast<const InstDesc*>(P->inst.p), P->n_inst, P->max_nvis,
+                              reinterpret_cast<float2*>(vis), reinterpret_cast<const float2*>(uv), offsets, stream));
   });
 }
 

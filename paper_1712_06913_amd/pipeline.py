@@ -131,3 +131,28 @@ class ImagingPipeline:
     def replay(self):
         self.graph.replay()
         return self.res
+
+
+def improved_clean(wl, radius_px, device="cuda:0", restore: bool = True, team_size: int = 0):
+    """Algorithm 1 (improved_clean) over a whole batch, every stage one batched launch:
+    dirty map and beam -> sky / disk levels (Sec. 4.1) -> CLEAN to the disk level mu_b ->
+    disk offset by correlation with a disk of `radius_px` pixels (Sec. 4.2) -> phase
+    correction of the visibilities -> dirty map and beam again -> levels -> CLEAN while the
+    peak exceeds the sky level mu_a (Sec. 4.3; positive peaks, loop gain of the workload).
+    Returns (result dict of hogbom_clean, offsets (n, 2) radians, levels (n, 6), the
+    corrected visibilities)."""
+    dev = torch.device(device)
+    b = api.Batch.from_workload(wl, dev)
+    vis, uv, w = api.workload_tensors(wl, dev)
+    niter = np.ascontiguousarray(wl.niter, np.int32)
+    dirty, beam, _ = api.dirty_image(b, vis, uv, w, beam=True)
+    _, _, mu_b = api.gmm_levels(b, dirty)
+    pre = api.hogbom_clean(b, dirty, beam, niter, gain=wl.gain, threshold=mu_b, positive_only=True,
+                           restore=False, want_model=False, want_components=False, team_size=team_size)
+    offsets = api.disk_offsets(b, pre["residual"], radius_px)
+    api.phase_shift(b, vis, uv, offsets)
+    dirty, beam, _ = api.dirty_image(b, vis, uv, w, beam=True, out=dirty, beam_out=beam)
+    levels, mu_a, _ = api.gmm_levels(b, dirty)
+    res = api.hogbom_clean(b, dirty, beam, niter, gain=wl.gain, threshold=mu_a, positive_only=True,
+                           restore=restore, team_size=team_size)
+    return res, offsets, levels, vis
