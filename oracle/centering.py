@@ -21,8 +21,9 @@ phase correction in improved_clean).  Readings (the paper gives no formulas):
 Pins (tests/test_oracle_centering.py): the FFT correlation equals the direct double sum on
 a small map; a disk map shifted by whole pixels is found at exactly that shift; a point
 source at (l0, m0) corrected by (l0, m0) has all visibilities equal to its flux; the
-synthetic sky displaced by a known offset is found within a fraction of a pixel and is
-centred after correction.
+synthetic sky displaced by a known offset is found within a few pixels (the limit of a
+plain disk template against a dirty, limb-brightened disk) and is much closer to centred
+after correction.
 """
 from __future__ import annotations
 
