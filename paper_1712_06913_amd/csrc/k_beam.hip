@@ -1,5 +1,5 @@
-// Beam-side kernels of the CLEAN stage (gfx950): the clean-beam fit and the beam's point
-// symmetry (made exact after the beam transform, checked before CLEAN).
+// Beam-side kernels of the CLEAN stage (gfx950): the clean-beam fit and the check of the
+// beam's point symmetry before CLEAN.
 #include <algorithm>
 
 #include "mi_internal.h"
@@ -13,24 +13,10 @@ constexpr int FIT_BOX = 2 * FIT_HALF + 1;
 constexpr int RESTORE_RMAX = 64;             // restore radius cap (pixels)
 
 // The beam of Hermitian-completed visibilities is point-symmetric about (N, N):
-// B[N + a][N + b] = B[N - a][N - b].  k_beam_symmetrize makes that exact in float32 by
-// copying the half a < 0 (and a = 0, b < 0) onto its mirror; k_beam_symcheck flags
-// instances whose beam is not exactly symmetric over the rows and columns 1..2N-1 that
-// CLEAN windows read.  Both cover, per instance, the mirror pixels (r, c) with r > N, or
-// r = N and c > N, and 1 <= c <= 2N-1.
-__global__ void __launch_bounds__(256)
-k_beam_symmetrize(const InstDesc* __restrict__ inst, float* __restrict__ beam) {
-  const InstDesc d = inst[blockIdx.y];
-  const int N = d.N, twoN = 2 * N;
-  float* B = beam + d.beam_off;
-  const int64_t npair = (int64_t)N * twoN;                 // rows N..2N-1, columns 0..2N-1
-  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < npair; q += (int64_t)gridDim.x * 256) {
-    const int r = N + (int)(q / twoN), c = (int)(q % twoN);
-    if (c == 0 || (r == N && c <= N)) continue;
-    B[(int64_t)r * twoN + c] = B[(int64_t)(twoN - r) * twoN + (twoN - c)];
-  }
-}
-
+// B[N + a][N + b] = B[N - a][N - b] (the library's own beams are stored exactly so).
+// k_beam_symcheck flags instances whose beam is not exactly symmetric over the rows and
+// columns 1..2N-1 that CLEAN windows read: per instance, the mirror pixels (r, c) with
+// r > N, or r = N and c > N, and 1 <= c <= 2N-1.
 __global__ void __launch_bounds__(256)
 k_beam_symcheck(const InstDesc* __restrict__ inst, const float* __restrict__ beam, int* __restrict__ asym) {
   const InstDesc d = inst[blockIdx.y];
@@ -178,12 +164,6 @@ hipError_t launch_beamfit(const InstDesc* inst, int n_inst, const float* beam, d
 }
 
 static int sym_blocks(int max_N) { return std::max(1, std::min(256, max_N * max_N / 4096)); }
-
-hipError_t launch_beam_symmetrize(const InstDesc* inst, int n_inst, int max_N, float* beam, hipStream_t st) {
-  if (n_inst <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_beam_symmetrize, dim3(sym_blocks(max_N), n_inst), dim3(256), 0, st, inst, beam);
-  return hipGetLastError();
-}
 
 hipError_t launch_beam_symcheck(const InstDesc* inst, int n_inst, int max_N, const float* beam, int* asym,
                                 hipStream_t st) {

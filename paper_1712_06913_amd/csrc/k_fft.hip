@@ -19,6 +19,8 @@
 //           one contiguous block Yb[line_block][y][line % nl] over the same footprint;
 //   pass B  (k_fft_b_c2r): ny rows y per workgroup; rebuilds the Hermitian spectrum
 //           along u from the blocks, length-P FFT, real part, correction, normalisation.
+// The beam's grid is also real and even, which k_fft_a_real / k_fft_b_c2r_sym use to halve
+// its transform work and bytes (see there).
 // The adjoint runs the mirror image (k_fft_b_r2c then k_fft_a_fwd); mi_ifft2 uses
 // k_fft_c2c_t twice on full complex arrays.
 //
@@ -159,6 +161,13 @@ __device__ __forceinline__ int rows_per_block(int P) {
   return ny > P ? P : ny;
 }
 
+// Real lines per workgroup of the beam's pass A: two real lines share one complex FFT.
+template <int ELEMS>
+__device__ __forceinline__ int real_lines_per_block(int P) {
+  const int nr = 2 * ELEMS / P;
+  return nr > P / 2 ? P / 2 : nr;
+}
+
 constexpr int LDS_PADDED(int elems) { return elems + elems / 8; }
 // Two 512-thread workgroups of the small block share a CU (LDS 2 x 72 KB), which needs
 // 4 waves per SIMD, i.e. at most 128 VGPRs.
@@ -166,17 +175,16 @@ constexpr int LDS_PADDED(int elems) { return elems + elems / 8; }
 
 }  // namespace
 
-// Pass A (inverse): half-grid lines -> FFT along v -> contiguous block Yb[b][y][l].
+// Pass A (inverse, dirty grid): half-grid lines -> FFT along v -> contiguous block Yb[b][y][l].
 template <int ELEMS, int THREADS>
 __global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES_PER_EU(ELEMS))))
-k_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int beam,
-        double2* __restrict__ grid, Tables T) {
+k_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, double2* __restrict__ grid, Tables T) {
   __shared__ double2 buf[LDS_PADDED(ELEMS)];
   const FftWork wk = work[blockIdx.x];
   const InstDesc d = inst[wk.inst];
-  const int P = beam ? 2 * d.N : d.N, log2P = ilog2(P);
+  const int P = d.N, log2P = ilog2(P);
   const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
-  double2* blk = grid + (beam ? d.gb_off : d.gd_off) + (int64_t)wk.first * P;   // block start
+  double2* blk = grid + d.gd_off + (int64_t)wk.first * P;   // block start
   const int n = nl * P;
   for (int q = threadIdx.x; q < n; q += THREADS) buf[pd(q)] = blk[q];
   __syncthreads();
@@ -187,22 +195,21 @@ k_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int
   }
 }
 
-// Pass B (inverse, complex-to-real): rows y0..y0+ny-1 of the image, two rows per complex
+// Pass B (inverse, complex-to-real, dirty image): rows y0..y0+ny-1, two rows per complex
 // line: Z = X1 + i X2 with X1, X2 Hermitian along u, so Re IDFT(Z) and Im IDFT(Z) are the
 // two real rows.
 template <int ELEMS, int THREADS>
 __global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES_PER_EU(ELEMS))))
-k_fft_b_c2r(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int beam,
-            const double2* __restrict__ yb, const double* __restrict__ b0, Tables T,
+k_fft_b_c2r(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, const double2* __restrict__ yb, const double* __restrict__ b0, Tables T,
             float* __restrict__ out) {
   __shared__ double2 buf[LDS_PADDED(ELEMS)];
   const FftWork wk = work[blockIdx.x];
   const InstDesc d = inst[wk.inst];
-  const int P = beam ? 2 * d.N : d.N, log2P = ilog2(P), h = P / 2;
+  const int P = d.N, log2P = ilog2(P), h = P / 2;
   const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
   const int ny = rows_per_block<ELEMS>(P), nz = ny / 2;
   const int y0 = wk.first;
-  const double2* src = yb + (beam ? d.gb_off : d.gd_off);
+  const double2* src = yb + d.gd_off;
   // element (line k', row y) of the blocked layout: (k'/nl) nl P + y nl + k' % nl
   const int nblk = h / nl;
   const int per_blk = nz * nl;
@@ -223,10 +230,10 @@ k_fft_b_c2r(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
   for (int zl = threadIdx.x; zl < nz; zl += THREADS) buf[pd(zl << log2P)] = make_double2(0.0, 0.0);
   __syncthreads();
   lds_fft<ELEMS, THREADS>(buf, log2P, nz, +1.0, T.twiddle);
-  const double bd = b0[2 * wk.inst + (beam ? 1 : 0)];
+  const double bd = b0[2 * wk.inst];
   const double inv_b0 = bd > 0.0 ? 1.0 / bd : 0.0;
   const double* ic = T.inv_corr + (P - 64);
-  float* o = out + (beam ? d.beam_off : d.img_off) + (int64_t)y0 * P;
+  float* o = out + d.img_off + (int64_t)y0 * P;
   for (int q = threadIdx.x; q < ny * P; q += THREADS) {
     const int yl = q >> log2P, x = q & (P - 1);
     const int y = y0 + yl;
@@ -234,6 +241,117 @@ k_fft_b_c2r(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
     if ((x + y) & 1) s = -s;
     const double2 z = buf[pd(((yl >> 1) << log2P) + x)];
     o[q] = (float)(((yl & 1) ? z.y : z.x) * s);
+  }
+}
+
+// The beam: its grid is real and even (w K at the samples and their mirrors), so
+//  * each half-grid line g_k(v) is real, and its transform along v has Y_k(P - y) =
+//    conj Y_k(y): rows y = 0..P/2 carry everything, and Y_k(0), Y_k(P/2) are real;
+//  * the beam is point-symmetric about (P/2, P/2): B[P - y][x] = B[y][(P - x) mod P].
+// Pass A packs two real lines into one complex FFT and stores, per line, P/2 complex
+// slots (slot 0 = (Y(0), Y(P/2)), slot s = Y(s)) over the same footprint as its P real
+// inputs; pass B transforms rows 0..P/2 only and writes each of them twice, at y and
+// mirrored at P - y, so the stored beam is exactly symmetric.
+
+// Beam pass A: real half-grid lines -> FFT along v of line pairs -> separated spectra,
+// slots 0..P/2-1, blocked layout Yb[b][s][l] (complex, nr lines per block).
+template <int ELEMS, int THREADS>
+__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES_PER_EU(ELEMS))))
+k_fft_a_real(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, double* __restrict__ grid,
+             Tables T) {
+  __shared__ double2 buf[LDS_PADDED(ELEMS)];
+  const FftWork wk = work[blockIdx.x];
+  const InstDesc d = inst[wk.inst];
+  const int P = 2 * d.N, log2P = ilog2(P), h = P / 2;
+  const int nr = real_lines_per_block<ELEMS>(P), log2nr = ilog2(nr), nc = nr / 2;
+  double* blk = grid + d.gb_off + (int64_t)wk.first * P;     // nr real lines of P
+  for (int q = threadIdx.x; q < nc * P; q += THREADS) {
+    const int c = q >> log2P, v = q & (P - 1);
+    const double* a = blk + ((int64_t)(2 * c) << log2P) + v;
+    buf[pd(q)] = make_double2(a[0], a[P]);
+  }
+  __syncthreads();
+  lds_fft<ELEMS, THREADS>(buf, log2P, nc, +1.0, T.twiddle);
+  double2* out = reinterpret_cast<double2*>(blk);               // nr x P/2 complex, same bytes
+  for (int q = threadIdx.x; q < nr * h; q += THREADS) {
+    const int sl = q >> log2nr, l = q & (nr - 1);
+    const int row = (l >> 1) << log2P;
+    const double2 Z = buf[pd(row + sl)];
+    double2 y;
+    if (sl == 0) {
+      const double2 Zh = buf[pd(row + h)];
+      y = (l & 1) ? make_double2(Z.y, Zh.y) : make_double2(Z.x, Zh.x);
+    } else {
+      const double2 Zm = buf[pd(row + P - sl)];
+      // first line (Z + conj Zm) / 2, second line -i (Z - conj Zm) / 2
+      y = (l & 1) ? make_double2(0.5 * (Z.y + Zm.y), 0.5 * (Zm.x - Z.x))
+                  : make_double2(0.5 * (Z.x + Zm.x), 0.5 * (Z.y - Zm.y));
+    }
+    out[q] = y;
+  }
+}
+
+// Beam pass B: rows y0..y0+ny-1 (only those <= P/2) from the slots, Hermitian completion
+// along u, FFT, real part, correction, normalisation; row y is stored at y and, for
+// 0 < y < P/2, mirrored at P - y; the right half of row P/2 mirrors its left half.
+template <int ELEMS, int THREADS>
+__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES_PER_EU(ELEMS))))
+k_fft_b_c2r_sym(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
+                const double* __restrict__ grid, const double* __restrict__ b0, Tables T,
+                float* __restrict__ out) {
+  __shared__ double2 buf[LDS_PADDED(ELEMS)];
+  const FftWork wk = work[blockIdx.x];
+  const InstDesc d = inst[wk.inst];
+  const int P = 2 * d.N, log2P = ilog2(P), h = P / 2;
+  const int nr = real_lines_per_block<ELEMS>(P), log2nr = ilog2(nr);
+  const int ny = rows_per_block<ELEMS>(P), nz = ny / 2;
+  const int y0 = wk.first;
+  const double2* src = reinterpret_cast<const double2*>(grid + d.gb_off);
+  const int nblk = h / nr, per_blk = nz * nr;
+  for (int q = threadIdx.x; q < nblk * per_blk; q += THREADS) {
+    const int b = q / per_blk, r = q - b * per_blk;
+    const int zl = r >> log2nr, l = r & (nr - 1);
+    const int ya = y0 + 2 * zl;
+    const double2* e = src + (int64_t)b * nr * h + l;
+    // ya and P/2 are even, so row P/2 always starts a pair (and is the last row)
+    double2 v1, v2;
+    if (ya == 0) {                       // rows 0 and 1
+      v1 = make_double2(e[0].x, 0.0);
+      v2 = e[nr];
+    } else if (ya < h) {
+      v1 = e[ya * nr];
+      v2 = e[(ya + 1) * nr];
+    } else {                             // row P/2 alone, or past it
+      v1 = make_double2(ya == h ? e[0].y : 0.0, 0.0);
+      v2 = make_double2(0.0, 0.0);
+    }
+    const int k = b * nr + l + 1;        // u frequency index 1..P/2
+    const int row = zl << log2P;
+    if (k < h) {
+      buf[pd(row + k)] = make_double2(v1.x - v2.y, v1.y + v2.x);
+      buf[pd(row + P - k)] = make_double2(v1.x + v2.y, v2.x - v1.y);
+    } else {
+      buf[pd(row + k)] = make_double2(v1.x, v2.x);   // u = 0 column: real by symmetry
+    }
+  }
+  for (int zl = threadIdx.x; zl < nz; zl += THREADS) buf[pd(zl << log2P)] = make_double2(0.0, 0.0);
+  __syncthreads();
+  lds_fft<ELEMS, THREADS>(buf, log2P, nz, +1.0, T.twiddle);
+  const double bd = b0[2 * wk.inst + 1];
+  const double inv_b0 = bd > 0.0 ? 1.0 / bd : 0.0;
+  const double* ic = T.inv_corr + (P - 64);
+  float* o = out + d.beam_off;
+  const int nrow = min(ny, h + 1 - y0);
+  for (int q = threadIdx.x; q < nrow * P; q += THREADS) {
+    const int yl = q >> log2P, x = q & (P - 1);
+    const int y = y0 + yl;
+    const int xs = (y == h && x > h) ? P - x : x;
+    double s = ic[xs] * (ic[y] * inv_b0);
+    if ((xs + y) & 1) s = -s;
+    const double2 z = buf[pd(((yl >> 1) << log2P) + xs)];
+    const float f = (float)(((yl & 1) ? z.y : z.x) * s);
+    o[((int64_t)y << log2P) + x] = f;
+    if (y > 0 && y < h) o[((int64_t)(P - y) << log2P) + ((P - x) & (P - 1))] = f;
   }
 }
 
@@ -355,16 +473,28 @@ k_fft_c2c_t(const int* __restrict__ n_arr, const int64_t* __restrict__ offs, con
       hipLaunchKernelGGL((KERNEL<4096, 512>), dim3(n_work), dim3(512), 0, st, __VA_ARGS__);       \
   } while (0)
 
-hipError_t launch_fft_a(int elems, const InstDesc* inst, const FftWork* work, int n_work, int beam, double2* grid,
+hipError_t launch_fft_a(int elems, const InstDesc* inst, const FftWork* work, int n_work, double2* grid,
                         const Tables& T, hipStream_t st) {
   if (n_work <= 0) return hipSuccess;
-  MI_FFT_DISPATCH(k_fft_a, inst, work, beam, grid, T);
+  MI_FFT_DISPATCH(k_fft_a, inst, work, grid, T);
   return hipGetLastError();
 }
-hipError_t launch_fft_b_c2r(int elems, const InstDesc* inst, const FftWork* work, int n_work, int beam,
-                            const double2* yb, const double* b0, const Tables& T, float* out, hipStream_t st) {
+hipError_t launch_fft_b_c2r(int elems, const InstDesc* inst, const FftWork* work, int n_work, const double2* yb,
+                            const double* b0, const Tables& T, float* out, hipStream_t st) {
   if (n_work <= 0) return hipSuccess;
-  MI_FFT_DISPATCH(k_fft_b_c2r, inst, work, beam, yb, b0, T, out);
+  MI_FFT_DISPATCH(k_fft_b_c2r, inst, work, yb, b0, T, out);
+  return hipGetLastError();
+}
+hipError_t launch_fft_a_real(int elems, const InstDesc* inst, const FftWork* work, int n_work, double* grid,
+                             const Tables& T, hipStream_t st) {
+  if (n_work <= 0) return hipSuccess;
+  MI_FFT_DISPATCH(k_fft_a_real, inst, work, grid, T);
+  return hipGetLastError();
+}
+hipError_t launch_fft_b_c2r_sym(int elems, const InstDesc* inst, const FftWork* work, int n_work,
+                                const double* grid, const double* b0, const Tables& T, float* out, hipStream_t st) {
+  if (n_work <= 0) return hipSuccess;
+  MI_FFT_DISPATCH(k_fft_b_c2r_sym, inst, work, grid, b0, T, out);
   return hipGetLastError();
 }
 hipError_t launch_fft_b_r2c(int elems, const InstDesc* inst, const FftWork* work, int n_work, const float* img,

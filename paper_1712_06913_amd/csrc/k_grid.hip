@@ -207,6 +207,12 @@ constexpr int GRID_THREADS = 256;
 constexpr int GRID_CHUNK = 32;
 constexpr int GRID_EB = 256;
 
+// Grid cell stores: FP64 complex, complex64 (mi_grid output), or FP64 real (the beam grid,
+// whose imaginary part is zero).
+__device__ __forceinline__ void put_cell(double2* p, double2 v) { *p = v; }
+__device__ __forceinline__ void put_cell(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+__device__ __forceinline__ void put_cell(double* p, double2 v) { *p = v.x; }
+
 template <class OutT>
 __global__ void __launch_bounds__(GRID_THREADS)
 k_grid(const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst, int n_tiles, int beam,
@@ -243,12 +249,8 @@ k_grid(const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst, int
     const int n = __builtin_amdgcn_readfirstlane(m_cnt[tt]);
 
     if (n == 0) {  // empty tile: plain zero fill
-      for (int q = tid; q < TK * TJ; q += GRID_THREADS) {
-        OutT z;
-        z.x = 0;
-        z.y = 0;
-        out[(int64_t)(q / TJ) * P + (q % TJ)] = z;
-      }
+      for (int q = tid; q < TK * TJ; q += GRID_THREADS)
+        put_cell(out + (int64_t)(q / TJ) * P + (q % TJ), make_double2(0.0, 0.0));
       continue;
     }
     for (int q = tid; q < TK * TJ; q += GRID_THREADS) acc[q] = make_double2(0.0, 0.0);
@@ -299,10 +301,7 @@ k_grid(const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst, int
       const int l = q / TJ, jj = q % TJ;
       double2 val = acc[q];
       if (modulate && (((k0 + l + 1) + (j0 + jj)) & 1)) { val.x = -val.x; val.y = -val.y; }
-      OutT o;
-      o.x = val.x;
-      o.y = val.y;
-      out[(int64_t)l * P + jj] = o;
+      put_cell(out + (int64_t)l * P + jj, val);
     }
     __syncthreads();
   }
@@ -370,6 +369,12 @@ hipError_t launch_grid_f32(const InstDesc* inst, const int* tile_inst, int n_til
                            const int* tcount, const Tables& T, float2* grid, int modulate, hipStream_t st) {
   return launch_grid_t(inst, tile_inst, n_tiles, beam, vis, uv, w_in, wts, ent, tstart, tcount, T, grid, modulate,
                        st);
+}
+
+hipError_t launch_grid_real(const InstDesc* inst, const int* tile_inst, int n_tiles, const float2* uv,
+                            const float* w_in, const float* wts, const int* ent, const int* tstart, const int* tcount,
+                            const Tables& T, double* grid, hipStream_t st) {
+  return launch_grid_t(inst, tile_inst, n_tiles, 1, nullptr, uv, w_in, wts, ent, tstart, tcount, T, grid, 1, st);
 }
 
 hipError_t launch_expand_full(const InstDesc* inst, int n_inst, int beam, const double2* half, float2* full,

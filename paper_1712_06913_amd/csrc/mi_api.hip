@@ -37,9 +37,14 @@ hipError_t launch_grid_f32(const InstDesc*, const int*, int, int, const float2*,
                            hipStream_t);
 hipError_t launch_expand_full(const InstDesc*, int, int, const double2*, float2*, const int64_t*, hipStream_t);
 hipError_t launch_fill_u32(unsigned*, int64_t, unsigned, hipStream_t);
-hipError_t launch_fft_a(int, const InstDesc*, const FftWork*, int, int, double2*, const Tables&, hipStream_t);
-hipError_t launch_fft_b_c2r(int, const InstDesc*, const FftWork*, int, int, const double2*, const double*,
-                            const Tables&, float*, hipStream_t);
+hipError_t launch_grid_real(const InstDesc*, const int*, int, const float2*, const float*, const float*, const int*,
+                            const int*, const int*, const Tables&, double*, hipStream_t);
+hipError_t launch_fft_a(int, const InstDesc*, const FftWork*, int, double2*, const Tables&, hipStream_t);
+hipError_t launch_fft_b_c2r(int, const InstDesc*, const FftWork*, int, const double2*, const double*, const Tables&,
+                            float*, hipStream_t);
+hipError_t launch_fft_a_real(int, const InstDesc*, const FftWork*, int, double*, const Tables&, hipStream_t);
+hipError_t launch_fft_b_c2r_sym(int, const InstDesc*, const FftWork*, int, const double*, const double*,
+                                const Tables&, float*, hipStream_t);
 hipError_t launch_fft_b_r2c(int, const InstDesc*, const FftWork*, int, const float*, const Tables&, double2*,
                             hipStream_t);
 hipError_t launch_fft_a_fwd(int, const InstDesc*, const FftWork*, int, const Tables&, double2*, hipStream_t);
@@ -58,7 +63,6 @@ hipError_t launch_corr_mul(double2*, const double2*, int64_t, hipStream_t);
 hipError_t launch_corr_peak(const InstDesc*, int, const double2*, double*, hipStream_t);
 hipError_t launch_phase_shift(const InstDesc*, int, int, float2*, const float2*, const double*, hipStream_t);
 hipError_t launch_beam_symcheck(const InstDesc*, int, int, const float*, int*, hipStream_t);
-hipError_t launch_beam_symmetrize(const InstDesc*, int, int, float*, hipStream_t);
 hipError_t launch_degrid(const InstDesc*, int, int, const float2*, const float*, const float*, const double*,
                          const double2*, const Tables&, int, float2*, hipStream_t);
 
@@ -68,6 +72,11 @@ int fft_elems_for(int P) { return P > FFT_ELEMS_SMALL ? FFT_ELEMS_LARGE : FFT_EL
 int fft_lines_per_block_host(int P, int elems) {
   int nl = elems / P;
   return nl > P / 2 ? P / 2 : nl;
+}
+// Real lines per workgroup of the beam's pass A (two real lines per complex line).
+int fft_real_lines_per_block_host(int P, int elems) {
+  int nr = 2 * elems / P;
+  return nr > P / 2 ? P / 2 : nr;
 }
 // Image rows per workgroup of the real-valued passes (two rows per complex line).
 int fft_rows_per_block_host(int P, int elems) {
@@ -155,7 +164,9 @@ struct Plan {
   int elems_d = FFT_ELEMS_SMALL, elems_b = FFT_ELEMS_SMALL;
   DevBuf inst, tile_inst_d, tile_inst_b, wa_d, wb_d, wa_b, wb_b;
   // workspace
-  DevBuf wts, b0, nkept, cnt, ent_d, ent_b, ts_d, tc_d, ts_b, tc_b, gd, gb, status_ws, full_off;
+  // gd: dirty half grids (FP64 complex); gbr: beam half grids (FP64 real), then the beam's
+  // transform slots in place; gb: FP64 complex beam grids for mi_grid's full layout
+  DevBuf wts, b0, nkept, cnt, ent_d, ent_b, ts_d, tc_d, ts_b, tc_b, gd, gbr, gb, status_ws, full_off;
   std::map<uint64_t, std::unique_ptr<CleanPlan>> cleans;
   // disk centering: radii (host copy for change detection), 2-D transform work list, buffers
   std::vector<double> radius;
@@ -284,12 +295,12 @@ Plan* get_plan(mi_ctx* ctx, const mi_batch* b) {
     max_tiles = std::max(max_tiles, std::max(ntd, ntb));
     for (int t = 0; t < ntd; ++t) tile_inst_d.push_back(i);
     for (int t = 0; t < ntb; ++t) tile_inst_b.push_back(i);
-    const int nld = fft_lines_per_block_host(N, P->elems_d), nlb = fft_lines_per_block_host(2 * N, P->elems_b);
+    const int nld = fft_lines_per_block_host(N, P->elems_d), nrb = fft_real_lines_per_block_host(2 * N, P->elems_b);
     const int nyd = fft_rows_per_block_host(N, P->elems_d), nyb = fft_rows_per_block_host(2 * N, P->elems_b);
     for (int l = 0; l < N / 2; l += nld) wa_d.push_back({i, l});
     for (int y = 0; y < N; y += nyd) wb_d.push_back({i, y});
-    for (int l = 0; l < N; l += nlb) wa_b.push_back({i, l});
-    for (int y = 0; y < 2 * N; y += nyb) wb_b.push_back({i, y});
+    for (int l = 0; l < N; l += nrb) wa_b.push_back({i, l});        // beam: N real lines
+    for (int y = 0; y <= N; y += nyb) wb_b.push_back({i, y});       // beam: rows 0..N
     P->max_N = std::max(P->max_N, N);
     P->max_nvis = std::max(P->max_nvis, d.n_vis);
   }
@@ -351,20 +362,27 @@ void run_grid(mi_ctx* ctx, Plan* P, const mi_c64* vis, const float* uv, const fl
                            tc, ctx->T, out, modulate, st));
 }
 
-void run_image(mi_ctx* ctx, Plan* P, bool beam, float* out, hipStream_t st) {
+// Dirty images from the dirty half grids in P->gd.
+void run_image(mi_ctx* ctx, Plan* P, float* out, hipStream_t st) {
   const InstDesc* inst = static_cast<const InstDesc*>(P->inst.p);
-  double2* g = beam ? static_cast<double2*>(P->gb.p) : static_cast<double2*>(P->gd.p);
+  double2* g = static_cast<double2*>(P->gd.p);
   const double* b0 = static_cast<const double*>(P->b0.p);
-  if (!beam) {
-    HIPCHK(launch_fft_a(P->elems_d, inst, static_cast<const FftWork*>(P->wa_d.p), P->n_wa_d, 0, g, ctx->T, st));
-    HIPCHK(launch_fft_b_c2r(P->elems_d, inst, static_cast<const FftWork*>(P->wb_d.p), P->n_wb_d, 0, g, b0, ctx->T,
-                            out, st));
-  } else {
-    HIPCHK(launch_fft_a(P->elems_b, inst, static_cast<const FftWork*>(P->wa_b.p), P->n_wa_b, 1, g, ctx->T, st));
-    HIPCHK(launch_fft_b_c2r(P->elems_b, inst, static_cast<const FftWork*>(P->wb_b.p), P->n_wb_b, 1, g, b0, ctx->T,
-                            out, st));
-    HIPCHK(launch_beam_symmetrize(inst, P->n_inst, P->max_N, out, st));
-  }
+  HIPCHK(launch_fft_a(P->elems_d, inst, static_cast<const FftWork*>(P->wa_d.p), P->n_wa_d, g, ctx->T, st));
+  HIPCHK(launch_fft_b_c2r(P->elems_d, inst, static_cast<const FftWork*>(P->wb_d.p), P->n_wb_d, g, b0, ctx->T, out,
+                          st));
+}
+
+// Beams: real FP64 beam grid (gridder), then the two symmetric transform passes.
+void run_beam(mi_ctx* ctx, Plan* P, const float* uv, const float* w_in, float* out, hipStream_t st) {
+  const InstDesc* inst = static_cast<const InstDesc*>(P->inst.p);
+  double* g = dev_alloc<double>(P->gbr, P->total_gb);
+  HIPCHK(launch_grid_real(inst, static_cast<const int*>(P->tile_inst_b.p), P->tiles_b,
+                          reinterpret_cast<const float2*>(uv), w_in, static_cast<const float*>(P->wts.p),
+                          static_cast<const int*>(P->ent_b.p), static_cast<const int*>(P->ts_b.p),
+                          static_cast<const int*>(P->tc_b.p), ctx->T, g, st));
+  HIPCHK(launch_fft_a_real(P->elems_b, inst, static_cast<const FftWork*>(P->wa_b.p), P->n_wa_b, g, ctx->T, st));
+  HIPCHK(launch_fft_b_c2r_sym(P->elems_b, inst, static_cast<const FftWork*>(P->wb_b.p), P->n_wb_b, g,
+                              static_cast<const double*>(P->b0.p), ctx->T, out, st));
 }
 
 // CLEAN schedule for one batch.  Every image size N gets its own team size G(N), the
@@ -817,12 +835,8 @@ mi_status mi_dirty_image(mi_ctx* ctx, const mi_batch* batch, const mi_c64* vis, 
     run_bin(ctx, P, batch, uv, w_in, beam, stream);
     double2* gd = dev_alloc<double2>(P->gd, P->total_gd);
     run_grid<double2>(ctx, P, vis, uv, w_in, false, gd, 1, stream);
-    run_image(ctx, P, false, dirty_out, stream);
-    if (beam) {
-      double2* gb = dev_alloc<double2>(P->gb, P->total_gb);
-      run_grid<double2>(ctx, P, vis, uv, w_in, true, gb, 1, stream);
-      run_image(ctx, P, true, beam_out, stream);
-    }
+    run_image(ctx, P, dirty_out, stream);
+    if (beam) run_beam(ctx, P, uv, w_in, beam_out, stream);
     copy_b0(P, b0_out, stream);
   });
 }
@@ -836,9 +850,7 @@ mi_status mi_dirty_beam(mi_ctx* ctx, const mi_batch* batch, const float* uv, con
     HIPCHK(hipSetDevice(ctx->device));
     Plan* P = get_plan(ctx, batch);
     run_bin(ctx, P, batch, uv, w_in, true, stream);
-    double2* gb = dev_alloc<double2>(P->gb, P->total_gb);
-    run_grid<double2>(ctx, P, nullptr, uv, w_in, true, gb, 1, stream);
-    run_image(ctx, P, true, beam_out, stream);
+    run_beam(ctx, P, uv, w_in, beam_out, stream);
   });
 }
 

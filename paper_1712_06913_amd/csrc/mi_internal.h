@@ -34,7 +34,7 @@ struct InstDesc {
   int64_t img_off;     // N*N image offset (floats)
   int64_t beam_off;    // (2N)^2 beam offset (floats)
   int64_t gd_off;      // dirty half grid offset (complex): N/2 * N
-  int64_t gb_off;      // beam half grid offset (complex): N * 2N
+  int64_t gb_off;      // beam half grid offset (elements): N * 2N per instance
   int64_t ent_off;     // entry-list offset (ENT_PER_VIS * n_vis per instance)
   int64_t cnt_off;     // uniform-weight count scratch offset (floats, N*N) or -1
   double scale;        // N * dl = 1 / du (u in wavelengths -> cells)
