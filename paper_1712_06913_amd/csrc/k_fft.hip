@@ -25,6 +25,8 @@
 // k_fft_c2c_t twice on full complex arrays.
 //
 // Twiddles come from a table exp(+2 pi i t / 8192) computed on the host in FP64.
+#include <algorithm>
+
 #include "mi_internal.h"
 
 namespace mi {
@@ -77,7 +79,8 @@ template <> __device__ __forceinline__ void small_dft<8>(double2* x, double s) {
 }
 
 // LDS index with one padding element per 8: strided butterfly stores of 16-byte elements
-// otherwise land on the same banks.
+// otherwise land on the same banks.  (A further element per line, against conflicts in
+// the staging and the transposed stores, measured slower overall.)
 __device__ __forceinline__ int pd(int i) { return i + (i >> 3); }
 
 // One Stockham radix-R pass over nl lines of P points held in LDS (line stride P).
@@ -175,72 +178,133 @@ constexpr int LDS_PADDED(int elems) { return elems + elems / 8; }
 
 }  // namespace
 
+// The four inverse passes below are persistent: a workgroup takes work items w =
+// blockIdx.x, blockIdx.x + gridDim.x, ... and issues the global loads of its next item into
+// registers as soon as the current one is staged in LDS, so those loads are in flight
+// during the transform and the stores (LDS barriers do not wait for global loads).
+
 // Pass A (inverse, dirty grid): half-grid lines -> FFT along v -> contiguous block Yb[b][y][l].
 template <int ELEMS, int THREADS>
 __global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES_PER_EU(ELEMS))))
-k_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, double2* __restrict__ grid, Tables T) {
+k_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int n_work, double2* grid, Tables T) {
   __shared__ double2 buf[LDS_PADDED(ELEMS)];
-  const FftWork wk = work[blockIdx.x];
-  const InstDesc d = inst[wk.inst];
-  const int P = d.N, log2P = ilog2(P);
-  const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
-  double2* blk = grid + d.gd_off + (int64_t)wk.first * P;   // block start
-  const int n = nl * P;
-  for (int q = threadIdx.x; q < n; q += THREADS) buf[pd(q)] = blk[q];
-  __syncthreads();
-  lds_fft<ELEMS, THREADS>(buf, log2P, nl, +1.0, T.twiddle);
-  for (int q = threadIdx.x; q < n; q += THREADS) {
-    const int y = q >> log2nl, l = q & (nl - 1);
-    blk[q] = buf[pd((l << log2P) + y)];
+  constexpr int NPT = ELEMS / THREADS;
+  double2 r[NPT];
+  auto fetch = [&](int wi) {
+    const FftWork wk = work[wi];
+    const InstDesc d = inst[wk.inst];
+    const int P = d.N, n = lines_per_block<ELEMS>(P) * P;
+    const double2* blk = grid + d.gd_off + (int64_t)wk.first * P;
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int q = threadIdx.x + i * THREADS;
+      if (q < n) {
+        const double2 v = blk[q];
+        r[i] = make_double2(v.x, v.y);   // component copy keeps r[] in registers
+      }
+    }
+  };
+  int w = blockIdx.x;
+  if (w < n_work) fetch(w);
+  for (; w < n_work; w += gridDim.x) {
+    const FftWork wk = work[w];
+    const InstDesc d = inst[wk.inst];
+    const int P = d.N, log2P = ilog2(P);
+    const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
+    const int n = nl * P;
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int q = threadIdx.x + i * THREADS;
+      if (q < n) buf[pd(q)] = r[i];
+    }
+    __syncthreads();
+    if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
+    lds_fft<ELEMS, THREADS>(buf, log2P, nl, +1.0, T.twiddle);
+    double2* blk = grid + d.gd_off + (int64_t)wk.first * P;
+    for (int q = threadIdx.x; q < n; q += THREADS) {
+      const int y = q >> log2nl, l = q & (nl - 1);
+      blk[q] = buf[pd((l << log2P) + y)];
+    }
+    __syncthreads();
   }
 }
 
 // Pass B (inverse, complex-to-real, dirty image): rows y0..y0+ny-1, two rows per complex
 // line: Z = X1 + i X2 with X1, X2 Hermitian along u, so Re IDFT(Z) and Im IDFT(Z) are the
-// two real rows.
+// two real rows.  Element (line k', row y) of the blocked layout is at
+// (k'/nl) nl P + y nl + k' % nl.
 template <int ELEMS, int THREADS>
 __global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES_PER_EU(ELEMS))))
-k_fft_b_c2r(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, const double2* __restrict__ yb, const double* __restrict__ b0, Tables T,
-            float* __restrict__ out) {
+k_fft_b_c2r(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int n_work,
+            const double2* __restrict__ yb, const double* __restrict__ b0, Tables T, float* __restrict__ out) {
   __shared__ double2 buf[LDS_PADDED(ELEMS)];
-  const FftWork wk = work[blockIdx.x];
-  const InstDesc d = inst[wk.inst];
-  const int P = d.N, log2P = ilog2(P), h = P / 2;
-  const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
-  const int ny = rows_per_block<ELEMS>(P), nz = ny / 2;
-  const int y0 = wk.first;
-  const double2* src = yb + d.gd_off;
-  // element (line k', row y) of the blocked layout: (k'/nl) nl P + y nl + k' % nl
-  const int nblk = h / nl;
-  const int per_blk = nz * nl;
-  for (int q = threadIdx.x; q < nblk * per_blk; q += THREADS) {
-    const int b = q / per_blk, r = q - b * per_blk;
-    const int zl = r >> log2nl, l = r & (nl - 1);
-    const int64_t e = (int64_t)b * nl * P + (int64_t)(y0 + 2 * zl) * nl + l;
-    const double2 v1 = src[e], v2 = src[e + nl];
-    const int k = b * nl + l + 1;          // u frequency index 1..P/2
-    const int row = zl << log2P;
-    if (k < h) {
-      buf[pd(row + k)] = make_double2(v1.x - v2.y, v1.y + v2.x);
-      buf[pd(row + P - k)] = make_double2(v1.x + v2.y, v2.x - v1.y);
-    } else {
-      buf[pd(row + k)] = make_double2(v1.x, v2.x);   // u = 0 column: real by symmetry
+  constexpr int NPT = ELEMS / 2 / THREADS;
+  double2 r1[NPT], r2[NPT];
+  auto fetch = [&](int wi) {
+    const FftWork wk = work[wi];
+    const InstDesc d = inst[wk.inst];
+    const int P = d.N, h = P / 2;
+    const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
+    const int nz = rows_per_block<ELEMS>(P) / 2, log2pb = ilog2(nz * nl);
+    const double2* src = yb + d.gd_off;
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int q = threadIdx.x + i * THREADS;
+      if (q < h * nz) {
+        const int b = q >> log2pb, r = q & ((1 << log2pb) - 1);
+        const int zl = r >> log2nl, l = r & (nl - 1);
+        const int64_t e = (int64_t)b * nl * P + (int64_t)(wk.first + 2 * zl) * nl + l;
+        const double2 v1 = src[e], v2 = src[e + nl];
+        r1[i] = make_double2(v1.x, v1.y);
+        r2[i] = make_double2(v2.x, v2.y);
+      }
     }
-  }
-  for (int zl = threadIdx.x; zl < nz; zl += THREADS) buf[pd(zl << log2P)] = make_double2(0.0, 0.0);
-  __syncthreads();
-  lds_fft<ELEMS, THREADS>(buf, log2P, nz, +1.0, T.twiddle);
-  const double bd = b0[2 * wk.inst];
-  const double inv_b0 = bd > 0.0 ? 1.0 / bd : 0.0;
-  const double* ic = T.inv_corr + (P - 64);
-  float* o = out + d.img_off + (int64_t)y0 * P;
-  for (int q = threadIdx.x; q < ny * P; q += THREADS) {
-    const int yl = q >> log2P, x = q & (P - 1);
-    const int y = y0 + yl;
-    double s = ic[x] * (ic[y] * inv_b0);
-    if ((x + y) & 1) s = -s;
-    const double2 z = buf[pd(((yl >> 1) << log2P) + x)];
-    o[q] = (float)(((yl & 1) ? z.y : z.x) * s);
+  };
+  int w = blockIdx.x;
+  if (w < n_work) fetch(w);
+  for (; w < n_work; w += gridDim.x) {
+    const FftWork wk = work[w];
+    const InstDesc d = inst[wk.inst];
+    const int P = d.N, log2P = ilog2(P), h = P / 2;
+    const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
+    const int ny = rows_per_block<ELEMS>(P), nz = ny / 2, log2pb = ilog2(nz * nl);
+    const int y0 = wk.first;
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int q = threadIdx.x + i * THREADS;
+      if (q < h * nz) {
+        const int b = q >> log2pb, r = q & ((1 << log2pb) - 1);
+        const int zl = r >> log2nl, l = r & (nl - 1);
+        const double2 v1 = r1[i], v2 = r2[i];
+        const int k = b * nl + l + 1;          // u frequency index 1..P/2
+        const int row = zl << log2P;
+        if (k < h) {
+          buf[pd(row + k)] = make_double2(v1.x - v2.y, v1.y + v2.x);
+          buf[pd(row + P - k)] = make_double2(v1.x + v2.y, v2.x - v1.y);
+        } else {
+          buf[pd(row + k)] = make_double2(v1.x, v2.x);   // u = 0 column: real by symmetry
+        }
+      }
+    }
+    for (int zl = threadIdx.x; zl < nz; zl += THREADS) buf[pd(zl << log2P)] = make_double2(0.0, 0.0);
+    __syncthreads();
+    if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
+    lds_fft<ELEMS, THREADS>(buf, log2P, nz, +1.0, T.twiddle);
+    const double bd = b0[2 * wk.inst];
+    const double inv_b0 = bd > 0.0 ? 1.0 / bd : 0.0;
+    const double* ic = T.inv_corr + (P - 64);
+    float* o = out + d.img_off + (int64_t)y0 * P;
+    for (int q = threadIdx.x; q < nz * P; q += THREADS) {   // rows y0 + 2 zl and y0 + 2 zl + 1
+      const int zl = q >> log2P, x = q & (P - 1);
+      const int y = y0 + 2 * zl;
+      double s0 = ic[x] * (ic[y] * inv_b0), s1 = ic[x] * (ic[y + 1] * inv_b0);
+      if ((x + y) & 1) s0 = -s0;
+      else s1 = -s1;
+      const double2 z = buf[pd(q)];
+      o[((2 * zl) << log2P) + x] = (float)(z.x * s0);
+      o[((2 * zl + 1) << log2P) + x] = (float)(z.y * s1);
+    }
+    __syncthreads();
   }
 }
 
@@ -257,37 +321,68 @@ k_fft_b_c2r(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
 // slots 0..P/2-1, blocked layout Yb[b][s][l] (complex, nr lines per block).
 template <int ELEMS, int THREADS>
 __global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES_PER_EU(ELEMS))))
-k_fft_a_real(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, double* __restrict__ grid,
+k_fft_a_real(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int n_work, double* grid,
              Tables T) {
   __shared__ double2 buf[LDS_PADDED(ELEMS)];
-  const FftWork wk = work[blockIdx.x];
-  const InstDesc d = inst[wk.inst];
-  const int P = 2 * d.N, log2P = ilog2(P), h = P / 2;
-  const int nr = real_lines_per_block<ELEMS>(P), log2nr = ilog2(nr), nc = nr / 2;
-  double* blk = grid + d.gb_off + (int64_t)wk.first * P;     // nr real lines of P
-  for (int q = threadIdx.x; q < nc * P; q += THREADS) {
-    const int c = q >> log2P, v = q & (P - 1);
-    const double* a = blk + ((int64_t)(2 * c) << log2P) + v;
-    buf[pd(q)] = make_double2(a[0], a[P]);
-  }
-  __syncthreads();
-  lds_fft<ELEMS, THREADS>(buf, log2P, nc, +1.0, T.twiddle);
-  double2* out = reinterpret_cast<double2*>(blk);               // nr x P/2 complex, same bytes
-  for (int q = threadIdx.x; q < nr * h; q += THREADS) {
-    const int sl = q >> log2nr, l = q & (nr - 1);
-    const int row = (l >> 1) << log2P;
-    const double2 Z = buf[pd(row + sl)];
-    double2 y;
-    if (sl == 0) {
-      const double2 Zh = buf[pd(row + h)];
-      y = (l & 1) ? make_double2(Z.y, Zh.y) : make_double2(Z.x, Zh.x);
-    } else {
-      const double2 Zm = buf[pd(row + P - sl)];
-      // first line (Z + conj Zm) / 2, second line -i (Z - conj Zm) / 2
-      y = (l & 1) ? make_double2(0.5 * (Z.y + Zm.y), 0.5 * (Zm.x - Z.x))
-                  : make_double2(0.5 * (Z.x + Zm.x), 0.5 * (Z.y - Zm.y));
+  constexpr int NPT = ELEMS / THREADS / 2;       // pairs of consecutive v per thread
+  double2 ra[NPT], rb[NPT];
+  auto fetch = [&](int wi) {
+    const FftWork wk = work[wi];
+    const InstDesc d = inst[wk.inst];
+    const int P = 2 * d.N, log2P = ilog2(P);
+    const int nc = real_lines_per_block<ELEMS>(P) / 2;
+    const double* blk = grid + d.gb_off + (int64_t)wk.first * P;     // nr real lines of P
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int q = threadIdx.x + i * THREADS;      // pair index: line pair c, v = 2 (q % (P/2))
+      if (q < nc * P / 2) {
+        const int c = q >> (log2P - 1), v = 2 * (q & (P / 2 - 1));
+        const double2* a = reinterpret_cast<const double2*>(blk + ((int64_t)(2 * c) << log2P) + v);
+        const double2 x = a[0], y = a[P / 2];
+        ra[i] = make_double2(x.x, x.y);
+        rb[i] = make_double2(y.x, y.y);
+      }
     }
-    out[q] = y;
+  };
+  int w = blockIdx.x;
+  if (w < n_work) fetch(w);
+  for (; w < n_work; w += gridDim.x) {
+    const FftWork wk = work[w];
+    const InstDesc d = inst[wk.inst];
+    const int P = 2 * d.N, log2P = ilog2(P), h = P / 2;
+    const int nr = real_lines_per_block<ELEMS>(P), log2nr = ilog2(nr), nc = nr / 2;
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int q = threadIdx.x + i * THREADS;
+      if (q < nc * P / 2) {
+        buf[pd(2 * q)] = make_double2(ra[i].x, rb[i].x);
+        buf[pd(2 * q + 1)] = make_double2(ra[i].y, rb[i].y);
+      }
+    }
+    __syncthreads();
+    if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
+    lds_fft<ELEMS, THREADS>(buf, log2P, nc, +1.0, T.twiddle);
+    double2* o = reinterpret_cast<double2*>(grid + d.gb_off + (int64_t)wk.first * P);   // nr x P/2 complex
+    const int log2nc = log2nr - 1;
+    for (int q = threadIdx.x; q < nc * h; q += THREADS) {   // slot sl of lines 2c and 2c + 1
+      const int sl = q >> log2nc, c = q & (nc - 1);
+      const int row = c << log2P;
+      const double2 Z = buf[pd(row + sl)];
+      double2 ya, yb;
+      if (sl == 0) {
+        const double2 Zh = buf[pd(row + h)];
+        ya = make_double2(Z.x, Zh.x);
+        yb = make_double2(Z.y, Zh.y);
+      } else {
+        const double2 Zm = buf[pd(row + P - sl)];
+        // first line (Z + conj Zm) / 2, second line -i (Z - conj Zm) / 2
+        ya = make_double2(0.5 * (Z.x + Zm.x), 0.5 * (Z.y - Zm.y));
+        yb = make_double2(0.5 * (Z.y + Zm.y), 0.5 * (Zm.x - Z.x));
+      }
+      o[(sl << log2nr) + 2 * c] = ya;
+      o[(sl << log2nr) + 2 * c + 1] = yb;
+    }
+    __syncthreads();
   }
 }
 
@@ -296,62 +391,101 @@ k_fft_a_real(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work
 // 0 < y < P/2, mirrored at P - y; the right half of row P/2 mirrors its left half.
 template <int ELEMS, int THREADS>
 __global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES_PER_EU(ELEMS))))
-k_fft_b_c2r_sym(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
+k_fft_b_c2r_sym(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int n_work,
                 const double* __restrict__ grid, const double* __restrict__ b0, Tables T,
                 float* __restrict__ out) {
   __shared__ double2 buf[LDS_PADDED(ELEMS)];
-  const FftWork wk = work[blockIdx.x];
-  const InstDesc d = inst[wk.inst];
-  const int P = 2 * d.N, log2P = ilog2(P), h = P / 2;
-  const int nr = real_lines_per_block<ELEMS>(P), log2nr = ilog2(nr);
-  const int ny = rows_per_block<ELEMS>(P), nz = ny / 2;
-  const int y0 = wk.first;
-  const double2* src = reinterpret_cast<const double2*>(grid + d.gb_off);
-  const int nblk = h / nr, per_blk = nz * nr;
-  for (int q = threadIdx.x; q < nblk * per_blk; q += THREADS) {
-    const int b = q / per_blk, r = q - b * per_blk;
-    const int zl = r >> log2nr, l = r & (nr - 1);
-    const int ya = y0 + 2 * zl;
-    const double2* e = src + (int64_t)b * nr * h + l;
-    // ya and P/2 are even, so row P/2 always starts a pair (and is the last row)
-    double2 v1, v2;
-    if (ya == 0) {                       // rows 0 and 1
-      v1 = make_double2(e[0].x, 0.0);
-      v2 = e[nr];
-    } else if (ya < h) {
-      v1 = e[ya * nr];
-      v2 = e[(ya + 1) * nr];
-    } else {                             // row P/2 alone, or past it
-      v1 = make_double2(ya == h ? e[0].y : 0.0, 0.0);
-      v2 = make_double2(0.0, 0.0);
+  constexpr int NPT = ELEMS / 2 / THREADS;
+  double2 r1[NPT], r2[NPT];
+  auto fetch = [&](int wi) {
+    const FftWork wk = work[wi];
+    const InstDesc d = inst[wk.inst];
+    const int P = 2 * d.N, h = P / 2;
+    const int nr = real_lines_per_block<ELEMS>(P), log2nr = ilog2(nr);
+    const int nz = rows_per_block<ELEMS>(P) / 2, log2pb = ilog2(nz * nr);
+    const double2* src = reinterpret_cast<const double2*>(grid + d.gb_off);
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int q = threadIdx.x + i * THREADS;
+      if (q < h * nz) {
+        const int b = q >> log2pb, r = q & ((1 << log2pb) - 1);
+        const int zl = r >> log2nr, l = r & (nr - 1);
+        const int ya = wk.first + 2 * zl;
+        const double2* e = src + (int64_t)b * nr * h + l;
+        // ya and P/2 are even, so row P/2 always starts a pair (and is the last row)
+        double2 v1, v2;
+        if (ya == 0) {                       // rows 0 and 1
+          v1 = make_double2(e[0].x, 0.0);
+          v2 = e[nr];
+        } else if (ya < h) {
+          v1 = e[ya * nr];
+          v2 = e[(ya + 1) * nr];
+        } else {                             // row P/2 alone, or past it
+          v1 = make_double2(ya == h ? e[0].y : 0.0, 0.0);
+          v2 = make_double2(0.0, 0.0);
+        }
+        r1[i] = make_double2(v1.x, v1.y);
+        r2[i] = make_double2(v2.x, v2.y);
+      }
     }
-    const int k = b * nr + l + 1;        // u frequency index 1..P/2
-    const int row = zl << log2P;
-    if (k < h) {
-      buf[pd(row + k)] = make_double2(v1.x - v2.y, v1.y + v2.x);
-      buf[pd(row + P - k)] = make_double2(v1.x + v2.y, v2.x - v1.y);
-    } else {
-      buf[pd(row + k)] = make_double2(v1.x, v2.x);   // u = 0 column: real by symmetry
+  };
+  int w = blockIdx.x;
+  if (w < n_work) fetch(w);
+  for (; w < n_work; w += gridDim.x) {
+    const FftWork wk = work[w];
+    const InstDesc d = inst[wk.inst];
+    const int P = 2 * d.N, log2P = ilog2(P), h = P / 2;
+    const int nr = real_lines_per_block<ELEMS>(P), log2nr = ilog2(nr);
+    const int ny = rows_per_block<ELEMS>(P), nz = ny / 2, log2pb = ilog2(nz * nr);
+    const int y0 = wk.first;
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int q = threadIdx.x + i * THREADS;
+      if (q < h * nz) {
+        const int b = q >> log2pb, r = q & ((1 << log2pb) - 1);
+        const int zl = r >> log2nr, l = r & (nr - 1);
+        const double2 v1 = r1[i], v2 = r2[i];
+        const int k = b * nr + l + 1;        // u frequency index 1..P/2
+        const int row = zl << log2P;
+        if (k < h) {
+          buf[pd(row + k)] = make_double2(v1.x - v2.y, v1.y + v2.x);
+          buf[pd(row + P - k)] = make_double2(v1.x + v2.y, v2.x - v1.y);
+        } else {
+          buf[pd(row + k)] = make_double2(v1.x, v2.x);   // u = 0 column: real by symmetry
+        }
+      }
     }
-  }
-  for (int zl = threadIdx.x; zl < nz; zl += THREADS) buf[pd(zl << log2P)] = make_double2(0.0, 0.0);
-  __syncthreads();
-  lds_fft<ELEMS, THREADS>(buf, log2P, nz, +1.0, T.twiddle);
-  const double bd = b0[2 * wk.inst + 1];
-  const double inv_b0 = bd > 0.0 ? 1.0 / bd : 0.0;
-  const double* ic = T.inv_corr + (P - 64);
-  float* o = out + d.beam_off;
-  const int nrow = min(ny, h + 1 - y0);
-  for (int q = threadIdx.x; q < nrow * P; q += THREADS) {
-    const int yl = q >> log2P, x = q & (P - 1);
-    const int y = y0 + yl;
-    const int xs = (y == h && x > h) ? P - x : x;
-    double s = ic[xs] * (ic[y] * inv_b0);
-    if ((xs + y) & 1) s = -s;
-    const double2 z = buf[pd(((yl >> 1) << log2P) + xs)];
-    const float f = (float)(((yl & 1) ? z.y : z.x) * s);
-    o[((int64_t)y << log2P) + x] = f;
-    if (y > 0 && y < h) o[((int64_t)(P - y) << log2P) + ((P - x) & (P - 1))] = f;
+    for (int zl = threadIdx.x; zl < nz; zl += THREADS) buf[pd(zl << log2P)] = make_double2(0.0, 0.0);
+    __syncthreads();
+    if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
+    lds_fft<ELEMS, THREADS>(buf, log2P, nz, +1.0, T.twiddle);
+    const double bd = b0[2 * wk.inst + 1];
+    const double inv_b0 = bd > 0.0 ? 1.0 / bd : 0.0;
+    const double* ic = T.inv_corr + (P - 64);
+    float* o = out + d.beam_off;
+    const int npair = (min(ny, h + 1 - y0) + 1) / 2;
+    for (int q = threadIdx.x; q < npair * P; q += THREADS) {   // rows ya = y0 + 2 zl and ya + 1
+      const int zl = q >> log2P, x = q & (P - 1);
+      const int ya = y0 + 2 * zl;
+      if (ya == h) {                       // row P/2: its right half mirrors its left half
+        const int xs = x > h ? P - x : x;
+        double s = ic[xs] * (ic[ya] * inv_b0);
+        if ((xs + ya) & 1) s = -s;
+        o[(ya << log2P) + x] = (float)(buf[pd((zl << log2P) + xs)].x * s);
+        continue;
+      }
+      double s0 = ic[x] * (ic[ya] * inv_b0), s1 = ic[x] * (ic[ya + 1] * inv_b0);
+      if ((x + ya) & 1) s0 = -s0;
+      else s1 = -s1;
+      const double2 z = buf[pd(q)];
+      const float f0 = (float)(z.x * s0), f1 = (float)(z.y * s1);
+      const int xm = (P - x) & (P - 1);
+      o[(ya << log2P) + x] = f0;
+      if (ya > 0) o[((P - ya) << log2P) + xm] = f0;
+      o[((ya + 1) << log2P) + x] = f1;     // 0 < ya + 1 < P/2: always mirrored
+      o[((P - ya - 1) << log2P) + xm] = f1;
+    }
+    __syncthreads();
   }
 }
 
@@ -473,28 +607,45 @@ k_fft_c2c_t(const int* __restrict__ n_arr, const int64_t* __restrict__ offs, con
       hipLaunchKernelGGL((KERNEL<4096, 512>), dim3(n_work), dim3(512), 0, st, __VA_ARGS__);       \
   } while (0)
 
-hipError_t launch_fft_a(int elems, const InstDesc* inst, const FftWork* work, int n_work, double2* grid,
+// Persistent passes: as many workgroups as are resident at once (or fewer items).
+template <class Kern>
+int resident_grid(Kern k, int threads, int n_work, int n_cu) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  return std::min(n_work, per_cu * n_cu);
+}
+#define MI_FFT_PERSISTENT(KERNEL, ...)                                                                    \
+  do {                                                                                                    \
+    if (elems == 8192)                                                                                    \
+      hipLaunchKernelGGL((KERNEL<8192, 512>), dim3(resident_grid(KERNEL<8192, 512>, 512, n_work, n_cu)),  \
+                         dim3(512), 0, st, __VA_ARGS__);                                                  \
+    else                                                                                                  \
+      hipLaunchKernelGGL((KERNEL<4096, 512>), dim3(resident_grid(KERNEL<4096, 512>, 512, n_work, n_cu)),  \
+                         dim3(512), 0, st, __VA_ARGS__);                                                  \
+  } while (0)
+
+hipError_t launch_fft_a(int elems, int n_cu, const InstDesc* inst, const FftWork* work, int n_work, double2* grid,
                         const Tables& T, hipStream_t st) {
   if (n_work <= 0) return hipSuccess;
-  MI_FFT_DISPATCH(k_fft_a, inst, work, grid, T);
+  MI_FFT_PERSISTENT(k_fft_a, inst, work, n_work, grid, T);
   return hipGetLastError();
 }
-hipError_t launch_fft_b_c2r(int elems, const InstDesc* inst, const FftWork* work, int n_work, const double2* yb,
-                            const double* b0, const Tables& T, float* out, hipStream_t st) {
+hipError_t launch_fft_b_c2r(int elems, int n_cu, const InstDesc* inst, const FftWork* work, int n_work,
+                            const double2* yb, const double* b0, const Tables& T, float* out, hipStream_t st) {
   if (n_work <= 0) return hipSuccess;
-  MI_FFT_DISPATCH(k_fft_b_c2r, inst, work, yb, b0, T, out);
+  MI_FFT_PERSISTENT(k_fft_b_c2r, inst, work, n_work, yb, b0, T, out);
   return hipGetLastError();
 }
-hipError_t launch_fft_a_real(int elems, const InstDesc* inst, const FftWork* work, int n_work, double* grid,
-                             const Tables& T, hipStream_t st) {
+hipError_t launch_fft_a_real(int elems, int n_cu, const InstDesc* inst, const FftWork* work, int n_work,
+                             double* grid, const Tables& T, hipStream_t st) {
   if (n_work <= 0) return hipSuccess;
-  MI_FFT_DISPATCH(k_fft_a_real, inst, work, grid, T);
+  MI_FFT_PERSISTENT(k_fft_a_real, inst, work, n_work, grid, T);
   return hipGetLastError();
 }
-hipError_t launch_fft_b_c2r_sym(int elems, const InstDesc* inst, const FftWork* work, int n_work,
+hipError_t launch_fft_b_c2r_sym(int elems, int n_cu, const InstDesc* inst, const FftWork* work, int n_work,
                                 const double* grid, const double* b0, const Tables& T, float* out, hipStream_t st) {
   if (n_work <= 0) return hipSuccess;
-  MI_FFT_DISPATCH(k_fft_b_c2r_sym, inst, work, grid, b0, T, out);
+  MI_FFT_PERSISTENT(k_fft_b_c2r_sym, inst, work, n_work, grid, b0, T, out);
   return hipGetLastError();
 }
 hipError_t launch_fft_b_r2c(int elems, const InstDesc* inst, const FftWork* work, int n_work, const float* img,

@@ -14,6 +14,8 @@
 //   k_grid  grid-stride over tiles of TK lines x TJ cells of a half grid: accumulate the
 //           tile's samples into LDS (no global atomics), then one coalesced flush that
 //           writes every cell of the tile (zeros included), so no separate memset pass.
+#include <type_traits>
+
 #include "mi_internal.h"
 
 namespace mi {
@@ -207,11 +209,10 @@ constexpr int GRID_THREADS = 256;
 constexpr int GRID_CHUNK = 32;
 constexpr int GRID_EB = 256;
 
-// Grid cell stores: FP64 complex, complex64 (mi_grid output), or FP64 real (the beam grid,
-// whose imaginary part is zero).
+// Grid cell stores: FP64 complex or complex64 (mi_grid output); the real FP64 beam grid
+// (imaginary part zero) is stored two cells at a time in the kernel.
 __device__ __forceinline__ void put_cell(double2* p, double2 v) { *p = v; }
 __device__ __forceinline__ void put_cell(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
-__device__ __forceinline__ void put_cell(double* p, double2 v) { *p = v.x; }
 
 template <class OutT>
 __global__ void __launch_bounds__(GRID_THREADS)
@@ -249,8 +250,13 @@ k_grid(const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst, int
     const int n = __builtin_amdgcn_readfirstlane(m_cnt[tt]);
 
     if (n == 0) {  // empty tile: plain zero fill
-      for (int q = tid; q < TK * TJ; q += GRID_THREADS)
-        put_cell(out + (int64_t)(q / TJ) * P + (q % TJ), make_double2(0.0, 0.0));
+      if constexpr (std::is_same<OutT, double>::value) {   // real cells, two per 16-byte store
+        for (int q = tid; q < TK * TJ / 2; q += GRID_THREADS)
+          *reinterpret_cast<double2*>(out + (int64_t)(2 * q / TJ) * P + (2 * q % TJ)) = make_double2(0.0, 0.0);
+      } else {
+        for (int q = tid; q < TK * TJ; q += GRID_THREADS)
+          put_cell(out + (int64_t)(q / TJ) * P + (q % TJ), make_double2(0.0, 0.0));
+      }
       continue;
     }
     for (int q = tid; q < TK * TJ; q += GRID_THREADS) acc[q] = make_double2(0.0, 0.0);
@@ -297,11 +303,23 @@ k_grid(const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst, int
       }
     }
     __syncthreads();
-    for (int q = tid; q < TK * TJ; q += GRID_THREADS) {
-      const int l = q / TJ, jj = q % TJ;
-      double2 val = acc[q];
-      if (modulate && (((k0 + l + 1) + (j0 + jj)) & 1)) { val.x = -val.x; val.y = -val.y; }
-      put_cell(out + (int64_t)l * P + jj, val);
+    if constexpr (std::is_same<OutT, double>::value) {     // real cells, two per 16-byte store
+      for (int q = tid; q < TK * TJ / 2; q += GRID_THREADS) {
+        const int l = 2 * q / TJ, jj = 2 * q % TJ;
+        double2 val = make_double2(acc[2 * q].x, acc[2 * q + 1].x);
+        if (modulate) {
+          if (((k0 + l + 1) + (j0 + jj)) & 1) val.x = -val.x;
+          else val.y = -val.y;
+        }
+        *reinterpret_cast<double2*>(out + (int64_t)l * P + jj) = val;
+      }
+    } else {
+      for (int q = tid; q < TK * TJ; q += GRID_THREADS) {
+        const int l = q / TJ, jj = q % TJ;
+        double2 val = acc[q];
+        if (modulate && (((k0 + l + 1) + (j0 + jj)) & 1)) { val.x = -val.x; val.y = -val.y; }
+        put_cell(out + (int64_t)l * P + jj, val);
+      }
     }
     __syncthreads();
   }

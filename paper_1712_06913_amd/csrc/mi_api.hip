@@ -39,11 +39,11 @@ hipError_t launch_expand_full(const InstDesc*, int, int, const double2*, float2*
 hipError_t launch_fill_u32(unsigned*, int64_t, unsigned, hipStream_t);
 hipError_t launch_grid_real(const InstDesc*, const int*, int, const float2*, const float*, const float*, const int*,
                             const int*, const int*, const Tables&, double*, hipStream_t);
-hipError_t launch_fft_a(int, const InstDesc*, const FftWork*, int, double2*, const Tables&, hipStream_t);
-hipError_t launch_fft_b_c2r(int, const InstDesc*, const FftWork*, int, const double2*, const double*, const Tables&,
-                            float*, hipStream_t);
-hipError_t launch_fft_a_real(int, const InstDesc*, const FftWork*, int, double*, const Tables&, hipStream_t);
-hipError_t launch_fft_b_c2r_sym(int, const InstDesc*, const FftWork*, int, const double*, const double*,
+hipError_t launch_fft_a(int, int, const InstDesc*, const FftWork*, int, double2*, const Tables&, hipStream_t);
+hipError_t launch_fft_b_c2r(int, int, const InstDesc*, const FftWork*, int, const double2*, const double*,
+                            const Tables&, float*, hipStream_t);
+hipError_t launch_fft_a_real(int, int, const InstDesc*, const FftWork*, int, double*, const Tables&, hipStream_t);
+hipError_t launch_fft_b_c2r_sym(int, int, const InstDesc*, const FftWork*, int, const double*, const double*,
                                 const Tables&, float*, hipStream_t);
 hipError_t launch_fft_b_r2c(int, const InstDesc*, const FftWork*, int, const float*, const Tables&, double2*,
                             hipStream_t);
@@ -367,8 +367,8 @@ void run_image(mi_ctx* ctx, Plan* P, float* out, hipStream_t st) {
   const InstDesc* inst = static_cast<const InstDesc*>(P->inst.p);
   double2* g = static_cast<double2*>(P->gd.p);
   const double* b0 = static_cast<const double*>(P->b0.p);
-  HIPCHK(launch_fft_a(P->elems_d, inst, static_cast<const FftWork*>(P->wa_d.p), P->n_wa_d, g, ctx->T, st));
-  HIPCHK(launch_fft_b_c2r(P->elems_d, inst, static_cast<const FftWork*>(P->wb_d.p), P->n_wb_d, g, b0, ctx->T, out,
+  HIPCHK(launch_fft_a(P->elems_d, ctx->n_cu, inst, static_cast<const FftWork*>(P->wa_d.p), P->n_wa_d, g, ctx->T, st));
+  HIPCHK(launch_fft_b_c2r(P->elems_d, ctx->n_cu, inst, static_cast<const FftWork*>(P->wb_d.p), P->n_wb_d, g, b0, ctx->T, out,
                           st));
 }
 
@@ -380,8 +380,8 @@ void run_beam(mi_ctx* ctx, Plan* P, const float* uv, const float* w_in, float* o
                           reinterpret_cast<const float2*>(uv), w_in, static_cast<const float*>(P->wts.p),
                           static_cast<const int*>(P->ent_b.p), static_cast<const int*>(P->ts_b.p),
                           static_cast<const int*>(P->tc_b.p), ctx->T, g, st));
-  HIPCHK(launch_fft_a_real(P->elems_b, inst, static_cast<const FftWork*>(P->wa_b.p), P->n_wa_b, g, ctx->T, st));
-  HIPCHK(launch_fft_b_c2r_sym(P->elems_b, inst, static_cast<const FftWork*>(P->wb_b.p), P->n_wb_b, g,
+  HIPCHK(launch_fft_a_real(P->elems_b, ctx->n_cu, inst, static_cast<const FftWork*>(P->wa_b.p), P->n_wa_b, g, ctx->T, st));
+  HIPCHK(launch_fft_b_c2r_sym(P->elems_b, ctx->n_cu, inst, static_cast<const FftWork*>(P->wb_b.p), P->n_wb_b, g,
                               static_cast<const double*>(P->b0.p), ctx->T, out, st));
 }
 
