@@ -16,6 +16,11 @@ is the classic Hogbom CLEAN (Sec. 2) it builds on:
 The beam is the 2N x 2N dirty beam (peak at (N, N)), "twice as large as the image" so a
 point can be subtracted from any pixel (Sec. 3.2.1).
 
+Window (the paper is silent; reading: the whole map by default): an optional box
+(x0, y0, x1, y1), half-open, restricts where the peak is searched; the subtraction still
+covers the whole map.  Peaks and ties are taken over the box's pixels in row-major order,
+which is the map's linear order restricted to the box.
+
 Clean beam (Algorithm 1's `gpu_cpsf`; the paper does not say how it is made): the main
 lobe is the 4-connected region around (N, N) where the beam exceeds 0.35; a Gaussian with
 peak 1, exp(-(a dx^2 + b dx dy + c dy^2)), is fitted to ln(beam) over the lobe by linear
@@ -39,7 +44,22 @@ def _window(beam, N, py, px):
     return beam[N - py: 2 * N - py, N - px: 2 * N - px]
 
 
-def hogbom(dirty, beam, gain=0.1, niter=100, threshold=0.0, positive_only=False):
+def _box(window, N):
+    x0, y0, x1, y1 = (0, 0, N, N) if window is None else (int(v) for v in window)
+    assert 0 <= x0 < x1 <= N and 0 <= y0 < y1 <= N, "window must be a non-empty box inside the map"
+    return x0, y0, x1, y1
+
+
+def _peak(R, window, positive_only):
+    """(py, px) of the first maximum of R (or |R|) over the window box."""
+    x0, y0, x1, y1 = _box(window, R.shape[0])
+    sub = R[y0:y1, x0:x1]
+    q = int(np.argmax(sub if positive_only else np.abs(sub)))   # first maximum = lowest index
+    qy, qx = divmod(q, x1 - x0)
+    return y0 + qy, x0 + qx
+
+
+def hogbom(dirty, beam, gain=0.1, niter=100, threshold=0.0, positive_only=False, window=None):
     """Returns (residual, model, comp_idx, comp_flux)."""
     R = np.array(dirty, dtype=np.float64, copy=True)
     N = R.shape[0]
@@ -48,8 +68,8 @@ def hogbom(dirty, beam, gain=0.1, niter=100, threshold=0.0, positive_only=False)
     model = np.zeros((N, N))
     idx, flux = [], []
     for _ in range(int(niter)):
-        p = int(np.argmax(R if positive_only else np.abs(R)))   # first maximum = lowest index
-        py, px = divmod(p, N)
+        py, px = _peak(R, window, positive_only)
+        p = py * N + px
         peak = R[py, px]
         if abs(peak) <= threshold:
             break
@@ -62,12 +82,13 @@ def hogbom(dirty, beam, gain=0.1, niter=100, threshold=0.0, positive_only=False)
 
 
 def replay(dirty, beam, comp_idx, comp_flux, gain=0.1, threshold=0.0, eps=None, n_stop=None,
-           positive_only=False):
+           positive_only=False, window=None):
     """Validate a component list produced elsewhere (several answers are correct under near-ties).
 
     Re-runs the loop in FP64 following the given picks: pick i is accepted iff its peak
-    value (|R_i[p_i]|, or R_i[p_i] with positive_only) is within eps of the map's peak
-    value, and |flux_i - gain R_i[p_i]| <= gain eps.  Returns (ok, first_bad_index,
+    value (|R_i[p_i]|, or R_i[p_i] with positive_only) is within eps of the peak value over
+    the window (the whole map by default), p_i lies in the window, and
+    |flux_i - gain R_i[p_i]| <= gain eps.  Returns (ok, first_bad_index,
     residual, model).  eps defaults to 1e-5 max|dirty|.
     """
     R = np.array(dirty, dtype=np.float64, copy=True)
@@ -76,14 +97,17 @@ def replay(dirty, beam, comp_idx, comp_flux, gain=0.1, threshold=0.0, eps=None, 
     if eps is None:
         eps = 1e-5 * float(np.max(np.abs(R)))
     model = np.zeros((N, N))
+    x0, y0, x1, y1 = _box(window, N)
     for i, (p, fl) in enumerate(zip(np.asarray(comp_idx), np.asarray(comp_flux))):
         p = int(p)
         py, px = divmod(p, N)
+        sub = R[y0:y1, x0:x1]
         if positive_only:
-            m, val = float(np.max(R)), R[py, px]
+            m, val = float(np.max(sub)), R[py, px]
         else:
-            m, val = float(np.max(np.abs(R))), abs(R[py, px])
-        if val < m - eps or abs(fl - gain * R[py, px]) > gain * eps:
+            m, val = float(np.max(np.abs(sub))), abs(R[py, px])
+        inside = x0 <= px < x1 and y0 <= py < y1
+        if not inside or val < m - eps or abs(fl - gain * R[py, px]) > gain * eps:
             return False, i, R, model
         f = gain * R[py, px]
         model[py, px] += f

@@ -143,3 +143,43 @@ def test_replay_positive_only_uses_signed_peak():
     beam = imager.dirty_beam(uv, w, N, cell, 0)
     _, _, idx, flux = clean.hogbom(dirty, beam, niter=40, positive_only=True)
     assert clean.replay(dirty, beam, idx, flux, positive_only=True)[0]
+
+
+def test_window_picks_follow_a_brute_force_search_and_subtract_everywhere():
+    # every pick is the lowest-index maximum of |R| over the window's pixels, found here by
+    # a plain double loop; the subtraction covers the whole map (checked pixel by pixel)
+    N = 16
+    beam = _real_beam(N, seed=5)
+    rng = np.random.default_rng(31)
+    dirty = rng.standard_normal((N, N))
+    dirty[1, 1] = 50.0                       # brightest pixel, outside the window
+    win = (4, 3, 13, 11)                     # x0, y0, x1, y1
+    R, model, idx, flux = clean.hogbom(dirty, beam, gain=0.2, niter=25, window=win)
+    assert len(idx) == 25
+    Rb = dirty.copy()
+    for p, f in zip(idx, flux):
+        best, bp = -1.0, -1
+        for y in range(win[1], win[3]):
+            for x in range(win[0], win[2]):
+                if abs(Rb[y, x]) > best:
+                    best, bp = abs(Rb[y, x]), y * N + x
+        assert p == bp and abs(f - 0.2 * Rb[bp // N, bp % N]) < 1e-12
+        py, px = divmod(int(p), N)
+        for y in range(N):
+            for x in range(N):
+                Rb[y, x] -= f * beam[y - py + N, x - px + N]
+    assert np.max(np.abs(Rb - R)) < 1e-12
+    assert abs(R[1, 1] - dirty[1, 1]) > 0 and model[1, 1] == 0.0   # changed by sidelobes, never picked
+    ok, bad, _, _ = clean.replay(dirty, beam, idx, flux, gain=0.2, window=win)
+    assert ok
+    ok, bad, _, _ = clean.replay(dirty, beam, idx, flux, gain=0.2)      # without the window: the first pick is wrong
+    assert not ok and bad == 0
+
+
+def test_full_window_equals_no_window():
+    N = 16
+    beam = _real_beam(N, seed=6)
+    dirty = np.random.default_rng(32).standard_normal((N, N))
+    a = clean.hogbom(dirty, beam, niter=40)
+    b = clean.hogbom(dirty, beam, niter=40, window=(0, 0, N, N))
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[0], b[0])
