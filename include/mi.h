@@ -96,6 +96,11 @@ typedef struct {
                                   spread one image over several XCDs (the "plain" path) */
   const float* threshold_dev;  /* device, n_inst, or NULL: thresholds read on the device
                                   (e.g. mu_a from mi_gmm_levels); overrides `threshold` */
+  const int32_t* window;       /* host, 4 per instance (x0, y0, x1, y1), or NULL: the peak
+                                  is searched only in the half-open box x0 <= x < x1,
+                                  y0 <= y < y1 (0 <= x0 < x1 <= N, likewise y); the
+                                  subtraction still covers the whole map.  NULL = whole
+                                  maps (the paper does not window its CLEAN)           */
 } mi_clean_params;
 
 /* Create / destroy a context on HIP device `device`.  The context owns plans,
@@ -150,7 +155,8 @@ mi_status mi_dirty_beam(mi_ctx* ctx, const mi_batch* batch, const float* uv,
 
 /* Hogbom CLEAN with restore (Algorithm 1, improved_clean; Sec. 4.3).
  *   dirty: float32 N*N per instance; beam: float32 (2N)^2 per instance (peak at (N, N)).
- *   Per iteration: p = argmax |R| (ties: lowest y*N + x), stop if |R[p]| <= threshold,
+ *   Per iteration: p = argmax |R| over the window (ties: lowest y*N + x), stop if
+ *   |R[p]| <= threshold,
  *   f = gain * R[p] (double), model[p] += f, R -= f * beam[y - p_y + N][x - p_x + N].
  *   residual_out: float32 N*N; model_out: double N*N (optional);
  *   comp_idx (int32) / comp_flux (double): niter[i] slots per instance, packed back to

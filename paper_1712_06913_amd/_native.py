@@ -26,7 +26,8 @@ class MiBatch(ctypes.Structure):
 
 class MiCleanParams(ctypes.Structure):
     _fields_ = [("gain", c_float), ("niter", c_void_p), ("threshold", c_void_p), ("positive_only", c_int32),
-                ("team_size", c_int32), ("threshold_dev", c_void_p)]
+                ("team_size", c_int32), ("threshold_dev", c_void_p),
+                ("window", c_void_p)]
 
 
 class MiError(RuntimeError):

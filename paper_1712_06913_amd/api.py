@@ -135,11 +135,12 @@ def ifft2(data: torch.Tensor, n, offs, device: int = 0):
 
 def hogbom_clean(batch: Batch, dirty, beam, niter, gain: float = 0.1, threshold=None, positive_only=False,
                  restore: bool = True, want_model: bool = True, want_components: bool = True, team_size: int = 0,
-                 out=None):
+                 out=None, window=None):
     """mi_hogbom_clean; returns a dict of device tensors (reused when `out` is a previous result).
 
     `threshold`: None, a host array (one per instance), or a float32 device tensor (read on
-    the device, e.g. the mu_a of gmm_levels)."""
+    the device, e.g. the mu_a of gmm_levels).  `window`: None (whole maps) or an
+    [n_inst, 4] array of peak-search boxes (x0, y0, x1, y1), half-open."""
     dev = batch.device
     niter = np.ascontiguousarray(niter, dtype=np.int32)
     thr_dev = None
@@ -149,6 +150,7 @@ def hogbom_clean(batch: Batch, dirty, beam, niter, gain: float = 0.1, threshold=
         thr_dev, thr = threshold.contiguous(), None
     else:
         thr = None if threshold is None else np.ascontiguousarray(threshold, dtype=np.float32)
+    win = None if window is None else np.ascontiguousarray(window, dtype=np.int32).reshape(batch.n_inst, 4)
     nimg = int(batch.img_off[-1])
     ncomp_total = max(1, int(niter.sum()))
     res = out
@@ -166,7 +168,8 @@ def hogbom_clean(batch: Batch, dirty, beam, niter, gain: float = 0.1, threshold=
         res["comp_off"] = np.concatenate([[0], np.cumsum(niter.astype(np.int64))])
     prm = nat.MiCleanParams(float(gain), niter.ctypes.data, None if thr is None else thr.ctypes.data,
                             1 if positive_only else 0, int(team_size),
-                            None if thr_dev is None else thr_dev.data_ptr())
+                            None if thr_dev is None else thr_dev.data_ptr(),
+                            None if win is None else win.ctypes.data)
     nat.check(batch.ctx, nat.lib().mi_hogbom_clean(
         batch.ctx, batch.c, _ptr(dirty), _ptr(beam), ctypes.byref(prm), _ptr(res["residual"]), _ptr(res["model"]),
         _ptr(res["comp_idx"]), _ptr(res["comp_flux"]), _ptr(res["n_comp"]), _ptr(res["restored"]),

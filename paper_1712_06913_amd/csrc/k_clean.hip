@@ -207,7 +207,7 @@ __device__ __forceinline__ void sub_window(float* R, __amdgpu_buffer_rsrc_t rs, 
 // c0 is a row start and a step of 4 CL_THREADS = 4096 pixels is 4096/N whole rows, i.e.
 // 8192 floats further into the beam window: each group is one 16-byte buffer load at a
 // uniform (SGPR) offset from a fixed per-thread offset.
-template <int PPT, bool LOCAL>
+template <int PPT, bool LOCAL, bool WIN>
 __global__ void __launch_bounds__(CL_THREADS)
 k_clean(CleanArgs A) {
   static_assert(PPT % 4 == 0, "4 pixels per load");
@@ -268,6 +268,14 @@ k_clean(CleanArgs A) {
     const bool sym = N >= 256 && A.asym[img] == 0;
     const int yw = row0 + __builtin_amdgcn_readfirstlane(t4 >> log2N);   // this wave's row at step 0
     const int RS = STEP >> log2N, log2RS = 12 - log2N;   // rows per load step (STEP = 2^12)
+    // peak-search box: pixel (x, y) of group s, component j is x = xt + j, y = yt + s RS
+    const int4 wb = WIN ? A.win[img] : make_int4(0, 0, N, N);
+    const bool windowed = WIN && (wb.x > 0 || wb.y > 0 || wb.z < N || wb.w < N);   // uniform
+    const int xt = t4 & (N - 1), yt = (c0 + t4) >> log2N;
+    auto in_win = [&](int s, int j) {
+      return (unsigned)(xt + j - wb.x) < (unsigned)(wb.z - wb.x) &&
+             (unsigned)(yt + s * RS - wb.y) < (unsigned)(wb.w - wb.y);
+    };
     float f = 0.0f;                                   // pending pick (none yet)
     int py = N / 2, px = N / 2;
     int it = 0;
@@ -287,7 +295,11 @@ k_clean(CleanArgs A) {
       K = __builtin_amdgcn_readfirstlane(K);
       sub_window<NS, LB>(R, rs, vd, vm, K, f);
       float best = posonly ? -INFINITY : -1.0f;
-      if (posonly) {
+      if (windowed) {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+          if (in_win(k >> 2, k & 3)) best = fmaxf(best, posonly ? R[k] : fabsf(R[k]));
+      } else if (posonly) {
 #pragma unroll
         for (int k = 0; k < PPT; ++k) best = fmaxf(best, R[k]);
       } else {
@@ -314,7 +326,8 @@ k_clean(CleanArgs A) {
           if (!found && s < smax) {
             unsigned long long mj[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) mj[j] = __ballot((posonly ? R[4 * s + j] : fabsf(R[4 * s + j])) == wv);
+            for (int j = 0; j < 4; ++j)
+              mj[j] = __ballot((posonly ? R[4 * s + j] : fabsf(R[4 * s + j])) == wv && (!windowed || in_win(s, j)));
             const unsigned long long m = mj[0] | mj[1] | mj[2] | mj[3];
             if (m) {
               found = true;
@@ -433,9 +446,13 @@ k_clean(CleanArgs A) {
 }
 
 // ---- host launchers ----
-#define MI_CLEAN_KERNEL(PPT, LOCAL) reinterpret_cast<const void*>(&k_clean<PPT, LOCAL>)
+// Windowed peak searches run a separate instantiation, so the unwindowed kernel's code and
+// register allocation are untouched by the window tests.
+#define MI_CLEAN_KERNEL(PPT, LOCAL)                                                     \
+  (win ? reinterpret_cast<const void*>(&k_clean<PPT, LOCAL, true>)                    \
+       : reinterpret_cast<const void*>(&k_clean<PPT, LOCAL, false>))
 
-static const void* clean_kernel(int ppt, bool local) {
+static const void* clean_kernel(int ppt, bool local, bool win) {
   switch (ppt) {
     case 4: return local ? MI_CLEAN_KERNEL(4, true) : MI_CLEAN_KERNEL(4, false);
     case 8: return local ? MI_CLEAN_KERNEL(8, true) : MI_CLEAN_KERNEL(8, false);
@@ -446,14 +463,14 @@ static const void* clean_kernel(int ppt, bool local) {
   }
 }
 
-hipError_t clean_max_blocks_per_cu(int ppt, bool local, size_t lds, int* nb) {
-  const void* k = clean_kernel(ppt, local);
+hipError_t clean_max_blocks_per_cu(int ppt, bool local, bool win, size_t lds, int* nb) {
+  const void* k = clean_kernel(ppt, local, win);
   if (!k) return hipErrorInvalidValue;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k, CL_THREADS, lds);
 }
 
 hipError_t launch_clean(const CleanArgs& A, int ppt, bool local, int n_blocks, size_t lds, hipStream_t st) {
-  const void* k = clean_kernel(ppt, local);
+  const void* k = clean_kernel(ppt, local, A.win != nullptr);
   if (!k) return hipErrorInvalidValue;
   CleanArgs a = A;
   void* args[] = {&a};

@@ -52,7 +52,7 @@ hipError_t launch_fft_c2c_t_f2d(int, const int*, const int64_t*, const FftWork*,
                                 const Tables&, double, int, int, hipStream_t);
 hipError_t launch_fft_c2c_t_d2f(int, const int*, const int64_t*, const FftWork*, int, const double2*, float2*,
                                 const Tables&, double, int, int, hipStream_t);
-hipError_t clean_max_blocks_per_cu(int ppt, bool local, size_t lds, int* nb);
+hipError_t clean_max_blocks_per_cu(int ppt, bool local, bool win, size_t lds, int* nb);
 hipError_t launch_clean(const CleanArgs&, int ppt, bool local, int n_blocks, size_t lds, hipStream_t);
 hipError_t launch_beamfit(const InstDesc*, int, const float*, double*, int*, int*, hipStream_t);
 hipError_t launch_gmm(const InstDesc*, int, const float*, int, int, double*, float*, float*, hipStream_t);
@@ -139,11 +139,12 @@ struct CleanPlan {
   std::vector<int32_t> niter;
   std::vector<float> thr;
   bool has_thr = false;
+  std::vector<int32_t> win;   // 4 per instance, empty: whole maps
   int T = 0, local = 1, n_blocks = 0, ppt = 0, team_req = 0, sub_px = 0;
   int64_t n_slots = 0;
   size_t lds = 0;        // restore staging: sub_px floats
   int64_t total_comp = 0;
-  DevBuf team_off, team_imgs, blk, team_G, team_slot, niter_d, thr_d, comp_off, slots, asym, comp_idx,
+  DevBuf team_off, team_imgs, blk, team_G, team_slot, niter_d, thr_d, win_d, comp_off, slots, asym, comp_idx,
       comp_flux, cbeam, rrad;
 };
 
@@ -438,7 +439,7 @@ void build_clean_schedule(mi_ctx* ctx, Plan* P, CleanPlan* C, int req) {
   const int sub_px = (int)std::min<int64_t>(max_chunk, CLEAN_RESTORE_SUB_PX);
   const size_t lds = (size_t)sub_px * sizeof(float);
   int per_cu = 0;
-  HIPCHK(clean_max_blocks_per_cu(ppt, local, lds, &per_cu));
+  HIPCHK(clean_max_blocks_per_cu(ppt, local, !C->win.empty(), lds, &per_cu));
   if (per_cu < 1) fail(MI_ERR_UNSUPPORTED, "CLEAN kernel cannot be resident");
   int cap = per_cu * ctx->n_cu;
   if (local) cap -= cap % 8;
@@ -525,6 +526,7 @@ void build_clean_schedule(mi_ctx* ctx, Plan* P, CleanPlan* C, int req) {
   upload(C->team_slot, tslot);
   upload(C->niter_d, C->niter);
   if (C->has_thr) upload(C->thr_d, C->thr);
+  if (!C->win.empty()) upload(C->win_d, C->win);
   upload(C->comp_off, coff);
   dev_alloc<unsigned long long>(C->slots, (size_t)ns);
 }
@@ -879,12 +881,25 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
     h = fnv1a(&req, sizeof req, h);
     const bool has_thr = prm->threshold != nullptr && prm->threshold_dev == nullptr;
     if (has_thr) h = fnv1a(prm->threshold, sizeof(float) * n, h ^ 0x9e3779b97f4a7c15ull);
+    if (prm->window) {
+      for (int i = 0; i < n; ++i) {
+        const int32_t* w = prm->window + 4 * i;
+        const int N = P->n[i];
+        if (!(0 <= w[0] && w[0] < w[2] && w[2] <= N && 0 <= w[1] && w[1] < w[3] && w[3] <= N))
+          fail(MI_ERR_ARG, "window[%d] = (%d, %d, %d, %d) is not a non-empty box inside the %d x %d map", i, w[0],
+               w[1], w[2], w[3], N, N);
+      }
+      h = fnv1a(prm->window, sizeof(int32_t) * 4 * n, h ^ 0x7f4a7c159e3779b9ull);
+    }
+    const size_t n_win = prm->window ? 4 * (size_t)n : 0;
     CleanPlan* C = nullptr;
     auto it = P->cleans.find(h);
     if (it != P->cleans.end() && it->second->team_req == req &&
         std::equal(it->second->niter.begin(), it->second->niter.end(), prm->niter) &&
         it->second->has_thr == has_thr &&
-        (!has_thr || std::equal(it->second->thr.begin(), it->second->thr.end(), prm->threshold))) {
+        (!has_thr || std::equal(it->second->thr.begin(), it->second->thr.end(), prm->threshold)) &&
+        it->second->win.size() == n_win &&
+        std::equal(it->second->win.begin(), it->second->win.end(), prm->window)) {
       C = it->second.get();
     } else {
       if (P->cleans.size() >= 8) P->cleans.erase(P->cleans.begin());
@@ -894,6 +909,7 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
       C->niter.assign(prm->niter, prm->niter + n);
       C->has_thr = has_thr;
       if (has_thr) C->thr.assign(prm->threshold, prm->threshold + n);
+      if (n_win) C->win.assign(prm->window, prm->window + n_win);
       build_clean_schedule(ctx, P, C, req);
       P->cleans[h] = std::move(up);
     }
@@ -929,6 +945,7 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
     A.beam = beam;
     A.niter = static_cast<const int*>(C->niter_d.p);
     A.thr = prm->threshold_dev ? prm->threshold_dev : (has_thr ? static_cast<const float*>(C->thr_d.p) : nullptr);
+    A.win = n_win ? static_cast<const int4*>(C->win_d.p) : nullptr;
     A.gain = prm->gain;
     A.posonly = prm->positive_only ? 1 : 0;
     A.cbeam = restore ? cbeam : nullptr;

@@ -71,6 +71,7 @@ struct CleanArgs {
   const float* beam;
   const int* niter;
   const float* thr;        // may be null (threshold 0)
+  const int4* win;         // per instance peak-search box (x0, y0, x1, y1), or null: whole maps
   float gain;
   int posonly;
   const double* cbeam;     // 6 per instance (a, b, c, ...) or null: no restore

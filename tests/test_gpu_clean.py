@@ -26,7 +26,8 @@ def _inputs(wl):
     return dirty, beams
 
 
-def _run(wl, niter, gain=0.1, threshold=None, positive_only=False, restore=True, team_size=0, inputs=None):
+def _run(wl, niter, gain=0.1, threshold=None, positive_only=False, restore=True, team_size=0, inputs=None,
+         window=None):
     require_gpu()
     from paper_1712_06913_amd import api
     dirty, beams = inputs if inputs is not None else _inputs(wl)
@@ -34,13 +35,15 @@ def _run(wl, niter, gain=0.1, threshold=None, positive_only=False, restore=True,
     d_t = torch.from_numpy(np.concatenate([x.ravel() for x in dirty])).cuda()
     b_t = torch.from_numpy(np.concatenate([x.ravel() for x in beams])).cuda()
     res = api.hogbom_clean(b, d_t, b_t, niter, gain=gain, threshold=threshold, positive_only=positive_only,
-                           restore=restore, team_size=team_size)
+                           restore=restore, team_size=team_size, window=window)
     torch.cuda.synchronize()
     return b, dirty, beams, res
 
 
-def _check(wl, niter, gain=0.1, threshold=None, positive_only=False, exact=False, team_size=0, inputs=None):
-    b, dirty, beams, res = _run(wl, niter, gain, threshold, positive_only, team_size=team_size, inputs=inputs)
+def _check(wl, niter, gain=0.1, threshold=None, positive_only=False, exact=False, team_size=0, inputs=None,
+           window=None):
+    b, dirty, beams, res = _run(wl, niter, gain, threshold, positive_only, team_size=team_size, inputs=inputs,
+                                window=window)
     resid = b.split(res["residual"])
     model = b.split(res["model"])
     restored = b.split(res["restored"])
@@ -53,8 +56,9 @@ def _check(wl, niter, gain=0.1, threshold=None, positive_only=False, exact=False
         D = dirty[i].astype(np.float64)
         B = beams[i].astype(np.float64)
         thr = 0.0 if threshold is None else float(threshold[i])
+        win = None if window is None else tuple(int(v) for v in window[i])
         R0, M0, idx0, flux0 = clean.hogbom(D, B, gain=gain, niter=int(niter[i]), threshold=thr,
-                                           positive_only=positive_only)
+                                           positive_only=positive_only, window=win)
         n = int(nc[i])
         gi, gf = ci[off[i]: off[i] + n], cf[off[i]: off[i] + n]
         peak = np.max(np.abs(D))
@@ -64,11 +68,14 @@ def _check(wl, niter, gain=0.1, threshold=None, positive_only=False, exact=False
             assert np.array_equal(gi, idx0)
             assert np.max(np.abs(gf - flux0)) <= 1e-5 * peak
         else:
-            ok, bad, Rr, Mr = clean.replay(D, B, gi, gf, gain=gain, threshold=thr, positive_only=positive_only)
+            ok, bad, Rr, Mr = clean.replay(D, B, gi, gf, gain=gain, threshold=thr, positive_only=positive_only,
+                                           window=win)
             assert ok, f"replay rejected pick {bad}"
             if n < int(niter[i]):
                 # stopped early: the next peak of the replayed residual is at the threshold
-                nxt = np.max(Rr) if positive_only else np.max(np.abs(Rr))
+                x0, y0, x1, y1 = win if win is not None else (0, 0, D.shape[0], D.shape[0])
+                Rw = Rr[y0:y1, x0:x1]
+                nxt = np.max(Rw) if positive_only else np.max(np.abs(Rw))
                 assert abs(nxt) <= thr + 1e-5 * peak
             R0, M0 = Rr, Mr
         assert max_abs(resid[i].cpu().numpy(), R0) <= 1e-4 * peak
@@ -93,6 +100,43 @@ def test_clean_threshold_stops_early_and_positive_only():
     thr = np.array([0.5 * np.max(np.abs(d)) for d in dirty], np.float32)
     _check(wl, np.array([400, 400], np.int32), threshold=thr)
     _check(wl, np.array([60, 60], np.int32), positive_only=True)
+
+
+def test_clean_window_restricts_the_peak_search():
+    log("[clean] peak-search windows excluding the brightest pixels, 64..1024, replayed by the oracle")
+    wl = synth.random_instances(27, [64, 256, 1024, 128], m_range=(150, 300))
+    inputs = _inputs(wl)
+    win = []
+    for d in inputs[0]:
+        N = d.shape[0]
+        py, px = divmod(int(np.argmax(np.abs(d))), N)
+        # a box on the far side of the brightest pixel, so that pixel is never a candidate
+        x0, x1 = (px + 3, N) if px < N // 2 else (0, px - 2)
+        y0, y1 = (N // 5, N - N // 7)
+        win.append((x0, y0, x1, y1))
+    win = np.array(win, np.int32)
+    niter = np.array([40, 80, 150, 60], np.int32)
+    _check(wl, niter, inputs=inputs, window=win)
+    _check(wl, niter, inputs=inputs, window=win, positive_only=True)
+    # a window covering every map gives exactly the unwindowed components
+    full = np.array([(0, 0, d.shape[0], d.shape[0]) for d in inputs[0]], np.int32)
+    _, _, _, ra = _run(wl, niter, inputs=inputs, window=full)
+    _, _, _, rb = _run(wl, niter, inputs=inputs)
+    assert torch.equal(ra["comp_idx"], rb["comp_idx"]) and torch.equal(ra["n_comp"], rb["n_comp"])
+
+
+def test_clean_window_rejects_bad_boxes():
+    log("[clean] bad windows are argument errors")
+    require_gpu()
+    from paper_1712_06913_amd import api, _native as nat
+    wl = synth.random_instances(28, [64], m_range=(50, 60))
+    dirty, beams = _inputs(wl)
+    b = api.Batch.from_workload(wl)
+    d_t = torch.from_numpy(dirty[0].ravel()).cuda()
+    b_t = torch.from_numpy(beams[0].ravel()).cuda()
+    for w in [(0, 0, 65, 64), (5, 5, 5, 9), (-1, 0, 10, 10), (10, 0, 3, 64)]:
+        with pytest.raises(nat.MiError):
+            api.hogbom_clean(b, d_t, b_t, np.array([10], np.int32), window=np.array([w], np.int32))
 
 
 def test_clean_single_point_closed_form_exact():
