@@ -189,14 +189,15 @@ __global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(FF
 k_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int n_work, double2* grid, Tables T) {
   __shared__ double2 buf[LDS_PADDED(ELEMS)];
   constexpr int NPT = ELEMS / THREADS;
-  double2 r[NPT];
+  constexpr int NPF = NPT / 2;                 // prefetched half; the rest is loaded at staging
+  double2 r[NPF];
   auto fetch = [&](int wi) {
     const FftWork wk = work[wi];
     const InstDesc d = inst[wk.inst];
     const int P = d.N, n = lines_per_block<ELEMS>(P) * P;
     const double2* blk = grid + d.gd_off + (int64_t)wk.first * P;
 #pragma unroll
-    for (int i = 0; i < NPT; ++i) {
+    for (int i = 0; i < NPF; ++i) {
       const int q = threadIdx.x + i * THREADS;
       if (q < n) {
         const double2 v = blk[q];
@@ -212,15 +213,20 @@ k_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int
     const int P = d.N, log2P = ilog2(P);
     const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
     const int n = nl * P;
+    double2* blk = grid + d.gd_off + (int64_t)wk.first * P;
 #pragma unroll
-    for (int i = 0; i < NPT; ++i) {
+    for (int i = NPF; i < NPT; ++i) {
+      const int q = threadIdx.x + i * THREADS;
+      if (q < n) buf[pd(q)] = blk[q];
+    }
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) {
       const int q = threadIdx.x + i * THREADS;
       if (q < n) buf[pd(q)] = r[i];
     }
     __syncthreads();
     if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
     lds_fft<ELEMS, THREADS>(buf, log2P, nl, +1.0, T.twiddle);
-    double2* blk = grid + d.gd_off + (int64_t)wk.first * P;
     for (int q = threadIdx.x; q < n; q += THREADS) {
       const int y = q >> log2nl, l = q & (nl - 1);
       blk[q] = buf[pd((l << log2P) + y)];
