@@ -14,4 +14,7 @@ Parity status per function (see each module header for the pins):
   gmm.histogram / gmm.em_fit / gmm.levels        pinned (exact binning, closed-form moments, monotone EM, known mixture)
   centering.correlate / peak_offset / disk_offset / phase_correct
                                                  pinned (direct-sum correlation, whole-pixel shifts, point-source phase)
+  wproj.exact_dirty / plan / kernel_table / dirty_image_w
+                                                 pinned (2-D DFT at w = 0, spheroidal product at w = 0, symmetries,
+                                                 phase rule, exact w-term image of a point source)
 """
