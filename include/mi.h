@@ -153,6 +153,31 @@ mi_status mi_dirty_image(mi_ctx* ctx, const mi_batch* batch, const mi_c64* vis,
 mi_status mi_dirty_beam(mi_ctx* ctx, const mi_batch* batch, const float* uv,
                         const float* w_in, float* beam_out, hipStream_t stream);
 
+/* w-projection parameters (Sec. 3.2.2, 6.1). */
+typedef struct {
+  const double* w_max;         /* host, n_inst: bound on |w| (wavelengths) of each
+                                  instance's visibilities                              */
+  double phase_tol;            /* radians; 0 = 0.1, the phase error the paper tolerates */
+} mi_wproj_params;
+
+/* Dirty image with the w-term corrected by w-projection (Sec. 3.2.2, 6.1; Algorithm 1's
+ * W-term correction).  w_lambda: float32 [M], the w coordinate of each visibility in
+ * wavelengths.  With r2 = l^2 + m^2 at the field corner and dw = phase_tol / (pi r2),
+ * instance i uses the planes w_j = j dw, j = 0 .. floor(w_max[i] / dw + 1/2) (one plane,
+ * i.e. no correction, when pi w_max r2 <= phase_tol / 2); each visibility is gridded with
+ * the kernel of the plane nearest to |w| (conjugated for w < 0): the field's transform of
+ * corr(l) corr(m) exp(+2 pi i w_j (sqrt(1 - l^2 - m^2) - 1)), tabulated at 16 points per
+ * cell over a support of 2 (3 + ceil(w_j sqrt(r2) N dl)) + 1 cells and interpolated
+ * bilinearly.  Weighting, transform, correction and B0 are those of mi_dirty_image.
+ * n_planes_out (host, n_inst, optional) receives the planes used per instance.  Kernel
+ * tables are built on the device when w_max or phase_tol change (the call then
+ * synchronises once).  MI_ERR_ARG for a negative or non-finite w_max;
+ * MI_ERR_UNSUPPORTED for N < 64 or a support above 63 cells.  The dirty beam does not
+ * depend on w (use mi_dirty_beam). */
+mi_status mi_dirty_image_w(mi_ctx* ctx, const mi_batch* batch, const mi_c64* vis, const float* uv,
+                           const float* w_lambda, const float* w_in, const mi_wproj_params* params,
+                           float* dirty_out, double* b0_out, int32_t* n_planes_out, hipStream_t stream);
+
 /* Hogbom CLEAN with restore (Algorithm 1, improved_clean; Sec. 4.3).
  *   dirty: float32 N*N per instance; beam: float32 (2N)^2 per instance (peak at (N, N)).
  *   Per iteration: p = argmax |R| over the window (ties: lowest y*N + x), stop if

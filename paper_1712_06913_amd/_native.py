@@ -16,7 +16,7 @@ MI_LAYOUT_FULL, MI_LAYOUT_HALF = 0, 1
 # every entry point declared in include/mi.h
 EXPORTS = ("mi_ctx_create", "mi_ctx_destroy", "mi_last_error", "mi_version", "mi_grid", "mi_ifft2",
            "mi_dirty_image", "mi_dirty_beam", "mi_hogbom_clean", "mi_degrid", "mi_gmm_levels", "mi_disk_offsets", "mi_phase_shift", "mi_profile_begin",
-           "mi_profile_end")
+           "mi_profile_end", "mi_dirty_image_w")
 
 
 class MiBatch(ctypes.Structure):
@@ -28,6 +28,10 @@ class MiCleanParams(ctypes.Structure):
     _fields_ = [("gain", c_float), ("niter", c_void_p), ("threshold", c_void_p), ("positive_only", c_int32),
                 ("team_size", c_int32), ("threshold_dev", c_void_p),
                 ("window", c_void_p)]
+
+
+class MiWprojParams(ctypes.Structure):
+    _fields_ = [("w_max", c_void_p), ("phase_tol", c_double)]
 
 
 class MiError(RuntimeError):
@@ -59,6 +63,7 @@ def lib():
     L.mi_dirty_beam.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, vp]
     L.mi_hogbom_clean.argtypes = [vp, POINTER(MiBatch), vp, vp, POINTER(MiCleanParams), vp, vp, vp, vp, vp, vp,
                                   vp, vp]
+    L.mi_dirty_image_w.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, vp, POINTER(MiWprojParams), vp, vp, vp, vp]
     L.mi_degrid.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, c_int, vp, vp]
     for name in EXPORTS:
         if name not in ("mi_last_error", "mi_version"):

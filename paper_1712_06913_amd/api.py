@@ -100,6 +100,23 @@ def dirty_image(batch: Batch, vis, uv, w, beam: bool = True, out=None, beam_out=
     return out, (beam_out if beam else None), b0_out
 
 
+def dirty_image_w(batch: Batch, vis, uv, w_lambda, w, w_max, phase_tol: float = 0.1, out=None, b0_out=None):
+    """mi_dirty_image_w: dirty images with w-projection; returns (images, B0, planes per instance).
+    `w_max`: host array, a bound on |w| per instance (wavelengths)."""
+    dev = batch.device
+    out = torch.empty(int(batch.img_off[-1]), dtype=torch.float32, device=dev) if out is None else out
+    b0_out = torch.empty(2 * batch.n_inst, dtype=torch.float64, device=dev) if b0_out is None else b0_out
+    wm = np.ascontiguousarray(w_max, dtype=np.float64)
+    if wm.shape != (batch.n_inst,):
+        raise ValueError("w_max: one value per instance")
+    n_planes = np.zeros(batch.n_inst, np.int32)
+    prm = nat.MiWprojParams(wm.ctypes.data, float(phase_tol))
+    nat.check(batch.ctx, nat.lib().mi_dirty_image_w(batch.ctx, batch.c, _ptr(vis), _ptr(uv), _ptr(w_lambda), _ptr(w),
+                                                    ctypes.byref(prm), _ptr(out), _ptr(b0_out), n_planes.ctypes.data,
+                                                    _stream(dev)))
+    return out, b0_out, n_planes
+
+
 def dirty_beam(batch: Batch, uv, w, out=None):
     dev = batch.device
     out = torch.empty(int(batch.beam_off[-1]), dtype=torch.float32, device=dev) if out is None else out

@@ -23,6 +23,7 @@
 #include "../../include/mi.h"
 #include "mi_internal.h"
 #include "mi_tables.h"
+#include "mi_wproj.h"
 
 namespace mi {
 
@@ -37,6 +38,10 @@ hipError_t launch_grid_f32(const InstDesc*, const int*, int, int, const float2*,
                            hipStream_t);
 hipError_t launch_expand_full(const InstDesc*, int, int, const double2*, float2*, const int64_t*, hipStream_t);
 hipError_t launch_fill_u32(unsigned*, int64_t, unsigned, hipStream_t);
+hipError_t launch_wtables(const WPlane*, int, const int2*, int, int, const Tables&, double2*, double2*, double2*,
+                          hipStream_t);
+hipError_t launch_grid_w(const InstDesc*, int, int, const float2*, const float2*, const float*, const float*,
+                         const float*, const WInst*, const WPlane*, const double2*, double2*, hipStream_t);
 hipError_t launch_grid_real(const InstDesc*, const int*, int, const float2*, const float*, const float*, const int*,
                             const int*, const int*, const Tables&, double*, hipStream_t);
 hipError_t launch_fft_a(int, int, const InstDesc*, const FftWork*, int, double2*, const Tables&, hipStream_t);
@@ -169,6 +174,14 @@ struct Plan {
   // transform slots in place; gb: FP64 complex beam grids for mi_grid's full layout
   DevBuf wts, b0, nkept, cnt, ent_d, ent_b, ts_d, tc_d, ts_b, tc_b, gd, gbr, gb, status_ws, full_off;
   std::map<uint64_t, std::unique_ptr<CleanPlan>> cleans;
+  // w-projection: plane plan and kernel tables for one (w_max, tolerance) set
+  struct WProj {
+    std::vector<double> w_max;
+    double tol = 0.0;
+    std::vector<int32_t> n_planes;   // per instance
+    DevBuf planes, rows, winst, screen, dft, tabs;
+  };
+  std::unique_ptr<WProj> wproj;
   // disk centering: radii (host copy for change detection), 2-D transform work list, buffers
   std::vector<double> radius;
   int corr_elems = 0, corr_nwork = 0;
@@ -840,6 +853,107 @@ mi_status mi_dirty_image(mi_ctx* ctx, const mi_batch* batch, const mi_c64* vis, 
     run_image(ctx, P, dirty_out, stream);
     if (beam) run_beam(ctx, P, uv, w_in, beam_out, stream);
     copy_b0(P, b0_out, stream);
+  });
+}
+
+// w-projection plan: instances with the same (N, cell) share one set of planes w_j = j dw,
+// dw = tol / (pi r2) with r2 = l^2 + m^2 at the field corner; an instance uses planes
+// 0 .. floor(w_max / dw + 1/2).  Plane supports widen the W = 7 support by the w-screen's
+// largest uv frequency over the field (in cells) on each side.  Tables are built on the
+// device, once per plan.
+void build_wproj(mi_ctx* ctx, Plan* P, const double* w_max, double tol, hipStream_t st) {
+  auto W = std::make_unique<Plan::WProj>();
+  const int n = P->n_inst;
+  W->w_max.assign(w_max, w_max + n);
+  W->tol = tol;
+  W->n_planes.resize(n);
+  std::vector<WPlane> planes;
+  std::vector<int2> rows;
+  std::vector<WInst> winst(n);
+  std::map<std::pair<int, double>, int> group_plane0;   // (N, cell) -> first plane
+  std::map<std::pair<int, double>, int> group_n;
+  auto plane_count = [&](int i) {
+    const double half = 0.5 * P->n[i] * P->cell[i];
+    const double r2 = 2.0 * half * half;
+    const double dw = tol / (M_PI * r2);
+    return std::make_pair((int)std::floor(w_max[i] / dw + 0.5) + 1, dw);
+  };
+  for (int i = 0; i < n; ++i) {
+    const auto key = std::make_pair((int)P->n[i], P->cell[i]);
+    group_n[key] = std::max(group_n[key], plane_count(i).first);
+  }
+  int64_t off = 0;
+  int half_max = 0;
+  for (auto& g : group_n) {
+    const int N = g.first.first;
+    const double cell = g.first.second;
+    const double half = 0.5 * N * cell;
+    const double r2 = 2.0 * half * half;
+    const double dw = tol / (M_PI * r2);
+    const double fov = N * cell;
+    group_plane0[g.first] = (int)planes.size();
+    if (N < WP_M) fail(MI_ERR_UNSUPPORTED, "w-projection needs N >= %d (got %d)", WP_M, N);
+    for (int j = 0; j < g.second; ++j) {
+      const int S = 2 * (3 + (int)std::ceil(j * dw * std::sqrt(r2) * fov)) + 1;
+      if (S > WP_SMAX)
+        fail(MI_ERR_UNSUPPORTED, "w-projection support %d > %d cells (w_max too large for N = %d)", S, WP_SMAX, N);
+      const int nd = S * WP_OS + 1;
+      const int p = (int)planes.size();
+      planes.push_back(WPlane{N, S, j * dw, cell, off});
+      for (int r = 0; r < nd; ++r) rows.push_back(make_int2(p, r));
+      off += (int64_t)nd * nd;
+      half_max = std::max(half_max, S * WP_OS / 2);
+    }
+  }
+  if (off * (int64_t)sizeof(double2) > (8LL << 30)) fail(MI_ERR_UNSUPPORTED, "w-projection tables exceed 8 GiB");
+  for (int i = 0; i < n; ++i) {
+    const auto pc = plane_count(i);
+    W->n_planes[i] = pc.first;
+    winst[i] = WInst{group_plane0[std::make_pair((int)P->n[i], P->cell[i])], pc.first, pc.second};
+  }
+  upload(W->planes, planes);
+  upload(W->rows, rows);
+  upload(W->winst, winst);
+  double2* scr = dev_alloc<double2>(W->screen, planes.size() * (size_t)(WP_M - 1) * (WP_M - 1));
+  double2* dft = dev_alloc<double2>(W->dft, (size_t)(2 * half_max + 1) * (WP_M - 1));
+  double2* tabs = dev_alloc<double2>(W->tabs, (size_t)off);
+  HIPCHK(launch_wtables(static_cast<const WPlane*>(W->planes.p), (int)planes.size(),
+                        static_cast<const int2*>(W->rows.p), (int)rows.size(), half_max, ctx->T, scr, dft, tabs, st));
+  P->wproj = std::move(W);
+}
+
+mi_status mi_dirty_image_w(mi_ctx* ctx, const mi_batch* batch, const mi_c64* vis, const float* uv,
+                           const float* w_lambda, const float* w_in, const mi_wproj_params* wp, float* dirty_out,
+                           double* b0_out, int32_t* n_planes_out, hipStream_t stream) {
+  return guard(ctx, [&] {
+    need(vis, "vis");
+    need(uv, "uv");
+    need(w_lambda, "w_lambda");
+    need(w_in, "w_in");
+    need(wp, "params");
+    need(wp->w_max, "params->w_max");
+    need(dirty_out, "dirty_out");
+    const double tol = wp->phase_tol > 0.0 ? wp->phase_tol : 0.1;
+    if (!std::isfinite(tol)) fail(MI_ERR_ARG, "phase_tol must be finite");
+    HIPCHK(hipSetDevice(ctx->device));
+    Plan* P = get_plan(ctx, batch);
+    for (int i = 0; i < P->n_inst; ++i)
+      if (!(wp->w_max[i] >= 0.0) || !std::isfinite(wp->w_max[i])) fail(MI_ERR_ARG, "w_max[%d] must be finite and >= 0", i);
+    if (!P->wproj || P->wproj->tol != tol ||
+        !std::equal(P->wproj->w_max.begin(), P->wproj->w_max.end(), wp->w_max))
+      build_wproj(ctx, P, wp->w_max, tol, stream);
+    Plan::WProj* W = P->wproj.get();
+    run_bin(ctx, P, batch, uv, w_in, false, stream);
+    double2* gd = dev_alloc<double2>(P->gd, P->total_gd);
+    HIPCHK(launch_fill_u32(reinterpret_cast<unsigned*>(gd), 4 * P->total_gd, 0u, stream));
+    HIPCHK(launch_grid_w(static_cast<const InstDesc*>(P->inst.p), P->n_inst, P->max_nvis,
+                         reinterpret_cast<const float2*>(vis), reinterpret_cast<const float2*>(uv), w_lambda, w_in,
+                         static_cast<const float*>(P->wts.p), static_cast<const WInst*>(W->winst.p),
+                         static_cast<const WPlane*>(W->planes.p), static_cast<const double2*>(W->tabs.p), gd,
+                         stream));
+    run_image(ctx, P, dirty_out, stream);
+    copy_b0(P, b0_out, stream);
+    if (n_planes_out) std::copy(W->n_planes.begin(), W->n_planes.end(), n_planes_out);
   });
 }
 

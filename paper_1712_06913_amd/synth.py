@@ -171,6 +171,8 @@ class Workload:
     freq_hz: np.ndarray        # float64 [n]
     gain: float = 0.1
     sky_centre: Optional[np.ndarray] = None   # float64 [n, 2]: true (l, m) of the disk centre (rad)
+    w_lambda: Optional[np.ndarray] = None     # float32 [M]: w coordinate (wavelengths), when the
+                                              # visibilities carry the w-term
 
     @property
     def n_inst(self) -> int:
@@ -179,6 +181,10 @@ class Workload:
     def instance(self, i: int):
         a, b = int(self.vis_offset[i]), int(self.vis_offset[i + 1])
         return self.vis[a:b], self.uv[a:b], self.w[a:b]
+
+    def instance_w(self, i: int):
+        a, b = int(self.vis_offset[i]), int(self.vis_offset[i + 1])
+        return self.w_lambda[a:b]
 
     def subset(self, idx) -> "Workload":
         idx = list(idx)
@@ -195,7 +201,9 @@ class Workload:
             vis_offset=off, n_img=self.n_img[idx].copy(), cell_rad=self.cell_rad[idx].copy(),
             weight_mode=self.weight_mode[idx].copy(), niter=self.niter[idx].copy(),
             freq_hz=self.freq_hz[idx].copy(), gain=self.gain,
-            sky_centre=None if self.sky_centre is None else self.sky_centre[idx].copy())
+            sky_centre=None if self.sky_centre is None else self.sky_centre[idx].copy(),
+            w_lambda=None if self.w_lambda is None else
+            (np.concatenate([self.instance_w(i) for i in idx]) if idx else np.zeros(0, np.float32)))
 
 
 def _instance_vis(bl_en, freq_hz, ha_rad, sky, noise_seed, dec_rad=math.radians(20.0)):
@@ -329,6 +337,35 @@ def offset_disk(seed: int = 7, n: int = 6, sizes=(256, 512), max_offset_px: floa
         centres.append(off)
     wl = _assemble(f"offset_disk_{n}", items)
     wl.sky_centre = np.array(centres, np.float64)
+    return wl
+
+
+def wterm_points(seed: int = 9, n: int = 4, sizes=(256, 512), freq_hz: float = 1.7e9, n_src: int = 4,
+                 dec_deg: float = -23.4, ha_hours=(-4.0, -2.0, 2.0, 4.0)) -> Workload:
+    """Point sources seen with the w-term (the measurement equation with w, closed form):
+    MUSER-II-like array, winter declination and hour angles away from transit (low
+    elevation, so |w| reaches a large fraction of the baseline), sources anywhere within
+    0.4 of the field from the centre, 1 % noise; natural weighting.  w_lambda holds w."""
+    rng = np.random.default_rng(seed)
+    bl = baselines(muser2_array())
+    items, ws = [], []
+    for k in range(n):
+        N = int(sizes[k % len(sizes)])
+        ha = ha_hours[k % len(ha_hours)] * math.pi / 12.0
+        uvw = uvw_metres(bl, ha, math.radians(dec_deg)) * (freq_hz / C_LIGHT)
+        u, v, w = uvw[:, 0], uvw[:, 1], uvw[:, 2]
+        vis = np.zeros(len(u), np.complex128)
+        for _ in range(n_src):
+            l0, m0 = rng.uniform(-0.4, 0.4, 2) * FOV_RAD
+            n0 = math.sqrt(1.0 - l0 * l0 - m0 * m0)
+            vis += rng.uniform(0.5, 2.0) * np.exp(-2j * math.pi * (u * l0 + v * m0 + w * (n0 - 1.0)))
+        sig = 0.01 * np.max(np.abs(vis))
+        vis += sig * (rng.standard_normal(len(u)) + 1j * rng.standard_normal(len(u)))
+        items.append(dict(vis=vis.astype(np.complex64), uv=np.stack([u, v], 1).astype(np.float32),
+                          w=np.ones(len(u), np.float32), N=N, mode=0, niter=500, freq=freq_hz))
+        ws.append(w.astype(np.float32))
+    wl = _assemble(f"wterm_points_{n}", items)
+    wl.w_lambda = np.concatenate(ws).astype(np.float32)
     return wl
 
 
