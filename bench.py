@@ -54,6 +54,14 @@ def synth_arcmin():
     return synth.ARCMIN
 
 
+def synth_w_lambda(name):
+    """w coordinates of the workload's visibilities, where its generator provides them."""
+    from paper_1712_06913_amd import synth
+    if name == "c3":
+        return synth.c3_w_lambda()
+    return None
+
+
 def make_workload(name):
     from paper_1712_06913_amd import synth
     if name == "c1":
@@ -242,6 +250,34 @@ def main():
     torch.cuda.synchronize()
     center_ms = ge[0].elapsed_time(ge[1]) / reps
 
+    # w-projection (not part of the step): dirty images with the w-term corrected, for the
+    # workload's own array geometry (w of each visibility), w_max over the kept visibilities
+    wproj = None
+    w_lambda = synth_w_lambda(args.workload)
+    if w_lambda is not None:
+        wl_t = torch.from_numpy(w_lambda).to(dev)
+        scale = (b.n_img.astype(np.float64) * b.cell_rad)
+        w_max = np.zeros(n_inst)
+        for i in range(n_inst):
+            a0, a1 = int(wl.vis_offset[i]), int(wl.vis_offset[i + 1])
+            g = np.abs(np.floor(np.abs(wl.uv[a0:a1].astype(np.float64) * scale[i]) + 0.5))
+            keep = np.all(g <= b.n_img[i] // 2 - 4, axis=1) & (wl.w[a0:a1] > 0)
+            w_max[i] = float(np.abs(w_lambda[a0:a1][keep].astype(np.float64)).max()) if keep.any() else 0.0
+        wimg, _, n_planes = api.dirty_image_w(b, vis, uv, wl_t, w, w_max)     # builds the kernel tables
+        torch.cuda.synchronize()
+        ge[0].record(stream)
+        for _ in range(reps):
+            api.dirty_image_w(b, vis, uv, wl_t, w, w_max, out=wimg)
+        ge[1].record(stream)
+        torch.cuda.synchronize()
+        wp_ms = ge[0].elapsed_time(ge[1]) / reps
+        r2 = 2.0 * (0.5 * scale) ** 2
+        wproj = {"ms": wp_ms, "planes_min": int(n_planes.min()), "planes_max": int(n_planes.max()),
+                 "w_max_lambda": float(w_max.max()),
+                 "corner_phase_max_rad": float(np.max(np.pi * w_max * r2)),
+                 "kept_vis_per_s": kept / (wp_ms * 1e-3)}
+        log("w-projection stage done")
+
     # roofline of the dominant kernel (k_clean): algorithmic bytes = per iteration the
     # beam window (4 N^2 bytes; the residual stays in LDS) plus once per image the dirty
     # map in, residual + restored out (3 x 4 N^2) and the FP64 model out (8 N^2)
@@ -274,6 +310,7 @@ def main():
         "kept_visibilities": kept,
         "components_total": int(n_comp.sum()),
         "instance_status_nonzero": int(np.count_nonzero(status)),
+        "w_projection": wproj,
         "roofline": roof,
     }
 

@@ -270,6 +270,15 @@ def c3_muser2(n_chan: int = 520, chans: Optional[List[int]] = None, N: int = 102
     return _assemble(f"c3_muser2_{len(chans)}ch_{N}", items)
 
 
+def c3_w_lambda(n_chan: int = 520, chans: Optional[List[int]] = None) -> np.ndarray:
+    """w coordinates (wavelengths, float32, same order as c3_muser2's visibilities) of the
+    MUSER-II-like array at the C3 pointing (hour angle 0, declination +20 deg)."""
+    bl = baselines(muser2_array())
+    chans = list(range(n_chan)) if chans is None else list(chans)
+    w_m = uvw_metres(bl, 0.0, math.radians(20.0))[:, 2]
+    return np.concatenate([w_m * ((2.0125 + 0.025 * c) * 1e9 / C_LIGHT) for c in chans]).astype(np.float32)
+
+
 def c4_uneven(n: int = 256) -> Workload:
     """Uneven serving-style batch: 200..1770 baselines, N in {256,512,1024}, niter 500..5000."""
     pos = muser2_array()
