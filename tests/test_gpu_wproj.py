@@ -90,3 +90,21 @@ def test_wproj_rejects_bad_arguments():
         _gpu(wl, np.array([-1.0]))
     with pytest.raises(nat.MiError):
         _gpu(wl, np.array([float("nan")]))
+
+
+def test_wproj_mixed_sizes_and_uniform_weighting():
+    log("[wproj] mixed N (plane groups per (N, cell)) and uniform weighting vs the oracle")
+    require_gpu()
+    wl = synth.wterm_points(seed=15, n=4, sizes=(64, 128, 256, 128), freq_hz=0.3e9)
+    wl.weight_mode = np.array([1, 0, 1, 1], np.int8)
+    w_max = _w_max(wl)
+    w_max[3] *= 1.5                      # a looser bound: more planes for the same group
+    b, imgs, b0, n_planes = _gpu(wl, w_max)
+    for i in range(wl.n_inst):
+        v, uv, w_in = wl.instance(i)
+        N, cell, mode = int(wl.n_img[i]), float(wl.cell_rad[i]), int(wl.weight_mode[i])
+        ref, (dw, np_ref, sup) = wproj.dirty_image_w(v, uv, wl.instance_w(i), w_in, N, cell, mode, w_max[i])
+        err = max_abs(imgs[i].cpu().numpy(), ref)
+        log(f"  inst {i} N={N} mode={mode}: planes {n_planes[i]} / {np_ref}, max|err| {err:.3e}")
+        assert n_planes[i] == np_ref
+        assert err <= 1e-5 * np.abs(ref).max()
