@@ -204,9 +204,12 @@ k_bin(const InstDesc* __restrict__ inst, const float2* __restrict__ uv, const fl
 // staged in LDS, so a run of empty tiles is a stream of stores with no dependent global
 // loads).  A non-empty tile stages up to GRID_EB of its samples' parameters in LDS, then
 // spreads (sample, tap row) pairs over all threads; accumulation is FP64 in LDS (the grid
-// correction later amplifies grid rounding by up to ~1e6 in the map corners).
+// correction later amplifies grid rounding by up to ~1e6 in the map corners).  Eight
+// tiles per workgroup measured fastest (32: 1.1 ms slower per 520 x 1024^2 dirty + beam
+// batch, the few dense tiles near each uv centre holding their workgroup longer; 2-4:
+// more per-workgroup setup).
 constexpr int GRID_THREADS = 256;
-constexpr int GRID_CHUNK = 32;
+constexpr int GRID_CHUNK = 8;
 constexpr int GRID_EB = 256;
 
 // Grid cell stores: FP64 complex or complex64 (mi_grid output); the real FP64 beam grid
