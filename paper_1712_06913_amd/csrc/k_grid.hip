@@ -224,7 +224,9 @@ k_grid(const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst, int
        const float* __restrict__ wts, const int* __restrict__ ent,
        const int* __restrict__ tstart, const int* __restrict__ tcount, Tables T,
        OutT* __restrict__ grid, int modulate) {
+  constexpr bool REAL = std::is_same<OutT, double>::value;
   __shared__ double2 acc[TK * TJ];
+  double* accr = reinterpret_cast<double*>(acc);       // real grids: one double per cell
   __shared__ double tab[TAB_LEN];
   __shared__ int m_inst[GRID_CHUNK], m_start[GRID_CHUNK], m_cnt[GRID_CHUNK];
   __shared__ int s_kp[GRID_EB], s_j[GRID_EB], s_ou[GRID_EB], s_ov[GRID_EB];
@@ -262,7 +264,11 @@ k_grid(const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst, int
       }
       continue;
     }
-    for (int q = tid; q < TK * TJ; q += GRID_THREADS) acc[q] = make_double2(0.0, 0.0);
+    if constexpr (REAL) {
+      for (int q = tid; q < TK * TJ / 2; q += GRID_THREADS) acc[q] = make_double2(0.0, 0.0);
+    } else {
+      for (int q = tid; q < TK * TJ; q += GRID_THREADS) acc[q] = make_double2(0.0, 0.0);
+    }
     const int st = m_start[tt];
     for (int e0 = 0; e0 < n; e0 += GRID_EB) {
       const int ne = min(GRID_EB, n - e0);
@@ -299,17 +305,22 @@ k_grid(const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst, int
           const int j = jb + dv;
           if (j < j0 || j >= j0 + TJ) continue;
           const double kk = tu * tab[dv * OS - ov + TAB_CENTRE];
-          double* a = reinterpret_cast<double*>(&acc[(kp - k0) * TJ + (j - j0)]);
-          atomicAdd(a, wr * kk);
-          if (!beam) atomicAdd(a + 1, wim * kk);
+          const int c = (kp - k0) * TJ + (j - j0);
+          if constexpr (REAL) {
+            atomicAdd(accr + c, wr * kk);
+          } else {
+            double* a = reinterpret_cast<double*>(&acc[c]);
+            atomicAdd(a, wr * kk);
+            if (!beam) atomicAdd(a + 1, wim * kk);
+          }
         }
       }
     }
     __syncthreads();
-    if constexpr (std::is_same<OutT, double>::value) {     // real cells, two per 16-byte store
+    if constexpr (REAL) {                                  // real cells, two per 16-byte store
       for (int q = tid; q < TK * TJ / 2; q += GRID_THREADS) {
         const int l = 2 * q / TJ, jj = 2 * q % TJ;
-        double2 val = make_double2(acc[2 * q].x, acc[2 * q + 1].x);
+        double2 val = acc[q];                              // cells 2q and 2q + 1
         if (modulate) {
           if (((k0 + l + 1) + (j0 + jj)) & 1) val.x = -val.x;
           else val.y = -val.y;
