@@ -77,6 +77,14 @@ def test_c3_two_channels_1024():
     _image_parity(synth.c3_muser2(chans=[0, 519]))
 
 
+def test_largest_image_sizes_2048_and_4096():
+    # the largest transforms: a 4096^2 beam (P = 4096, one complex line per block) and an
+    # 8192^2 beam (P = 8192, the 8192-element LDS blocks)
+    log("[imaging] largest sizes: 2048^2 and 4096^2 (beams 4096^2 and 8192^2)")
+    wl = synth.random_instances(31, [2048, 4096], m_range=(150, 200))
+    _image_parity(wl)
+
+
 def test_empty_and_flagged_instances():
     log("[imaging] empty instance")
     wl = synth.random_instances(3, [64, 128], m_range=(20, 20))
