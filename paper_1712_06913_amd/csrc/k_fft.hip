@@ -300,15 +300,17 @@ k_fft_b_c2r(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
     const double inv_b0 = bd > 0.0 ? 1.0 / bd : 0.0;
     const double* ic = T.inv_corr + (P - 64);
     float* o = out + d.img_off + (int64_t)y0 * P;
-    for (int q = threadIdx.x; q < nz * P; q += THREADS) {   // rows y0 + 2 zl and y0 + 2 zl + 1
+    for (int q2 = threadIdx.x; q2 < nz * P / 2; q2 += THREADS) {   // pixels x, x + 1 of rows y0 + 2 zl, + 1
+      const int q = 2 * q2;
       const int zl = q >> log2P, x = q & (P - 1);
       const int y = y0 + 2 * zl;
-      double s0 = ic[x] * (ic[y] * inv_b0), s1 = ic[x] * (ic[y + 1] * inv_b0);
-      if ((x + y) & 1) s0 = -s0;
-      else s1 = -s1;
-      const double2 z = buf[pd(q)];
-      o[((2 * zl) << log2P) + x] = (float)(z.x * s0);
-      o[((2 * zl + 1) << log2P) + x] = (float)(z.y * s1);
+      const double ry = ic[y] * inv_b0, ry1 = ic[y + 1] * inv_b0;
+      double s0 = ic[x] * ry, s1 = ic[x] * ry1, t0 = ic[x + 1] * ry, t1 = ic[x + 1] * ry1;
+      if ((x + y) & 1) { s0 = -s0; t1 = -t1; }
+      else { s1 = -s1; t0 = -t0; }
+      const double2 z = buf[pd(q)], zz = buf[pd(q + 1)];
+      *reinterpret_cast<float2*>(o + ((2 * zl) << log2P) + x) = make_float2((float)(z.x * s0), (float)(zz.x * t0));
+      *reinterpret_cast<float2*>(o + ((2 * zl + 1) << log2P) + x) = make_float2((float)(z.y * s1), (float)(zz.y * t1));
     }
     __syncthreads();
   }
