@@ -472,26 +472,41 @@ k_fft_b_c2r_sym(const InstDesc* __restrict__ inst, const FftWork* __restrict__ w
     const double* ic = T.inv_corr + (P - 64);
     float* o = out + d.beam_off;
     const int npair = (min(ny, h + 1 - y0) + 1) / 2;
-    for (int q = threadIdx.x; q < npair * P; q += THREADS) {   // rows ya = y0 + 2 zl and ya + 1
+    for (int q2 = threadIdx.x; q2 < npair * P / 2; q2 += THREADS) {   // pixels x, x + 1 of rows ya, ya + 1
+      const int q = 2 * q2;
       const int zl = q >> log2P, x = q & (P - 1);
       const int ya = y0 + 2 * zl;
+      const int row = zl << log2P;
+      float fa[2], fb[2];
       if (ya == h) {                       // row P/2: its right half mirrors its left half
-        const int xs = x > h ? P - x : x;
-        double s = ic[xs] * (ic[ya] * inv_b0);
-        if ((xs + ya) & 1) s = -s;
-        o[(ya << log2P) + x] = (float)(buf[pd((zl << log2P) + xs)].x * s);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int xs = x + e > h ? P - x - e : x + e;
+          double s = ic[xs] * (ic[ya] * inv_b0);
+          if ((xs + ya) & 1) s = -s;
+          fa[e] = (float)(buf[pd(row + xs)].x * s);
+        }
+        *reinterpret_cast<float2*>(o + (ya << log2P) + x) = make_float2(fa[0], fa[1]);
         continue;
       }
-      double s0 = ic[x] * (ic[ya] * inv_b0), s1 = ic[x] * (ic[ya + 1] * inv_b0);
-      if ((x + ya) & 1) s0 = -s0;
-      else s1 = -s1;
-      const double2 z = buf[pd(q)];
-      const float f0 = (float)(z.x * s0), f1 = (float)(z.y * s1);
-      const int xm = (P - x) & (P - 1);
-      o[(ya << log2P) + x] = f0;
-      if (ya > 0) o[((P - ya) << log2P) + xm] = f0;
-      o[((ya + 1) << log2P) + x] = f1;     // 0 < ya + 1 < P/2: always mirrored
-      o[((P - ya - 1) << log2P) + xm] = f1;
+      const double ra = ic[ya] * inv_b0, rb = ic[ya + 1] * inv_b0;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        double sa = ic[x + e] * ra, sb = ic[x + e] * rb;
+        if ((x + e + ya) & 1) sa = -sa;
+        else sb = -sb;
+        const double2 z = buf[pd(row + x + e)];
+        fa[e] = (float)(z.x * sa);
+        fb[e] = (float)(z.y * sb);
+      }
+      *reinterpret_cast<float2*>(o + (ya << log2P) + x) = make_float2(fa[0], fa[1]);
+      *reinterpret_cast<float2*>(o + ((ya + 1) << log2P) + x) = make_float2(fb[0], fb[1]);
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int xm = (P - x - e) & (P - 1);
+        if (ya > 0) o[((P - ya) << log2P) + xm] = fa[e];
+        o[((P - ya - 1) << log2P) + xm] = fb[e];
+      }
     }
     __syncthreads();
   }
