@@ -515,70 +515,128 @@ k_fft_b_c2r_sym(const InstDesc* __restrict__ inst, const FftWork* __restrict__ w
 // Adjoint pass B^T: image rows -> pre-correction and (-1)^(x+y) -> forward FFT along x ->
 // keep u frequencies 1..P/2 -> blocked layout.  Two real rows per complex line, separated
 // after the transform by X1 = (Z[k] + conj Z[-k]) / 2, X2 = (Z[k] - conj Z[-k]) / 2i.
+// Persistent with the next item's image rows prefetched into registers, like the inverse.
 template <int ELEMS, int THREADS>
 __global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES_PER_EU(ELEMS))))
-k_fft_b_r2c(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
+k_fft_b_r2c(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int n_work,
             const float* __restrict__ img, Tables T, double2* __restrict__ yb) {
   __shared__ double2 buf[LDS_PADDED(ELEMS)];
-  const FftWork wk = work[blockIdx.x];
-  const InstDesc d = inst[wk.inst];
-  const int P = d.N, log2P = ilog2(P), h = P / 2;
-  const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
-  const int ny = rows_per_block<ELEMS>(P), nz = ny / 2;
-  const int y0 = wk.first;
-  const double* ic = T.inv_corr + (P - 64);
-  const float* src = img + d.img_off + (int64_t)y0 * P;
-  for (int q = threadIdx.x; q < nz * P; q += THREADS) {
-    const int zl = q >> log2P, x = q & (P - 1);
-    const int y = y0 + 2 * zl;
-    double s = ic[x] * ic[y], s2 = ic[x] * ic[y + 1];
-    if ((x + y) & 1) s = -s;
-    else s2 = -s2;
-    const float* r0 = src + ((int64_t)(2 * zl) << log2P) + x;
-    buf[pd(q)] = make_double2((double)r0[0] * s, (double)r0[P] * s2);
-  }
-  __syncthreads();
-  lds_fft<ELEMS, THREADS>(buf, log2P, nz, -1.0, T.twiddle);
-  double2* dst = yb + d.gd_off;
-  const int nblk = h / nl, per_blk = nz * nl;
-  for (int q = threadIdx.x; q < nblk * per_blk; q += THREADS) {
-    const int b = q / per_blk, r = q - b * per_blk;
-    const int zl = r >> log2nl, l = r & (nl - 1);
-    const int k = b * nl + l + 1;
-    const double2 A = buf[pd((zl << log2P) + k)];
-    const double2 B = buf[pd((zl << log2P) + ((P - k) & (P - 1)))];
-    // X1 = (A + conj B) / 2,  X2 = -i (A - conj B) / 2
-    const double2 x1 = make_double2(0.5 * (A.x + B.x), 0.5 * (A.y - B.y));
-    const double2 x2 = make_double2(0.5 * (A.y + B.y), -0.5 * (A.x - B.x));
-    const int64_t e = (int64_t)b * nl * P + (int64_t)(y0 + 2 * zl) * nl + l;
-    dst[e] = x1;
-    dst[e + nl] = x2;
+  constexpr int NPT = ELEMS / THREADS;
+  float ra[NPT], rb[NPT];
+  auto fetch = [&](int wi) {
+    const FftWork wk = work[wi];
+    const InstDesc d = inst[wk.inst];
+    const int P = d.N, log2P = ilog2(P);
+    const int nz = rows_per_block<ELEMS>(P) / 2;
+    const float* src = img + d.img_off + (int64_t)wk.first * P;
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int q = threadIdx.x + i * THREADS;
+      if (q < nz * P) {
+        const int zl = q >> log2P, x = q & (P - 1);
+        const float* r0 = src + ((int64_t)(2 * zl) << log2P) + x;
+        ra[i] = r0[0];
+        rb[i] = r0[P];
+      }
+    }
+  };
+  int w = blockIdx.x;
+  if (w < n_work) fetch(w);
+  for (; w < n_work; w += gridDim.x) {
+    const FftWork wk = work[w];
+    const InstDesc d = inst[wk.inst];
+    const int P = d.N, log2P = ilog2(P), h = P / 2;
+    const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
+    const int ny = rows_per_block<ELEMS>(P), nz = ny / 2;
+    const int y0 = wk.first;
+    const double* ic = T.inv_corr + (P - 64);
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int q = threadIdx.x + i * THREADS;
+      if (q < nz * P) {
+        const int zl = q >> log2P, x = q & (P - 1);
+        const int y = y0 + 2 * zl;
+        double s = ic[x] * ic[y], s2 = ic[x] * ic[y + 1];
+        if ((x + y) & 1) s = -s;
+        else s2 = -s2;
+        buf[pd(q)] = make_double2((double)ra[i] * s, (double)rb[i] * s2);
+      }
+    }
+    __syncthreads();
+    if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
+    lds_fft<ELEMS, THREADS>(buf, log2P, nz, -1.0, T.twiddle);
+    double2* dst = yb + d.gd_off;
+    const int nblk = h / nl, per_blk = nz * nl;
+    for (int q = threadIdx.x; q < nblk * per_blk; q += THREADS) {
+      const int b = q / per_blk, r = q - b * per_blk;
+      const int zl = r >> log2nl, l = r & (nl - 1);
+      const int k = b * nl + l + 1;
+      const double2 A = buf[pd((zl << log2P) + k)];
+      const double2 B = buf[pd((zl << log2P) + ((P - k) & (P - 1)))];
+      // X1 = (A + conj B) / 2,  X2 = -i (A - conj B) / 2
+      const double2 x1 = make_double2(0.5 * (A.x + B.x), 0.5 * (A.y - B.y));
+      const double2 x2 = make_double2(0.5 * (A.y + B.y), -0.5 * (A.x - B.x));
+      const int64_t e = (int64_t)b * nl * P + (int64_t)(y0 + 2 * zl) * nl + l;
+      dst[e] = x1;
+      dst[e + nl] = x2;
+    }
+    __syncthreads();
   }
 }
 
 // Adjoint pass A^T: blocked layout -> forward FFT along v -> (-1)^(i+j) -> half grid lines.
+// Persistent; half of the next item is prefetched (within 128 VGPRs), as in pass A.
 template <int ELEMS, int THREADS>
 __global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES_PER_EU(ELEMS))))
-k_fft_a_fwd(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, Tables T,
-            double2* __restrict__ grid) {
+k_fft_a_fwd(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int n_work, Tables T,
+            double2* grid) {
   __shared__ double2 buf[LDS_PADDED(ELEMS)];
-  const FftWork wk = work[blockIdx.x];
-  const InstDesc d = inst[wk.inst];
-  const int P = d.N, log2P = ilog2(P);
-  const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
-  double2* blk = grid + d.gd_off + (int64_t)wk.first * P;
-  const int n = nl * P;
-  for (int q = threadIdx.x; q < n; q += THREADS) {
-    const int y = q >> log2nl, l = q & (nl - 1);
-    buf[pd((l << log2P) + y)] = blk[q];
-  }
-  __syncthreads();
-  lds_fft<ELEMS, THREADS>(buf, log2P, nl, -1.0, T.twiddle);
-  for (int q = threadIdx.x; q < n; q += THREADS) {
-    const int l = q >> log2P, j = q & (P - 1);
-    double2 v = buf[pd(q)];
-    if (((wk.first + l + 1) + j) & 1) { v.x = -v.x; v.y = -v.y; }
-    blk[q] = v;
+  constexpr int NPT = ELEMS / THREADS;
+  constexpr int NPF = NPT / 2;
+  double2 r[NPF];
+  auto fetch = [&](int wi) {
+    const FftWork wk = work[wi];
+    const InstDesc d = inst[wk.inst];
+    const int P = d.N, n = lines_per_block<ELEMS>(P) * P;
+    const double2* blk = grid + d.gd_off + (int64_t)wk.first * P;
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) {
+      const int q = threadIdx.x + i * THREADS;
+      if (q < n) {
+        const double2 v = blk[q];
+        r[i] = make_double2(v.x, v.y);   // component copy keeps r[] in registers
+      }
+    }
+  };
+  int w = blockIdx.x;
+  if (w < n_work) fetch(w);
+  for (; w < n_work; w += gridDim.x) {
+    const FftWork wk = work[w];
+    const InstDesc d = inst[wk.inst];
+    const int P = d.N, log2P = ilog2(P);
+    const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
+    const int n = nl * P;
+    double2* blk = grid + d.gd_off + (int64_t)wk.first * P;
+#pragma unroll
+    for (int i = NPF; i < NPT; ++i) {
+      const int q = threadIdx.x + i * THREADS;
+      if (q < n) buf[pd(((q & (nl - 1)) << log2P) + (q >> log2nl))] = blk[q];
+    }
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) {
+      const int q = threadIdx.x + i * THREADS;
+      if (q < n) buf[pd(((q & (nl - 1)) << log2P) + (q >> log2nl))] = r[i];
+    }
+    __syncthreads();
+    if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
+    lds_fft<ELEMS, THREADS>(buf, log2P, nl, -1.0, T.twiddle);
+    for (int q = threadIdx.x; q < n; q += THREADS) {
+      const int l = q >> log2P, j = q & (P - 1);
+      double2 v = buf[pd(q)];
+      if (((wk.first + l + 1) + j) & 1) { v.x = -v.x; v.y = -v.y; }
+      blk[q] = v;
+    }
+    __syncthreads();
   }
 }
 
@@ -622,13 +680,6 @@ k_fft_c2c_t(const int* __restrict__ n_arr, const int64_t* __restrict__ offs, con
 // ---- host launchers.  elems selects the LDS block: 4096 complex doubles (72 KB with
 // padding, 512 threads, two workgroups per CU) or 8192 (144 KB, 512 threads, needed only
 // for P = 8192).
-#define MI_FFT_DISPATCH(KERNEL, ...)                                                              \
-  do {                                                                                            \
-    if (elems == 8192)                                                                            \
-      hipLaunchKernelGGL((KERNEL<8192, 512>), dim3(n_work), dim3(512), 0, st, __VA_ARGS__);       \
-    else                                                                                          \
-      hipLaunchKernelGGL((KERNEL<4096, 512>), dim3(n_work), dim3(512), 0, st, __VA_ARGS__);       \
-  } while (0)
 
 // Persistent passes: as many workgroups as are resident at once (or fewer items).
 template <class Kern>
@@ -671,16 +722,16 @@ hipError_t launch_fft_b_c2r_sym(int elems, int n_cu, const InstDesc* inst, const
   MI_FFT_PERSISTENT(k_fft_b_c2r_sym, inst, work, n_work, grid, b0, T, out);
   return hipGetLastError();
 }
-hipError_t launch_fft_b_r2c(int elems, const InstDesc* inst, const FftWork* work, int n_work, const float* img,
-                            const Tables& T, double2* yb, hipStream_t st) {
+hipError_t launch_fft_b_r2c(int elems, int n_cu, const InstDesc* inst, const FftWork* work, int n_work,
+                            const float* img, const Tables& T, double2* yb, hipStream_t st) {
   if (n_work <= 0) return hipSuccess;
-  MI_FFT_DISPATCH(k_fft_b_r2c, inst, work, img, T, yb);
+  MI_FFT_PERSISTENT(k_fft_b_r2c, inst, work, n_work, img, T, yb);
   return hipGetLastError();
 }
-hipError_t launch_fft_a_fwd(int elems, const InstDesc* inst, const FftWork* work, int n_work, const Tables& T,
-                            double2* grid, hipStream_t st) {
+hipError_t launch_fft_a_fwd(int elems, int n_cu, const InstDesc* inst, const FftWork* work, int n_work,
+                            const Tables& T, double2* grid, hipStream_t st) {
   if (n_work <= 0) return hipSuccess;
-  MI_FFT_DISPATCH(k_fft_a_fwd, inst, work, T, grid);
+  MI_FFT_PERSISTENT(k_fft_a_fwd, inst, work, n_work, T, grid);
   return hipGetLastError();
 }
 hipError_t launch_fft_c2c_t_f2d(int elems, const int* n_arr, const int64_t* offs, const FftWork* work, int n_work,

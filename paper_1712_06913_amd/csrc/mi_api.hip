@@ -50,9 +50,9 @@ hipError_t launch_fft_b_c2r(int, int, const InstDesc*, const FftWork*, int, cons
 hipError_t launch_fft_a_real(int, int, const InstDesc*, const FftWork*, int, double*, const Tables&, hipStream_t);
 hipError_t launch_fft_b_c2r_sym(int, int, const InstDesc*, const FftWork*, int, const double*, const double*,
                                 const Tables&, float*, hipStream_t);
-hipError_t launch_fft_b_r2c(int, const InstDesc*, const FftWork*, int, const float*, const Tables&, double2*,
+hipError_t launch_fft_b_r2c(int, int, const InstDesc*, const FftWork*, int, const float*, const Tables&, double2*,
                             hipStream_t);
-hipError_t launch_fft_a_fwd(int, const InstDesc*, const FftWork*, int, const Tables&, double2*, hipStream_t);
+hipError_t launch_fft_a_fwd(int, int, const InstDesc*, const FftWork*, int, const Tables&, double2*, hipStream_t);
 hipError_t launch_fft_c2c_t_f2d(int, const int*, const int64_t*, const FftWork*, int, const float2*, double2*,
                                 const Tables&, double, int, int, hipStream_t);
 hipError_t launch_fft_c2c_t_d2f(int, const int*, const int64_t*, const FftWork*, int, const double2*, float2*,
@@ -1105,9 +1105,9 @@ mi_status mi_degrid(mi_ctx* ctx, const mi_batch* batch, const float* image, cons
     run_bin(ctx, P, batch, uv, w_in, false, stream);
     double2* g = dev_alloc<double2>(P->gd, P->total_gd);
     const InstDesc* inst = static_cast<const InstDesc*>(P->inst.p);
-    HIPCHK(launch_fft_b_r2c(P->elems_d, inst, static_cast<const FftWork*>(P->wb_d.p), P->n_wb_d, image, ctx->T, g,
+    HIPCHK(launch_fft_b_r2c(P->elems_d, ctx->n_cu, inst, static_cast<const FftWork*>(P->wb_d.p), P->n_wb_d, image, ctx->T, g,
                             stream));
-    HIPCHK(launch_fft_a_fwd(P->elems_d, inst, static_cast<const FftWork*>(P->wa_d.p), P->n_wa_d, ctx->T, g, stream));
+    HIPCHK(launch_fft_a_fwd(P->elems_d, ctx->n_cu, inst, static_cast<const FftWork*>(P->wa_d.p), P->n_wa_d, ctx->T, g, stream));
     HIPCHK(launch_degrid(inst, P->n_inst, P->max_nvis, reinterpret_cast<const float2*>(uv), w_in,
                          static_cast<const float*>(P->wts.p), static_cast<const double*>(P->b0.p), g, ctx->T,
                          adjoint, reinterpret_cast<float2*>(vis_out), stream));
