@@ -28,7 +28,7 @@ k_corr_prep(const InstDesc* __restrict__ inst, const float* __restrict__ images,
     const int y = (int)(q >> d.log2N), x = (int)(q & (N - 1));
     const double dx = x - h, dy = y - h;
     X[d.img_off + q] = make_double2((double)images[d.img_off + q], 0.0);
-    D[d.img_off + q] = make_double2(dx * dx + dy * dy <= r2 ? 1.0 : 0.0, 0.0);
+    if (D) D[d.img_off + q] = make_double2(dx * dx + dy * dy <= r2 ? 1.0 : 0.0, 0.0);   // null: model cached
   }
 }
 

@@ -185,6 +185,7 @@ struct Plan {
   // disk centering: radii (host copy for change detection), 2-D transform work list, buffers
   std::vector<double> radius;
   int corr_elems = 0, corr_nwork = 0;
+  bool corr_model_ready = false;      // corr_d holds the disk models' transforms for `radius`
   DevBuf radius_d, corr_n, corr_offs, corr_work, corr_x, corr_d, corr_s, offsets_ws;
 };
 
@@ -655,6 +656,7 @@ mi_status mi_disk_offsets(mi_ctx* ctx, const mi_batch* batch, const float* image
     if (P->radius.size() != (size_t)n || !std::equal(P->radius.begin(), P->radius.end(), radius_px)) {
       P->radius.assign(radius_px, radius_px + n);
       upload(P->radius_d, P->radius);
+      P->corr_model_ready = false;
     }
     if (!P->corr_work.p) {                              // 2-D transform plan over the packed maps
       std::vector<int32_t> nn(P->n.begin(), P->n.end());
@@ -681,12 +683,17 @@ mi_status mi_disk_offsets(mi_ctx* ctx, const mi_batch* batch, const float* image
     const int64_t* od = static_cast<const int64_t*>(P->corr_offs.p);
     const FftWork* wk = static_cast<const FftWork*>(P->corr_work.p);
     const int e = P->corr_elems, nw = P->corr_nwork;
-    HIPCHK(launch_corr_prep(inst, n, P->max_N, images, static_cast<const double*>(P->radius_d.p), X, D, stream));
+    const bool model = !P->corr_model_ready;            // the disk models' transforms are kept
+    HIPCHK(launch_corr_prep(inst, n, P->max_N, images, static_cast<const double*>(P->radius_d.p), X,
+                            model ? D : nullptr, stream));
     // forward 2-D DFTs (two line passes with transposed writes), plain (no centring)
     HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, nw, X, S, ctx->T, -1.0, 0, 0, stream));
     HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, nw, S, X, ctx->T, -1.0, 0, 0, stream));
-    HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, nw, D, S, ctx->T, -1.0, 0, 0, stream));
-    HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, nw, S, D, ctx->T, -1.0, 0, 0, stream));
+    if (model) {
+      HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, nw, D, S, ctx->T, -1.0, 0, 0, stream));
+      HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, nw, S, D, ctx->T, -1.0, 0, 0, stream));
+      P->corr_model_ready = true;
+    }
     HIPCHK(launch_corr_mul(X, D, total, stream));
     HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, nw, X, S, ctx->T, +1.0, 0, 0, stream));
     HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, nw, S, X, ctx->T, +1.0, 0, 0, stream));
