@@ -109,3 +109,24 @@ def test_improved_clean_chain():
         log(f"  inst {i}: centring error {err:.2f} px, mu_a {levels[i, 0].item():.3e}, {nc[i]} components")
         assert err < 5.0 and 0 < nc[i] <= 1500
     assert torch.isfinite(res["restored"]).all()
+
+
+def test_disk_offsets_follow_a_change_of_radius():
+    log("[center] the cached disk-model transforms follow a change of radius")
+    require_gpu()
+    from paper_1712_06913_amd import api
+    wl = synth.offset_disk(n=2, sizes=(128, 256))
+    maps = []
+    for i in range(wl.n_inst):
+        v, uv, w = wl.instance(i)
+        maps.append(imager.dirty_image(v, uv, w, int(wl.n_img[i]), float(wl.cell_rad[i]), 0).astype(np.float32))
+    b = api.Batch.from_workload(wl)
+    imgs = torch.from_numpy(np.concatenate([m.ravel() for m in maps])).cuda()
+    r1 = np.array([16.0 * synth.ARCMIN / c for c in wl.cell_rad])
+    r2 = 0.6 * r1
+    for radius in (r1, r2, r2, r1):
+        off = api.disk_offsets(b, imgs, radius).cpu().numpy()
+        for i, m in enumerate(maps):
+            cell = float(wl.cell_rad[i])
+            ref = centering.disk_offset(m.astype(np.float64), radius[i], cell)
+            assert abs(off[i, 0] - ref[0]) <= 1e-9 * cell and abs(off[i, 1] - ref[1]) <= 1e-9 * cell
