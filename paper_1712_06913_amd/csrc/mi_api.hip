@@ -40,8 +40,11 @@ hipError_t launch_expand_full(const InstDesc*, int, int, const double2*, float2*
 hipError_t launch_fill_u32(unsigned*, int64_t, unsigned, hipStream_t);
 hipError_t launch_wtables(const WPlane*, int, const int2*, int, int, const Tables&, double2*, double2*, double2*,
                           hipStream_t);
-hipError_t launch_grid_w(const InstDesc*, int, int, const float2*, const float2*, const float*, const float*,
-                         const float*, const WInst*, const WPlane*, const double2*, double2*, hipStream_t);
+hipError_t launch_bin_w(const InstDesc*, int, size_t, const float2*, const float*, const float*, const WInst*,
+                       const WPlane*, int*, int*, int*, hipStream_t);
+hipError_t launch_grid_wt(const InstDesc*, const int*, int, const float2*, const float2*, const float*, const float*,
+                          const float*, const int*, const int*, const int*, const WInst*, const WPlane*,
+                          const double2*, double2*, hipStream_t);
 hipError_t launch_grid_real(const InstDesc*, const int*, int, const float2*, const float*, const float*, const int*,
                             const int*, const int*, const Tables&, double*, hipStream_t);
 hipError_t launch_fft_a(int, int, const InstDesc*, const FftWork*, int, double2*, const Tables&, hipStream_t);
@@ -179,7 +182,7 @@ struct Plan {
     std::vector<double> w_max;
     double tol = 0.0;
     std::vector<int32_t> n_planes;   // per instance
-    DevBuf planes, rows, winst, screen, dft, tabs;
+    DevBuf planes, rows, winst, screen, dft, tabs, ent, ts, tc;
   };
   std::unique_ptr<WProj> wproj;
   // disk centering: radii (host copy for change detection), 2-D transform work list, buffers
@@ -952,12 +955,20 @@ mi_status mi_dirty_image_w(mi_ctx* ctx, const mi_batch* batch, const mi_c64* vis
     Plan::WProj* W = P->wproj.get();
     run_bin(ctx, P, batch, uv, w_in, false, stream);
     double2* gd = dev_alloc<double2>(P->gd, P->total_gd);
-    HIPCHK(launch_fill_u32(reinterpret_cast<unsigned*>(gd), 4 * P->total_gd, 0u, stream));
-    HIPCHK(launch_grid_w(static_cast<const InstDesc*>(P->inst.p), P->n_inst, P->max_nvis,
-                         reinterpret_cast<const float2*>(vis), reinterpret_cast<const float2*>(uv), w_lambda, w_in,
-                         static_cast<const float*>(P->wts.p), static_cast<const WInst*>(W->winst.p),
-                         static_cast<const WPlane*>(W->planes.p), static_cast<const double2*>(W->tabs.p), gd,
-                         stream));
+    if ((int64_t)WP_ENT * P->total_vis >= (1LL << 31)) fail(MI_ERR_SHAPE, "batch too large for w-projection binning");
+    int* ent = dev_alloc<int>(W->ent, (size_t)WP_ENT * P->total_vis);
+    int* ts = dev_alloc<int>(W->ts, P->tiles_d);
+    int* tc = dev_alloc<int>(W->tc, P->tiles_d);
+    const InstDesc* inst = static_cast<const InstDesc*>(P->inst.p);
+    const WInst* winst = static_cast<const WInst*>(W->winst.p);
+    const WPlane* planes = static_cast<const WPlane*>(W->planes.p);
+    const size_t lds = (size_t)(P->max_N / 2 / TK) * (P->max_N / TJ) * sizeof(int);
+    HIPCHK(launch_bin_w(inst, P->n_inst, lds, reinterpret_cast<const float2*>(uv), w_in, w_lambda, winst, planes, ent,
+                        ts, tc, stream));
+    HIPCHK(launch_grid_wt(inst, static_cast<const int*>(P->tile_inst_d.p), P->tiles_d,
+                          reinterpret_cast<const float2*>(vis), reinterpret_cast<const float2*>(uv), w_lambda, w_in,
+                          static_cast<const float*>(P->wts.p), ent, ts, tc, winst, planes,
+                          static_cast<const double2*>(W->tabs.p), gd, stream));
     run_image(ctx, P, dirty_out, stream);
     copy_b0(P, b0_out, stream);
     if (n_planes_out) std::copy(W->n_planes.begin(), W->n_planes.end(), n_planes_out);

@@ -8,6 +8,7 @@ namespace mi {
 constexpr int WP_M = 64;        // field points per axis in the kernel construction (minus one, symmetric)
 constexpr int WP_OS = 16;       // kernel table points per cell
 constexpr int WP_SMAX = 63;     // largest kernel support (cells)
+constexpr int WP_ENT = 20;      // (sample, tile) entries per visibility: 2 samples x at most 5 x 2 tiles
 
 // One w-plane of one (N, cell) group of instances.
 struct WPlane {
