@@ -300,17 +300,23 @@ k_fft_b_c2r(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
     const double inv_b0 = bd > 0.0 ? 1.0 / bd : 0.0;
     const double* ic = T.inv_corr + (P - 64);
     float* o = out + d.img_off + (int64_t)y0 * P;
-    for (int q2 = threadIdx.x; q2 < nz * P / 2; q2 += THREADS) {   // pixels x, x + 1 of rows y0 + 2 zl, + 1
-      const int q = 2 * q2;
+    for (int q4 = threadIdx.x; q4 < nz * P / 4; q4 += THREADS) {   // pixels x .. x + 3 of rows y0 + 2 zl, + 1
+      const int q = 4 * q4;
       const int zl = q >> log2P, x = q & (P - 1);
       const int y = y0 + 2 * zl;
       const double ry = ic[y] * inv_b0, ry1 = ic[y + 1] * inv_b0;
-      double s0 = ic[x] * ry, s1 = ic[x] * ry1, t0 = ic[x + 1] * ry, t1 = ic[x + 1] * ry1;
-      if ((x + y) & 1) { s0 = -s0; t1 = -t1; }
-      else { s1 = -s1; t0 = -t0; }
-      const double2 z = buf[pd(q)], zz = buf[pd(q + 1)];
-      *reinterpret_cast<float2*>(o + ((2 * zl) << log2P) + x) = make_float2((float)(z.x * s0), (float)(zz.x * t0));
-      *reinterpret_cast<float2*>(o + ((2 * zl + 1) << log2P) + x) = make_float2((float)(z.y * s1), (float)(zz.y * t1));
+      float fa[4], fb[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        double s0 = ic[x + e] * ry, s1 = ic[x + e] * ry1;
+        if ((x + e + y) & 1) s0 = -s0;
+        else s1 = -s1;
+        const double2 z = buf[pd(q + e)];
+        fa[e] = (float)(z.x * s0);
+        fb[e] = (float)(z.y * s1);
+      }
+      *reinterpret_cast<float4*>(o + ((2 * zl) << log2P) + x) = make_float4(fa[0], fa[1], fa[2], fa[3]);
+      *reinterpret_cast<float4*>(o + ((2 * zl + 1) << log2P) + x) = make_float4(fb[0], fb[1], fb[2], fb[3]);
     }
     __syncthreads();
   }
