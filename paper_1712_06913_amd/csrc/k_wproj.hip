@@ -174,6 +174,16 @@ k_bin_w(const InstDesc* __restrict__ inst, const float2* __restrict__ uv, const 
 constexpr int WG_THREADS = 256;
 constexpr int WG_CHUNK = 8;      // tiles per workgroup
 constexpr int WG_EB = 256;       // samples staged at a time
+// LDS accumulator row stride: one cell of padding moves the rows that the lanes of one
+// sample add into (same column, consecutive rows) onto different banks.
+constexpr int WG_RS = TJ + 1;
+
+// Grid cells are written once and read only by the next kernel: nontemporal 16-byte stores.
+typedef double wt_double2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void put_wcell(double2* p, double x, double y) {
+  const wt_double2 v = {x, y};
+  __builtin_nontemporal_store(v, reinterpret_cast<wt_double2*>(p));
+}
 
 // Tiled w-projection gridder: WG_CHUNK consecutive tiles of the dirty half grids per
 // workgroup; (sample, tap row) items over the threads, FP64 LDS accumulation, one flush.
@@ -183,7 +193,7 @@ k_grid_wt(const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst, 
           const float* __restrict__ w_in, const float* __restrict__ wts, const int* __restrict__ ent,
           const int* __restrict__ tstart, const int* __restrict__ tcount, const WInst* __restrict__ winst,
           const WPlane* __restrict__ planes, const double2* __restrict__ tabs, double2* __restrict__ grid) {
-  __shared__ double2 acc[TK * TJ];
+  __shared__ double2 acc[TK * WG_RS];
   __shared__ int m_inst[WG_CHUNK], m_start[WG_CHUNK], m_cnt[WG_CHUNK];
   __shared__ int s_kp[WG_EB], s_j[WG_EB], s_pl[WG_EB];
   __shared__ double s_fu[WG_EB], s_fv[WG_EB], s_wr[WG_EB], s_wi[WG_EB];
@@ -208,11 +218,11 @@ k_grid_wt(const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst, 
     double2* out = grid + d.gd_off + (int64_t)k0 * N + j0;
     const int n = __builtin_amdgcn_readfirstlane(m_cnt[tt]);
     if (n == 0) {                                    // empty tile: plain zero fill
-      for (int q = tid; q < TK * TJ; q += WG_THREADS) out[(int64_t)(q / TJ) * N + (q % TJ)] = make_double2(0.0, 0.0);
+      for (int q = tid; q < TK * TJ; q += WG_THREADS) put_wcell(out + (int64_t)(q / TJ) * N + (q % TJ), 0.0, 0.0);
       continue;
     }
     const int Smax = planes[wi.plane0 + wi.n_planes - 1].S, Hmax = (Smax - 1) / 2;
-    for (int q = tid; q < TK * TJ; q += WG_THREADS) acc[q] = make_double2(0.0, 0.0);
+    for (int q = tid; q < TK * WG_RS; q += WG_THREADS) acc[q] = make_double2(0.0, 0.0);
     const int st = m_start[tt];
     for (int e0 = 0; e0 < n; e0 += WG_EB) {
       const int ne = min(WG_EB, n - e0);
@@ -266,7 +276,7 @@ k_grid_wt(const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst, 
           const double kr = (1 - ay) * ((1 - ax) * k00.x + ax * k01.x) + ay * ((1 - ax) * k10.x + ax * k11.x);
           double ki = (1 - ay) * ((1 - ax) * k00.y + ax * k01.y) + ay * ((1 - ax) * k10.y + ax * k11.y);
           if (cj) ki = -ki;
-          double* a = reinterpret_cast<double*>(&acc[(kp - k0) * TJ + (j - j0)]);
+          double* a = reinterpret_cast<double*>(&acc[(kp - k0) * WG_RS + (j - j0)]);
           atomicAdd(a, wr * kr - wim * ki);
           atomicAdd(a + 1, wr * ki + wim * kr);
         }
@@ -275,9 +285,9 @@ k_grid_wt(const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst, 
     __syncthreads();
     for (int q = tid; q < TK * TJ; q += WG_THREADS) {
       const int l = q / TJ, jj = q % TJ;
-      double2 val = acc[q];
+      double2 val = acc[l * WG_RS + jj];
       if (((k0 + l + 1) + (j0 + jj)) & 1) { val.x = -val.x; val.y = -val.y; }
-      out[(int64_t)l * N + jj] = val;
+      put_wcell(out + (int64_t)l * N + jj, val.x, val.y);
     }
     __syncthreads();
   }
