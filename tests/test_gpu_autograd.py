@@ -80,9 +80,10 @@ def test_predict_op_forward_backward_dot_product():
     p = ag.predict(y, b, uv, w)
     lhs = torch.sum(p.real.double() * u.real.double() + p.imag.double() * u.imag.double())
     lhs.backward()
-    rhs = torch.dot(y.detach().double(), y.grad.double())
-    log(f"  <Py,u>={float(lhs):.9e} <y,PTu>={float(rhs):.9e}")
-    assert abs(float(lhs) - float(rhs)) <= 1e-5 * abs(float(lhs))
+    lv = float(lhs.detach())
+    rv = float(torch.dot(y.detach().double(), y.grad.double()))
+    log(f"  <Py,u>={lv:.9e} <y,PTu>={rv:.9e}")
+    assert abs(lv - rv) <= 1e-5 * abs(lv)
     # forward against the oracle prediction for the first instance
     N = int(wl.n_img[0])
     vi, uvi, wi = wl.instance(0)
