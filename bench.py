@@ -155,7 +155,7 @@ def main():
         log(f"CPU oracle: {cpu['value']:.4f} images/s")
 
     import torch
-    from paper_1712_06913_amd import api
+    from paper_1712_06913_amd import _native as nat, api
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -200,12 +200,16 @@ def main():
 
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     torch.cuda.synchronize()
-    api.profile_begin(dev.index or 0)              # HIP events around each Hogbom kernel launch
+    # HIP events around each Hogbom, gridder and inverse-transform launch
+    api.profile_begin(dev.index or 0, kinds=nat.MI_PROF_CLEAN | nat.MI_PROF_GRID | nat.MI_PROF_IFFT)
     t0 = time.perf_counter()
     for k in range(args.steps):
         res = step(evs[k])
     torch.cuda.synchronize()
-    kernel_times = api.profile_end(dev.index or 0)
+    prof_ms, prof_kind = api.profile_end_kinds(dev.index or 0)
+    kernel_times = [t for t, k in zip(prof_ms, prof_kind) if k == nat.MI_PROF_CLEAN]
+    grid_k_ms = sum(t for t, k in zip(prof_ms, prof_kind) if k == nat.MI_PROF_GRID) / args.steps
+    ifft_k_ms = sum(t for t, k in zip(prof_ms, prof_kind) if k == nat.MI_PROF_IFFT) / args.steps
     log(f"{args.steps} timed steps done")
     wall = time.perf_counter() - t0
     ms_step = wall * 1e3 / args.steps
@@ -292,6 +296,30 @@ def main():
             "traffic_unit": "HBM-side bytes per launch (L2 read and write requests by size)",
             "traffic_over_algorithmic": (traffic / clean_bytes) if traffic else None}
 
+    # gridding and inverse transforms of the step, timed by the same events: algorithmic
+    # bytes of this design per step (FP64 complex dirty half grid N/2 x N, FP64 real beam
+    # half grid N x 2N, float32 maps; the gridders also read 24 B (dirty) and 16 B (beam)
+    # per visibility; the transform's two passes move each half grid in and out of HBM)
+    Nf = b.n_img.astype(np.float64)
+    hd = float(np.sum(Nf / 2 * Nf * 16.0))
+    hbr = float(np.sum(Nf * 2 * Nf * 8.0))
+    im, bm = float(np.sum(4.0 * Nf ** 2)), float(np.sum(16.0 * Nf ** 2))
+    M = float(wl.vis_offset[-1])
+    grid_alg = hd + 24.0 * M + hbr + 16.0 * M
+    fft_alg = 2 * hd + (hd + im) + 2 * hbr + (hbr + bm)
+    fft_min = (hd + im) + (hbr + bm)
+    def _roof(alg, ms):
+        a = alg / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "ms": ms, "algorithmic_bytes": alg, "achieved": a, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": a / HBM_PEAK_GBS}
+    imaging_roof = {
+        "gridding": dict(_roof(grid_alg, grid_k_ms), kernels="k_grid: dirty FP64 complex + beam FP64 real half grids"),
+        "inverse_transform": dict(_roof(fft_alg, ifft_k_ms),
+                                  kernels="k_fft_a, k_fft_b_c2r (dirty), k_fft_a_real, k_fft_b_c2r_sym (beam)",
+                                  information_minimal_bytes=fft_min,
+                                  frac_information_minimal=fft_min / (ifft_k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS),
+    }
+
     out = {
         "metric": "images/s (grid+iFFT+Hogbom CLEAN, 1024^2, batched)",
         "value": n_inst / (ms_step * 1e-3),
@@ -312,6 +340,7 @@ def main():
         "instance_status_nonzero": int(np.count_nonzero(status)),
         "w_projection": wproj,
         "roofline": roof,
+        "imaging_roofline": imaging_roof,
     }
 
     if not args.no_plain:

@@ -254,6 +254,23 @@ mi_status mi_phase_shift(mi_ctx* ctx, const mi_batch* batch, mi_c64* vis, const 
 mi_status mi_profile_begin(mi_ctx* ctx);
 mi_status mi_profile_end(mi_ctx* ctx, float* ms_out, int32_t cap, int32_t* n_out);
 
+/* Kernel kinds for mi_profile_begin_kinds (bit mask). */
+enum {
+  MI_PROF_CLEAN = 1,  /* the Hogbom kernel of mi_hogbom_clean (what mi_profile_begin records)  */
+  MI_PROF_GRID = 2,   /* each FP64 tiled gridder launch: the dirty half grid (mi_dirty_image,
+                         mi_grid with MI_LAYOUT_HALF) and the real beam half grid
+                         (mi_dirty_image with beams, mi_dirty_beam)                           */
+  MI_PROF_IFFT = 4    /* each inverse transform pass: two per dirty-image batch (mi_dirty_image,
+                         mi_dirty_image_w), two per beam batch                                */
+};
+
+/* mi_profile_begin_kinds: as mi_profile_begin, for every launch of the kernel kinds in the
+ *   bit mask `kinds` (MI_PROF_*).  MI_ERR_ARG for an empty mask or unknown bits.
+ * mi_profile_end_kinds: as mi_profile_end; also writes each record's kind (one MI_PROF_*
+ *   bit) to the host array kind_out (up to `cap` entries; kind_out may be NULL).          */
+mi_status mi_profile_begin_kinds(mi_ctx* ctx, uint32_t kinds);
+mi_status mi_profile_end_kinds(mi_ctx* ctx, float* ms_out, int32_t* kind_out, int32_t cap, int32_t* n_out);
+
 #ifdef __cplusplus
 }
 #endif

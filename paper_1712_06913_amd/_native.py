@@ -12,11 +12,12 @@ MI_OK, MI_ERR_ARG, MI_ERR_SHAPE, MI_ERR_UNSUPPORTED, MI_ERR_NOMEM, MI_ERR_DEVICE
 MI_INST_EMPTY, MI_INST_LOBE_CLIPPED, MI_INST_RESTORE_CLIPPED, MI_INST_TEST_FAILED = 1, 2, 4, 8
 MI_NATURAL, MI_UNIFORM = 0, 1
 MI_LAYOUT_FULL, MI_LAYOUT_HALF = 0, 1
+MI_PROF_CLEAN, MI_PROF_GRID, MI_PROF_IFFT = 1, 2, 4
 
 # every entry point declared in include/mi.h
 EXPORTS = ("mi_ctx_create", "mi_ctx_destroy", "mi_last_error", "mi_version", "mi_grid", "mi_ifft2",
            "mi_dirty_image", "mi_dirty_beam", "mi_hogbom_clean", "mi_degrid", "mi_gmm_levels", "mi_disk_offsets", "mi_phase_shift", "mi_profile_begin",
-           "mi_profile_end", "mi_dirty_image_w")
+           "mi_profile_end", "mi_dirty_image_w", "mi_profile_begin_kinds", "mi_profile_end_kinds")
 
 
 class MiBatch(ctypes.Structure):
@@ -65,6 +66,8 @@ def lib():
                                   vp, vp]
     L.mi_dirty_image_w.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, vp, POINTER(MiWprojParams), vp, vp, vp, vp]
     L.mi_degrid.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, c_int, vp, vp]
+    L.mi_profile_begin_kinds.argtypes = [vp, ctypes.c_uint32]
+    L.mi_profile_end_kinds.argtypes = [vp, vp, vp, c_int32, vp]
     for name in EXPORTS:
         if name not in ("mi_last_error", "mi_version"):
             getattr(L, name).restype = c_int

@@ -234,16 +234,25 @@ def phase_shift(batch: Batch, vis, uv, offsets):
     return vis
 
 
-def profile_begin(device: int = 0):
-    """mi_profile_begin: record HIP events around every following Hogbom kernel launch."""
+def profile_begin(device: int = 0, kinds: int = nat.MI_PROF_CLEAN):
+    """mi_profile_begin_kinds: record HIP events around every following launch of the kernel
+    kinds in the mask (MI_PROF_CLEAN: the Hogbom kernel; MI_PROF_GRID: the FP64 gridders;
+    MI_PROF_IFFT: the inverse transform passes)."""
     ctx = context(device)
-    nat.check(ctx, nat.lib().mi_profile_begin(ctx))
+    nat.check(ctx, nat.lib().mi_profile_begin_kinds(ctx, kinds))
+
+
+def profile_end_kinds(device: int = 0, cap: int = 4096):
+    """mi_profile_end_kinds: (durations in milliseconds, kinds), oldest first."""
+    ctx = context(device)
+    buf = (ctypes.c_float * cap)()
+    kb = (ctypes.c_int32 * cap)()
+    n = ctypes.c_int32()
+    nat.check(ctx, nat.lib().mi_profile_end_kinds(ctx, buf, kb, cap, ctypes.byref(n)))
+    m = min(n.value, cap)
+    return [float(buf[i]) for i in range(m)], [int(kb[i]) for i in range(m)]
 
 
 def profile_end(device: int = 0, cap: int = 1024):
-    """mi_profile_end: the recorded Hogbom kernel durations in milliseconds (oldest first)."""
-    ctx = context(device)
-    buf = (ctypes.c_float * cap)()
-    n = ctypes.c_int32()
-    nat.check(ctx, nat.lib().mi_profile_end(ctx, buf, cap, ctypes.byref(n)))
-    return [float(buf[i]) for i in range(min(n.value, cap))]
+    """mi_profile_end: the recorded kernel durations in milliseconds (oldest first)."""
+    return profile_end_kinds(device, cap)[0]

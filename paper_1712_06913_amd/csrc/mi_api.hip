@@ -213,10 +213,11 @@ struct mi_ctx {
   mi::DevBuf ifft_scratch;
   int fail_inst = -1;
   int n_cu = 256;
-  // kernel timing: event pairs around Hogbom launches while profiling is on
-  bool profiling = false;
+  // kernel timing: event pairs around launches of the kinds in prof_kinds (MI_PROF_*)
+  uint32_t prof_kinds = 0;
   size_t prof_used = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
+  std::vector<uint32_t> prof_kind;
   ~mi_ctx() {
     for (auto& e : prof_ev) {
       (void)hipEventDestroy(e.first);
@@ -229,6 +230,27 @@ namespace mi {
 namespace {
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Kernel timing: when `kind` is being recorded, record the start event of a fresh pair on
+// the stream and return the pair's end event (to be recorded after the launch); else null.
+hipEvent_t prof_start(mi_ctx* ctx, uint32_t kind, hipStream_t st) {
+  if (!(ctx->prof_kinds & kind)) return nullptr;
+  if (ctx->prof_used == ctx->prof_ev.size()) {
+    std::pair<hipEvent_t, hipEvent_t> e{};
+    HIPCHK(hipEventCreate(&e.first));
+    HIPCHK(hipEventCreate(&e.second));
+    ctx->prof_ev.push_back(e);
+    ctx->prof_kind.push_back(0u);
+  }
+  const size_t i = ctx->prof_used++;
+  ctx->prof_kind[i] = kind;
+  HIPCHK(hipEventRecord(ctx->prof_ev[i].first, st));
+  return ctx->prof_ev[i].second;
+}
+
+void prof_stop(hipEvent_t e, hipStream_t st) {
+  if (e) HIPCHK(hipEventRecord(e, st));
+}
 int ilog2i(int v) { int r = 0; while ((1 << r) < v) ++r; return r; }
 
 void check_batch(const mi_batch* b) {
@@ -372,10 +394,12 @@ void run_grid(mi_ctx* ctx, Plan* P, const mi_c64* vis, const float* uv, const fl
   const int* tc = static_cast<const int*>(beam ? P->tc_b.p : P->tc_d.p);
   const float2* v = beam ? nullptr : reinterpret_cast<const float2*>(vis);
   const float* wts = static_cast<const float*>(P->wts.p);
-  if constexpr (std::is_same<OutT, double2>::value)
+  if constexpr (std::is_same<OutT, double2>::value) {
+    hipEvent_t pe = prof_start(ctx, MI_PROF_GRID, st);
     HIPCHK(launch_grid(inst, tmap, nt, beam ? 1 : 0, v, reinterpret_cast<const float2*>(uv), w_in, wts, ent, ts, tc,
                        ctx->T, out, modulate, st));
-  else
+    prof_stop(pe, st);
+  } else
     HIPCHK(launch_grid_f32(inst, tmap, nt, beam ? 1 : 0, v, reinterpret_cast<const float2*>(uv), w_in, wts, ent, ts,
                            tc, ctx->T, out, modulate, st));
 }
@@ -385,22 +409,32 @@ void run_image(mi_ctx* ctx, Plan* P, float* out, hipStream_t st) {
   const InstDesc* inst = static_cast<const InstDesc*>(P->inst.p);
   double2* g = static_cast<double2*>(P->gd.p);
   const double* b0 = static_cast<const double*>(P->b0.p);
+  hipEvent_t pe = prof_start(ctx, MI_PROF_IFFT, st);
   HIPCHK(launch_fft_a(P->elems_d, ctx->n_cu, inst, static_cast<const FftWork*>(P->wa_d.p), P->n_wa_d, g, ctx->T, st));
+  prof_stop(pe, st);
+  pe = prof_start(ctx, MI_PROF_IFFT, st);
   HIPCHK(launch_fft_b_c2r(P->elems_d, ctx->n_cu, inst, static_cast<const FftWork*>(P->wb_d.p), P->n_wb_d, g, b0, ctx->T, out,
                           st));
+  prof_stop(pe, st);
 }
 
 // Beams: real FP64 beam grid (gridder), then the two symmetric transform passes.
 void run_beam(mi_ctx* ctx, Plan* P, const float* uv, const float* w_in, float* out, hipStream_t st) {
   const InstDesc* inst = static_cast<const InstDesc*>(P->inst.p);
   double* g = dev_alloc<double>(P->gbr, P->total_gb);
+  hipEvent_t pe = prof_start(ctx, MI_PROF_GRID, st);
   HIPCHK(launch_grid_real(inst, static_cast<const int*>(P->tile_inst_b.p), P->tiles_b,
                           reinterpret_cast<const float2*>(uv), w_in, static_cast<const float*>(P->wts.p),
                           static_cast<const int*>(P->ent_b.p), static_cast<const int*>(P->ts_b.p),
                           static_cast<const int*>(P->tc_b.p), ctx->T, g, st));
+  prof_stop(pe, st);
+  pe = prof_start(ctx, MI_PROF_IFFT, st);
   HIPCHK(launch_fft_a_real(P->elems_b, ctx->n_cu, inst, static_cast<const FftWork*>(P->wa_b.p), P->n_wa_b, g, ctx->T, st));
+  prof_stop(pe, st);
+  pe = prof_start(ctx, MI_PROF_IFFT, st);
   HIPCHK(launch_fft_b_c2r_sym(P->elems_b, ctx->n_cu, inst, static_cast<const FftWork*>(P->wb_b.p), P->n_wb_b, g,
                               static_cast<const double*>(P->b0.p), ctx->T, out, st));
+  prof_stop(pe, st);
 }
 
 // CLEAN schedule for one batch.  Every image size N gets its own team size G(N), the
@@ -717,14 +751,18 @@ mi_status mi_phase_shift(mi_ctx* ctx, const mi_batch* batch, mi_c64* vis, const 
   });
 }
 
-mi_status mi_profile_begin(mi_ctx* ctx) {
+mi_status mi_profile_begin_kinds(mi_ctx* ctx, uint32_t kinds) {
   return guard(ctx, [&] {
-    ctx->profiling = true;
+    const uint32_t all = MI_PROF_CLEAN | MI_PROF_GRID | MI_PROF_IFFT;
+    if (kinds == 0u || (kinds & ~all)) fail(MI_ERR_ARG, "kinds must be a non-empty mask of MI_PROF_* bits (got %u)", kinds);
+    ctx->prof_kinds = kinds;
     ctx->prof_used = 0;
   });
 }
 
-mi_status mi_profile_end(mi_ctx* ctx, float* ms_out, int32_t cap, int32_t* n_out) {
+mi_status mi_profile_begin(mi_ctx* ctx) { return mi_profile_begin_kinds(ctx, MI_PROF_CLEAN); }
+
+mi_status mi_profile_end_kinds(mi_ctx* ctx, float* ms_out, int32_t* kind_out, int32_t cap, int32_t* n_out) {
   return guard(ctx, [&] {
     need(n_out, "n_out");
     if (cap > 0) need(ms_out, "ms_out");
@@ -735,11 +773,16 @@ mi_status mi_profile_end(mi_ctx* ctx, float* ms_out, int32_t cap, int32_t* n_out
       float ms = 0.0f;
       HIPCHK(hipEventElapsedTime(&ms, ctx->prof_ev[i].first, ctx->prof_ev[i].second));
       ms_out[i] = ms;
+      if (kind_out) kind_out[i] = (int32_t)ctx->prof_kind[i];
     }
     *n_out = (int32_t)n;
-    ctx->profiling = false;
+    ctx->prof_kinds = 0;
     ctx->prof_used = 0;
   });
+}
+
+mi_status mi_profile_end(mi_ctx* ctx, float* ms_out, int32_t cap, int32_t* n_out) {
+  return mi_profile_end_kinds(ctx, ms_out, nullptr, cap, n_out);
 }
 
 mi_status mi_grid(mi_ctx* ctx, const mi_batch* batch, const mi_c64* vis, const float* uv, const float* w_in,
@@ -1092,21 +1135,9 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
     A.slots = static_cast<unsigned long long*>(C->slots.p);
     A.asym = asym;
     A.status = status;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (ctx->profiling) {
-      if (ctx->prof_used == ctx->prof_ev.size()) {
-        std::pair<hipEvent_t, hipEvent_t> e{};
-        HIPCHK(hipEventCreate(&e.first));
-        HIPCHK(hipEventCreate(&e.second));
-        ctx->prof_ev.push_back(e);
-      }
-      e0 = ctx->prof_ev[ctx->prof_used].first;
-      e1 = ctx->prof_ev[ctx->prof_used].second;
-      ++ctx->prof_used;
-      HIPCHK(hipEventRecord(e0, stream));
-    }
+    hipEvent_t pe = prof_start(ctx, MI_PROF_CLEAN, stream);
     HIPCHK(launch_clean(A, C->ppt, C->local != 0, C->n_blocks, C->lds, stream));
-    if (e1) HIPCHK(hipEventRecord(e1, stream));
+    prof_stop(pe, stream);
   });
 }
 

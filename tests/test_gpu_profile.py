@@ -1,0 +1,55 @@
+"""Kernel timing hook (mi_profile_begin_kinds / mi_profile_end_kinds): which launches it
+records, in which order, and what it rejects.  Measurement plumbing, not imaging arithmetic:
+the durations are only checked to be positive."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1712_06913_amd import synth
+from tests.gpu_helpers import log, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def test_profile_records_the_selected_kinds_in_launch_order():
+    log("[profile] gridder, transform and Hogbom launches of one batch, by kind")
+    require_gpu()
+    from paper_1712_06913_amd import _native as nat, api
+    wl = synth.c3_muser2(n_chan=3, N=256, niter=50)
+    b = api.Batch.from_workload(wl)
+    vis, uv, w = api.workload_tensors(wl)
+    dirty, beam, _ = api.dirty_image(b, vis, uv, w, beam=True)        # plans built outside the records
+    api.hogbom_clean(b, dirty, beam, wl.niter.astype(np.int32), restore=False)
+    torch.cuda.synchronize()
+    G, F, C = nat.MI_PROF_GRID, nat.MI_PROF_IFFT, nat.MI_PROF_CLEAN
+
+    api.profile_begin(0, kinds=G | F | C)
+    dirty, beam, _ = api.dirty_image(b, vis, uv, w, beam=True)
+    api.hogbom_clean(b, dirty, beam, wl.niter.astype(np.int32), restore=False)
+    ms, kinds = api.profile_end_kinds(0)
+    log(f"  kinds {kinds}, ms {[round(t, 3) for t in ms]}")
+    # dirty: grid, pass A, pass B; beam: grid, pass A, pass B; then the Hogbom kernel
+    assert kinds == [G, F, F, G, F, F, C]
+    assert all(t > 0.0 for t in ms)
+
+    api.profile_begin(0, kinds=F)                  # one kind only
+    api.dirty_image(b, vis, uv, w, beam=False, out=dirty)
+    ms, kinds = api.profile_end_kinds(0)
+    assert kinds == [F, F]
+
+    api.profile_begin(0)                           # the default records the Hogbom kernel only
+    api.dirty_image(b, vis, uv, w, beam=True, out=dirty, beam_out=beam)
+    api.hogbom_clean(b, dirty, beam, wl.niter.astype(np.int32), restore=False)
+    assert len(api.profile_end(0)) == 1
+
+    ms, kinds = api.profile_end_kinds(0)           # nothing recorded after the end
+    assert ms == [] and kinds == []
+
+
+def test_profile_rejects_bad_masks():
+    log("[profile] empty and unknown kind masks are rejected")
+    require_gpu()
+    from paper_1712_06913_amd import _native as nat, api
+    for bad in (0, 8, 1 | 16):
+        with pytest.raises(nat.MiError):
+            api.profile_begin(0, kinds=bad)
