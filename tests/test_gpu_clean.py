@@ -93,6 +93,17 @@ def test_clean_small_batch_mixed_sizes():
     _check(wl, np.array([50, 120, 200, 0], np.int32))
 
 
+def test_clean_all_zero_map_yields_no_components():
+    log("[clean] an all-zero dirty map next to a normal one: no components, zero maps exactly")
+    wl = synth.random_instances(24, [128, 128], m_range=(150, 250))
+    dirty, beams = _inputs(wl)
+    dirty[1] = np.zeros_like(dirty[1])
+    # the zero map's tolerances are all 0 (peak 0): residual, model and restored must be exact zeros
+    _check(wl, np.array([60, 60], np.int32), inputs=(dirty, beams))
+    _, _, _, res = _run(wl, np.array([60, 60], np.int32), inputs=(dirty, beams))
+    assert int(res["n_comp"][1].item()) == 0
+
+
 def test_clean_threshold_stops_early_and_positive_only():
     log("[clean] threshold / positive-only")
     wl = synth.random_instances(22, [64, 128], m_range=(150, 250))
