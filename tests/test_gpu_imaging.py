@@ -92,6 +92,21 @@ def test_empty_and_flagged_instances():
     _image_parity(wl)
 
 
+def test_kept_band_edges_and_nonfinite_uv():
+    log("[imaging] samples at the edge of the kept band, near half-cell ties, NaN / inf / huge uv")
+    wl = synth.random_instances(5, [128, 256], m_range=(200, 200))
+    for i in range(wl.n_inst):
+        a = int(wl.vis_offset[i])
+        N, sc = int(wl.n_img[i]), int(wl.n_img[i]) * float(wl.cell_rad[i])
+        lim = N // 2 - 4                   # largest kept |cell| (support 7 inside the half grid)
+        g = [lim, lim + 0.49, lim + 0.5, -(lim + 0.5), lim - 0.5, -lim - 0.4999, lim + 1, -lim]
+        pts = [(x, 3.2) for x in g] + [(2.7, y) for y in g]
+        pts += [(np.nan, 1.0), (1.0, np.inf), (-np.inf, 0.0), (1e30, 2.0)]
+        for k, (x, y) in enumerate(pts):
+            wl.uv[a + k] = (np.float32(x / sc), np.float32(y / sc))
+    _image_parity(wl)
+
+
 @pytest.mark.parametrize("which", [0, 1])
 def test_grid_full_layout_matches_oracle(which):
     log(f"[grid] full layout which={which}")
