@@ -42,6 +42,39 @@ def test_degrid_matches_oracle(adj):
         assert err <= 1e-5 * scale * np.log2(N)
 
 
+@pytest.mark.parametrize("adj", [False, True])
+def test_degrid_dropped_samples_are_exact_zeros(adj):
+    log(f"[degrid] kept-band edge and non-finite uv, adjoint={adj}")
+    api = _api()
+    wl = synth.random_instances(32, [64, 128], m_range=(60, 60))
+    for i in range(wl.n_inst):
+        a = int(wl.vis_offset[i])
+        N, sc = int(wl.n_img[i]), int(wl.n_img[i]) * float(wl.cell_rad[i])
+        lim = N // 2 - 4
+        pts = [(lim, 1.2), (lim + 1, 0.3), (np.nan, 1.0), (1.0, np.inf), (1e30, 2.0), (-(lim + 0.5), 2.0)]
+        for k, (x, y) in enumerate(pts):
+            wl.uv[a + k] = (np.float32(x / sc), np.float32(y / sc))
+    b = api.Batch.from_workload(wl)
+    vis, uv, w = api.workload_tensors(wl)
+    rng = np.random.default_rng(3)
+    imgs = [rng.standard_normal((int(N), int(N))).astype(np.float32) for N in wl.n_img]
+    y = torch.from_numpy(np.concatenate([x.ravel() for x in imgs])).cuda()
+    out = api.degrid(b, y, uv, w, adjoint=adj)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    for i in range(wl.n_inst):
+        v, uvi, wi = wl.instance(i)
+        N, cell, mode = int(wl.n_img[i]), float(wl.cell_rad[i]), int(wl.weight_mode[i])
+        yi = imgs[i].astype(np.float64)
+        ref = adjoint.adjoint(yi, uvi, wi, N, cell, mode) if adj else adjoint.predict(yi, uvi, wi, N, cell)
+        got = out[wl.vis_offset[i]: wl.vis_offset[i + 1]]
+        keep = imager.Prep(uvi, wi, N, cell).keep
+        assert np.all(got[~keep] == 0)
+        assert np.all(np.isfinite(got))
+        scale = np.max(np.abs(ref))
+        assert np.max(np.abs(got - ref)) <= 1e-5 * scale * np.log2(N)
+
+
 def test_dot_product_identity_on_gpu():
     log("[degrid] dot-product test C5-like slice")
     api = _api()
