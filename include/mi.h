@@ -165,7 +165,8 @@ typedef struct {
  * wavelengths.  With r2 = l^2 + m^2 at the field corner and dw = phase_tol / (pi r2),
  * instance i uses the planes w_j = j dw, j = 0 .. floor(w_max[i] / dw + 1/2) (one plane,
  * i.e. no correction, when pi w_max r2 <= phase_tol / 2); each visibility is gridded with
- * the kernel of the plane nearest to |w| (conjugated for w < 0): the field's transform of
+ * the kernel of the plane nearest to |w| (halves rounded up; the last plane for |w| beyond
+ * it, or not finite), conjugated for w < 0: the field's transform of
  * corr(l) corr(m) exp(+2 pi i w_j (sqrt(1 - l^2 - m^2) - 1)), tabulated at 16 points per
  * cell over a support of 2 (3 + ceil(w_j sqrt(r2) N dl)) + 1 cells and interpolated
  * bilinearly.  Weighting, transform, correction and B0 are those of mi_dirty_image.

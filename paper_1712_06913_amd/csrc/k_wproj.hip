@@ -121,9 +121,12 @@ __device__ void wave0_exclusive_scan(int* a, int n) {
   }
 }
 
-// Plane of a visibility: nearest to |w|, at most the instance's last.
+// Plane of a visibility: nearest to |w| (halves away from zero, the cell rounding), at most
+// the instance's last; a non-finite w compares false and takes the last plane too, so no
+// NaN or infinity reaches the integer conversion.
 __device__ __forceinline__ int plane_of(const WInst& wi, double w) {
-  return min((int)floor(fabs(w) / wi.dw + 0.5), wi.n_planes - 1);
+  const double p = rhaz(fabs(w) / wi.dw);
+  return p < (double)(wi.n_planes - 1) ? (int)p : wi.n_planes - 1;
 }
 
 // Tile lists of the dirty half grid for w-projection: one workgroup per instance, counting
