@@ -139,7 +139,7 @@ def cpu_baseline(wl, restore_sample=300):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: the imaging instances are independent and this build runs on "
+        print(f"bench.py measures one GPU only: the imaging instances are independent and the library runs on "
               f"a single MI355X (requested --gpus {args.gpus}).", file=sys.stderr)
         sys.exit(2)
     log(f"generating workload {args.workload}")
