@@ -11,9 +11,10 @@
 //   k_bin   one workgroup per instance: keep/cell decisions, uniform counts (sparse
 //           scratch grid, touched cells only), per-visibility weights, B0 sums, and a
 //           counting sort of (sample, tile) entries for the dirty and the beam half grids.
-//   k_grid  grid-stride over tiles of TK lines x TJ cells of a half grid: accumulate the
-//           tile's samples into LDS (no global atomics), then one coalesced flush that
-//           writes every cell of the tile (zeros included), so no separate memset pass.
+//   k_grid  GRID_CHUNK consecutive tiles of TK lines x TJ cells of a half grid per
+//           workgroup: accumulate each tile's samples into LDS (no global atomics), then one
+//           coalesced flush of nontemporal 16-byte stores that writes every cell of the
+//           tile (zeros included), so no separate memset pass.
 #include <type_traits>
 
 #include "mi_internal.h"
@@ -24,11 +25,11 @@ namespace {
 
 constexpr int BIN_THREADS = 1024;
 
-__device__ __forceinline__ int warp_sum_i(int v) {
+__device__ __forceinline__ int wave_sum_i(int v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
 }
-__device__ __forceinline__ double warp_sum_d(double v) {
+__device__ __forceinline__ double wave_sum_d(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
 }
@@ -159,9 +160,9 @@ k_bin(const InstDesc* __restrict__ inst, const float2* __restrict__ uv, const fl
     }
     wts[d.vis_off + k] = w;
   }
-  sd = warp_sum_d(sd);
-  sb = warp_sum_d(sb);
-  nk = warp_sum_i(nk);
+  sd = wave_sum_d(sd);
+  sb = wave_sum_d(sb);
+  nk = wave_sum_i(nk);
   if ((tid & 63) == 0) {
     red_d[0][tid >> 6] = sd;
     red_d[1][tid >> 6] = sb;
