@@ -14,6 +14,9 @@ Parity status per function (see each module header for the pins):
   gmm.histogram / gmm.em_fit / gmm.levels        pinned (exact binning, closed-form moments, monotone EM, known mixture)
   centering.correlate / peak_offset / disk_offset / phase_correct
                                                  pinned (direct-sum correlation, whole-pixel shifts, point-source phase)
+  steer.steer / steer.replay / steer.convolve_window
+                                                 pinned (trim 1 = Hogbom, point-source and flat-source closed
+                                                 forms, two-tap alpha, CLEAN identity, direct-sum convolution)
   wproj.exact_dirty / plan / kernel_table / dirty_image_w
                                                  pinned (2-D DFT at w = 0, spheroidal product at w = 0, symmetries,
                                                  phase rule, exact w-term image of a point source)
