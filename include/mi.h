@@ -15,6 +15,15 @@
  *  - Every call is asynchronous on the given HIP stream (0 = the null stream).  The
  *    first call with a new batch descriptor builds a plan (workspace, device tables) and
  *    may synchronise once; later calls with an identical descriptor do not synchronise.
+ *    The same holds for a new set of CLEAN parameters (mi_hogbom_clean), new w_max /
+ *    phase_tol (mi_dirty_image_w) and new radii (mi_disk_offsets): each of those calls
+ *    uploads its tables synchronously once; repeats with the same values do not.  No
+ *    other call synchronises.
+ *  - Graph capture: a call whose plan already exists (run it once outside the capture)
+ *    can be captured into a HIP graph; its plan is then kept for the context's lifetime.
+ *    A call that would build a new plan while its stream is capturing returns
+ *    MI_ERR_UNSUPPORTED.  Other plans are evicted least recently used first (at most 16
+ *    batch descriptors, 8 CLEAN parameter sets per descriptor, 16 transform layouts).
  *  - Argument errors are detected on the host before any launch; the call then returns
  *    a nonzero mi_status, writes nothing, and mi_last_error() describes the problem.
  *  - Per-instance problems (no kept visibilities, ...) do not abort the batch: they are
@@ -181,6 +190,9 @@ mi_status mi_dirty_image_w(mi_ctx* ctx, const mi_batch* batch, const mi_c64* vis
 
 /* Hogbom CLEAN with restore (Algorithm 1, improved_clean; Sec. 4.3).
  *   dirty: float32 N*N per instance; beam: float32 (2N)^2 per instance (peak at (N, N)).
+ *   N: every image size of the batch, 64 ... 4096 (each member of a team keeps 64K
+ *   residual pixels in registers, so 4096^2 takes all 256 compute units for one image;
+ *   MI_ERR_UNSUPPORTED if the teams cannot be resident together).
  *   Per iteration: p = argmax |R| over the window (ties: lowest y*N + x), stop if
  *   |R[p]| <= threshold,
  *   f = gain * R[p] (double), model[p] += f, R -= f * beam[y - p_y + N][x - p_x + N].
@@ -211,6 +223,15 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
 mi_status mi_degrid(mi_ctx* ctx, const mi_batch* batch, const float* image, const float* uv,
                     const float* w_in, int adjoint, mi_c64* vis_out, hipStream_t stream);
 
+/* Transpose of the prediction (mi_degrid with adjoint = 0): with unit weights on the kept
+ * visibilities (w_in > 0 and on the grid; the weighting mode is ignored),
+ *   (P^T v)[x][y] = Re sum_k v_k S_k(x, y) / (corr(x) corr(y)) = Re I_raw / (2 corr corr),
+ * i.e. the dirty image of v with unit weights scaled by B0 / 2 instead of 1 / B0.  Under the
+ * real inner products <a,b> = sum a b and Re sum conj(v) u, <P y, v> = <y, P^T v>.
+ *   vis: complex, one per input visibility; image_out: float32 N*N per instance.   */
+mi_status mi_predict_transpose(mi_ctx* ctx, const mi_batch* batch, const mi_c64* vis, const float* uv,
+                               const float* w_in, float* image_out, hipStream_t stream);
+
 /* Sky and disk levels of maps (Sec. 4.1): the finite pixel values of each N*N map are put
  * into n_bins equal ranges between their minimum and maximum (bin = floor((x - lo) /
  * (hi - lo) * n_bins), last bin closed) and a two-component Gaussian mixture is fitted
@@ -233,7 +254,8 @@ mi_status mi_gmm_levels(mi_ctx* ctx, const mi_batch* batch, const float* images,
  * radius_px[i] pixels centred on pixel (N/2, N/2) (FP64 DFTs); the largest correlation
  * value (ties: lowest linear index) is refined per axis by a parabola through it and its
  * neighbours.  radius_px: host, n_inst, > 0.  offsets_out (device): double [n_inst][2] =
- * (dl, dm) in radians (+x, +y = increasing pixel index).                          */
+ * (dl, dm) in radians (+x, +y = increasing pixel index).  The disk models' transforms
+ * are kept between calls; a call with new radii uploads them and synchronises once.  */
 mi_status mi_disk_offsets(mi_ctx* ctx, const mi_batch* batch, const float* images, const double* radius_px,
                           double* offsets_out, hipStream_t stream);
 

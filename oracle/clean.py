@@ -87,7 +87,8 @@ def replay(dirty, beam, comp_idx, comp_flux, gain=0.1, threshold=0.0, eps=None, 
 
     Re-runs the loop in FP64 following the given picks: pick i is accepted iff its peak
     value (|R_i[p_i]|, or R_i[p_i] with positive_only) is within eps of the peak value over
-    the window (the whole map by default), p_i lies in the window, and
+    the window (the whole map by default), p_i lies in the window, that peak value is above
+    threshold - eps (the loop runs only while the peak exceeds the threshold), and
     |flux_i - gain R_i[p_i]| <= gain eps.  Returns (ok, first_bad_index,
     residual, model).  eps defaults to 1e-5 max|dirty|.
     """
@@ -107,7 +108,7 @@ def replay(dirty, beam, comp_idx, comp_flux, gain=0.1, threshold=0.0, eps=None, 
         else:
             m, val = float(np.max(np.abs(sub))), abs(R[py, px])
         inside = x0 <= px < x1 and y0 <= py < y1
-        if not inside or val < m - eps or abs(fl - gain * R[py, px]) > gain * eps:
+        if not inside or val < m - eps or m <= threshold - eps or abs(fl - gain * R[py, px]) > gain * eps:
             return False, i, R, model
         f = gain * R[py, px]
         model[py, px] += f
@@ -204,6 +205,21 @@ def restore(residual, model, abc):
         dy = yy - py
         out += model[py, px] * np.exp(-(a * dx * dx + b * dx * dy + c * dy * dy))
     return out
+
+
+def restore_conv(residual, model, abc, radius=None):
+    """The same restore as `restore`, by one FFT convolution of the model with the Gaussian
+    sampled at every offset |dx|, |dy| <= radius (default N - 1: every offset between two
+    pixels of the map, i.e. the full extent).  scipy's FFT convolution is a library primitive."""
+    from scipy.signal import fftconvolve
+    a, b, c = abc[:3]
+    N = residual.shape[0]
+    r = N - 1 if radius is None else min(int(radius), N - 1)
+    d = np.arange(-r, r + 1, dtype=np.float64)
+    dy, dx = np.meshgrid(d, d, indexing="ij")
+    G = np.exp(-(a * dx * dx + b * dx * dy + c * dy * dy))
+    full = fftconvolve(np.asarray(model, np.float64), G, mode="full")
+    return np.asarray(residual, np.float64) + full[r:r + N, r:r + N]
 
 
 def clean_identity(dirty, beam, residual, model):

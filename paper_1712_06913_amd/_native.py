@@ -9,7 +9,7 @@ from ctypes import POINTER, c_char_p, c_double, c_float, c_int, c_int32, c_void_
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmi.so")
 
 MI_OK, MI_ERR_ARG, MI_ERR_SHAPE, MI_ERR_UNSUPPORTED, MI_ERR_NOMEM, MI_ERR_DEVICE, MI_ERR_INSTANCE = range(7)
-MI_INST_EMPTY, MI_INST_LOBE_CLIPPED, MI_INST_RESTORE_CLIPPED, MI_INST_TEST_FAILED = 1, 2, 4, 8
+MI_INST_EMPTY, MI_INST_LOBE_CLIPPED, MI_INST_RESTORE_CLIPPED, MI_INST_TEST_FAILED, MI_INST_ABORTED = 1, 2, 4, 8, 16
 MI_NATURAL, MI_UNIFORM = 0, 1
 MI_LAYOUT_FULL, MI_LAYOUT_HALF = 0, 1
 MI_PROF_CLEAN, MI_PROF_GRID, MI_PROF_IFFT = 1, 2, 4
@@ -17,7 +17,8 @@ MI_PROF_CLEAN, MI_PROF_GRID, MI_PROF_IFFT = 1, 2, 4
 # every entry point declared in include/mi.h
 EXPORTS = ("mi_ctx_create", "mi_ctx_destroy", "mi_last_error", "mi_version", "mi_grid", "mi_ifft2",
            "mi_dirty_image", "mi_dirty_beam", "mi_hogbom_clean", "mi_degrid", "mi_gmm_levels", "mi_disk_offsets", "mi_phase_shift", "mi_profile_begin",
-           "mi_profile_end", "mi_dirty_image_w", "mi_profile_begin_kinds", "mi_profile_end_kinds")
+           "mi_profile_end", "mi_dirty_image_w", "mi_profile_begin_kinds", "mi_profile_end_kinds",
+           "mi_predict_transpose")
 
 
 class MiBatch(ctypes.Structure):
@@ -44,6 +45,10 @@ class MiError(RuntimeError):
 _lib = None
 
 
+def loaded() -> bool:
+    return _lib is not None
+
+
 def lib():
     """The loaded library (raises if it is not built)."""
     global _lib
@@ -66,6 +71,7 @@ def lib():
                                   vp, vp]
     L.mi_dirty_image_w.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, vp, POINTER(MiWprojParams), vp, vp, vp, vp]
     L.mi_degrid.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, c_int, vp, vp]
+    L.mi_predict_transpose.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, vp, vp]
     L.mi_profile_begin_kinds.argtypes = [vp, ctypes.c_uint32]
     L.mi_profile_end_kinds.argtypes = [vp, vp, vp, c_int32, vp]
     for name in EXPORTS:

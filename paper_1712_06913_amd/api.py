@@ -6,8 +6,9 @@ current stream and do not synchronise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
-from typing import Dict, Optional
+from typing import Dict, List, Optional
 
 import numpy as np
 import torch
@@ -15,17 +16,60 @@ import torch
 from . import _native as nat
 
 _ctx_cache: Dict[int, ctypes.c_void_p] = {}
+_private: List["Context"] = []
+
+
+def _create(device: int) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    code = nat.lib().mi_ctx_create(ctypes.byref(ctx), device)
+    if code != nat.MI_OK:
+        raise nat.MiError(code, "mi_ctx_create failed")
+    return ctx
 
 
 def context(device: int = 0) -> ctypes.c_void_p:
-    """Per-device library context (created on first use, kept for the process)."""
+    """Per-device shared library context (created on first use, kept until close())."""
     if device not in _ctx_cache:
-        ctx = ctypes.c_void_p()
-        code = nat.lib().mi_ctx_create(ctypes.byref(ctx), device)
-        if code != nat.MI_OK:
-            raise nat.MiError(code, "mi_ctx_create failed")
-        _ctx_cache[device] = ctx
+        _ctx_cache[device] = _create(device)
     return _ctx_cache[device]
+
+
+class Context:
+    """A private library context (its own plans and workspaces), e.g. for a captured graph
+    that must not share the process-wide plan cache.  Destroyed by close() or at exit."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        self.handle = _create(device)
+        _private.append(self)
+
+    def close(self):
+        if self.handle is not None:
+            torch.cuda.synchronize(self.device)
+            nat.lib().mi_ctx_destroy(self.handle)
+            self.handle = None
+        if self in _private:
+            _private.remove(self)
+
+
+def close():
+    """Synchronise, destroy every library context and release torch's cached device memory.
+    Registered at exit, so the library's device memory is gone before the HIP runtime (and any
+    profiler attached to it) shuts down."""
+    if not nat.loaded():
+        return
+    if torch.cuda.is_available() and torch.cuda.is_initialized():
+        torch.cuda.synchronize()
+    for c in list(_private):
+        c.close()
+    for dev, ctx in list(_ctx_cache.items()):
+        nat.lib().mi_ctx_destroy(ctx)
+        del _ctx_cache[dev]
+    if torch.cuda.is_available() and torch.cuda.is_initialized():
+        torch.cuda.empty_cache()
+
+
+atexit.register(close)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -43,7 +87,8 @@ def _stream(device: torch.device):
 class Batch:
     """Host-side batch descriptor (mi_batch) plus a device status array."""
 
-    def __init__(self, vis_offset, n_img, cell_rad, weight_mode, device="cuda:0"):
+    def __init__(self, vis_offset, n_img, cell_rad, weight_mode, device="cuda:0", ctx: Optional[Context] = None):
+        self._own_ctx = ctx
         self.vis_offset = np.ascontiguousarray(vis_offset, dtype=np.int64)
         self.n_img = np.ascontiguousarray(n_img, dtype=np.int32)
         self.cell_rad = np.ascontiguousarray(cell_rad, dtype=np.float64)
@@ -58,8 +103,8 @@ class Batch:
             self.weight_mode.ctypes.data, self.status.data_ptr())
 
     @classmethod
-    def from_workload(cls, wl, device="cuda:0") -> "Batch":
-        return cls(wl.vis_offset, wl.n_img, wl.cell_rad, wl.weight_mode, device)
+    def from_workload(cls, wl, device="cuda:0", ctx: Optional[Context] = None) -> "Batch":
+        return cls(wl.vis_offset, wl.n_img, wl.cell_rad, wl.weight_mode, device, ctx)
 
     @property
     def c(self):
@@ -67,6 +112,10 @@ class Batch:
 
     @property
     def ctx(self):
+        if self._own_ctx is not None:
+            if self._own_ctx.handle is None:
+                raise RuntimeError("the batch's library context was closed")
+            return self._own_ctx.handle
         return context(self.device.index or 0)
 
     def split(self, flat: torch.Tensor, beam: bool = False):
@@ -201,6 +250,15 @@ def degrid(batch: Batch, image, uv, w, adjoint: bool = False, out=None):
     out = torch.empty(m, dtype=torch.complex64, device=dev) if out is None else out
     nat.check(batch.ctx, nat.lib().mi_degrid(batch.ctx, batch.c, _ptr(image), _ptr(uv), _ptr(w),
                                              1 if adjoint else 0, _ptr(out), _stream(dev)))
+    return out
+
+
+def predict_transpose(batch: Batch, vis, uv, w, out=None):
+    """mi_predict_transpose: P^T v (the transpose of degrid(adjoint=False)), float32 images."""
+    dev = batch.device
+    out = torch.empty(int(batch.img_off[-1]), dtype=torch.float32, device=dev) if out is None else out
+    nat.check(batch.ctx, nat.lib().mi_predict_transpose(batch.ctx, batch.c, _ptr(vis), _ptr(uv), _ptr(w), _ptr(out),
+                                                        _stream(dev)))
     return out
 
 

@@ -6,9 +6,9 @@ ImagingOp:  vis (complex64, all instances packed)  ->  dirty images (float32, pa
             <v,u> = Re sum conj(v) u; for torch's complex gradient convention the
             gradient of a real loss w.r.t. v is exactly that vector).
 PredictOp:  model image (float32, packed) -> model visibilities P(model) (complex64)
-            forward = mi_degrid(adjoint=0); its transpose is the imager with unit weights:
-            P^T(v) = sum_k Re(v_k S_k(x)) / corr(x) = (B0_1 / 2) * dirty_image(v, w = 1),
-            where B0_1 is the normalisation of that unit-weight image.
+            forward = mi_degrid(adjoint=0), backward = mi_predict_transpose: the imager
+            with unit weights on the kept visibilities, scaled by 1/(2 corr) instead of
+            1/(corr B0), P^T(v) = sum_k Re(v_k S_k(x)) / corr(x).
 
 Both run entirely in the HIP library; these classes only wire the calls together.
 """
@@ -41,13 +41,8 @@ class PredictOp(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_vis):
-        b = ctx.batch
-        unit = (ctx.w > 0).to(torch.float32)
-        nb = api.Batch(b.vis_offset, b.n_img, b.cell_rad, b.weight_mode * 0, b.device)
-        img, _, b0 = api.dirty_image(nb, grad_vis.contiguous().to(torch.complex64), ctx.uv, unit, beam=False)
-        scale = torch.repeat_interleave(b0.view(-1, 2)[:, 0] / 2.0,
-                                        torch.as_tensor(b.n_img.astype("int64") ** 2, device=img.device))
-        return (img.double() * scale).float(), None, None, None
+        img = api.predict_transpose(ctx.batch, grad_vis.contiguous().to(torch.complex64), ctx.uv, ctx.w)
+        return img, None, None, None
 
 
 def dirty(vis, batch, uv, w):

@@ -135,15 +135,18 @@ __device__ __forceinline__ float key_value(unsigned k32, int posonly) {
 // barrier `seq`, poll the team's G slots until all carry `seq`, and leave their maximum in
 // *out (~0 if the wait timed out).  `ordered`: wait for this wave's earlier stores
 // (component list) before publishing.
-constexpr unsigned POLL_LIMIT = 1u << 22;
+constexpr unsigned POLL_LIMIT = 1u << 22;     // polls per wait (seconds): a hang becomes an abort
 
+// `poll_limit` bounds every wait; `skip_publish` (failure-path tests only, set from the
+// host) leaves this member's slot unwritten so that every member of the team times out.
 template <bool LOCAL>
 __device__ __forceinline__ void team_exchange(unsigned long long* slots, int G, int member, unsigned seq,
-                                              unsigned long long wk, unsigned long long* out, bool ordered) {
+                                              unsigned long long wk, unsigned long long* out, bool ordered,
+                                              unsigned poll_limit, bool skip_publish) {
   const int lane = threadIdx.x & 63;
   const unsigned s7 = seq & 127u;
   unsigned long long* sl = slots + (seq & 1u) * G;
-  if (lane == 0) {
+  if (lane == 0 && !skip_publish) {
     if (ordered) wait_vm();
     st_shared_u64<LOCAL>(sl + member, (wk & ~0xFEull) | ((unsigned long long)s7 << 1));
   }
@@ -160,7 +163,7 @@ __device__ __forceinline__ void team_exchange(unsigned long long* slots, int G, 
         done = ((unsigned)(v >> 1) & 127u) == s7;
       }
       if (__all(done)) break;
-      if (++spins > POLL_LIMIT) { timed_out = true; break; }
+      if (++spins > poll_limit) { timed_out = true; break; }
     }
     if (m < G && done) k = v > k ? v : k;
   }
@@ -223,6 +226,7 @@ k_clean(CleanArgs A) {
   const int G = A.team_G[team];
   unsigned long long* slots = A.slots + A.team_slot[team];
   unsigned seq = 0;
+  const unsigned poll_limit = A.poll_limit ? A.poll_limit : POLL_LIMIT;
   const float NaN = __uint_as_float(0x7fc00000u);
   const int posonly = A.posonly;
 
@@ -343,14 +347,15 @@ k_clean(CleanArgs A) {
           }
         }
       }
+      const bool stall = A.test_stall && member == 0;
       if (n_tied == 1) {
-        if (wk32 == wg32) team_exchange<LOCAL>(slots, G, member, seq, key, &red_k[seq & 1u], false);
+        if (wk32 == wg32) team_exchange<LOCAL>(slots, G, member, seq, key, &red_k[seq & 1u], false, poll_limit, stall);
       } else {                                        // several waves hold the maximum
         if (lane == 0) red_k[2 + wave] = key;
         __syncthreads();
         if (wave == 0) {
           const unsigned long long wk = wave_max_u64(lane < CL_WAVES ? red_k[2 + lane] : 0ull);
-          team_exchange<LOCAL>(slots, G, member, seq, wk, &red_k[seq & 1u], false);
+          team_exchange<LOCAL>(slots, G, member, seq, wk, &red_k[seq & 1u], false, poll_limit, stall);
         }
       }
       __syncthreads();
@@ -379,7 +384,10 @@ k_clean(CleanArgs A) {
       px = p & (N - 1);
     }
     if (aborted) {
-      if (tid == 0 && A.status) atomicOr(&A.status[img], 16);
+      // this member leaves the kernel: every image still on the team's list (this one
+      // included) is left incomplete, so each of them is flagged
+      if (tid == 0 && A.status)
+        for (int tj = ti; tj < A.team_off[team + 1]; ++tj) atomicOr(&A.status[A.team_imgs[tj]], 16);
       return;
     }
     if (member == 0 && tid == 0 && A.ncomp) A.ncomp[img] = it;
@@ -396,10 +404,11 @@ k_clean(CleanArgs A) {
       // member 0's component stores
       ++seq;
       __syncthreads();
-      if (wave == 0) team_exchange<LOCAL>(slots, G, member, seq, 0ull, &red_k[seq & 1u], true);
+      if (wave == 0) team_exchange<LOCAL>(slots, G, member, seq, 0ull, &red_k[seq & 1u], true, poll_limit, false);
       __syncthreads();
       if (red_k[seq & 1u] == ~0ull) {
-        if (tid == 0 && A.status) atomicOr(&A.status[img], 16);
+        if (tid == 0 && A.status)
+          for (int tj = ti; tj < A.team_off[team + 1]; ++tj) atomicOr(&A.status[A.team_imgs[tj]], 16);
         return;
       }
       const float ga = (float)A.cbeam[6 * img + 0], gb = (float)A.cbeam[6 * img + 1],

@@ -111,7 +111,7 @@ k_bin(const InstDesc* __restrict__ inst, const float2* __restrict__ uv, const fl
       int* __restrict__ status, float* __restrict__ cnt_scratch,
       int* __restrict__ ent_d, int* __restrict__ ent_b,
       int* __restrict__ tstart_d, int* __restrict__ tcount_d,
-      int* __restrict__ tstart_b, int* __restrict__ tcount_b, int fail_inst, int do_beam) {
+      int* __restrict__ tstart_b, int* __restrict__ tcount_b, int fail_inst, int do_beam, int unit_w) {
   extern __shared__ int lds[];
   __shared__ int wave_tot[BIN_THREADS / 64 + 1];
   __shared__ double red_d[2][BIN_THREADS / 64];
@@ -122,7 +122,7 @@ k_bin(const InstDesc* __restrict__ inst, const float2* __restrict__ uv, const fl
 
   // ---- uniform weighting: sum of w_in per nearest N-grid cell (mirrors included).  Only
   // touched cells of the scratch grid are written (zeroed first), so no dense clear.
-  float* cnt = (d.mode == 1) ? cnt_scratch + d.cnt_off : nullptr;
+  float* cnt = (d.mode == 1 && !unit_w) ? cnt_scratch + d.cnt_off : nullptr;
   if (cnt) {
     for (int k = tid; k < d.n_vis; k += blockDim.x) {
       const float2 q = uv[d.vis_off + k];
@@ -152,7 +152,7 @@ k_bin(const InstDesc* __restrict__ inst, const float2* __restrict__ uv, const fl
     const Sample s = prep_sample(q.x, q.y, wi, d.scale, N);
     float w = 0.0f;
     if (s.keep) {
-      w = cnt ? wi / cnt[(s.cv + N / 2) * N + (s.cu + N / 2)] : wi;
+      w = unit_w ? 1.0f : cnt ? wi / cnt[(s.cv + N / 2) * N + (s.cu + N / 2)] : wi;
       ++nk;
       const double wd = 2.0 * (double)w;
       sd += wd * T.tsum[s.ou + OS / 2] * T.tsum[s.ov + OS / 2];
@@ -390,9 +390,9 @@ __global__ void k_expand_full(const InstDesc* __restrict__ inst, int n_inst, int
 hipError_t launch_bin(const InstDesc* inst, int n_inst, const float2* uv, const float* w_in, const Tables& T,
                       float* wts, double* b0, int* nkept, int* status, float* cnt, int* ent_d, int* ent_b,
                       int* tstart_d, int* tcount_d, int* tstart_b, int* tcount_b, int fail_inst, int do_beam,
-                      size_t lds_bytes, hipStream_t st) {
+                      int unit_w, size_t lds_bytes, hipStream_t st) {
   hipLaunchKernelGGL(k_bin, dim3(n_inst), dim3(BIN_THREADS), lds_bytes, st, inst, uv, w_in, T, wts, b0, nkept,
-                     status, cnt, ent_d, ent_b, tstart_d, tcount_d, tstart_b, tcount_b, fail_inst, do_beam);
+                     status, cnt, ent_d, ent_b, tstart_d, tcount_d, tstart_b, tcount_b, fail_inst, do_beam, unit_w);
   return hipGetLastError();
 }
 

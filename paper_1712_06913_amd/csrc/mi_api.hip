@@ -30,7 +30,7 @@ namespace mi {
 
 // launchers (defined next to their kernels)
 hipError_t launch_bin(const InstDesc*, int, const float2*, const float*, const Tables&, float*, double*, int*, int*,
-                      float*, int*, int*, int*, int*, int*, int*, int, int, size_t, hipStream_t);
+                      float*, int*, int*, int*, int*, int*, int*, int, int, int, size_t, hipStream_t);
 hipError_t launch_grid(const InstDesc*, const int*, int, int, const float2*, const float2*, const float*,
                        const float*, const int*, const int*, const int*, const Tables&, double2*, int, hipStream_t);
 hipError_t launch_grid_f32(const InstDesc*, const int*, int, int, const float2*, const float2*, const float*,
@@ -143,7 +143,15 @@ uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
   return h;
 }
 
-struct CleanPlan {
+// Cached plans are evicted least-recently-used first.  A plan used while its stream is
+// being captured into a graph is pinned: the graph holds raw pointers into its buffers,
+// so it stays until the context is destroyed.
+struct CacheEntry {
+  uint64_t last_use = 0;
+  bool pinned = false;
+};
+
+struct CleanPlan : CacheEntry {
   std::vector<int32_t> niter;
   std::vector<float> thr;
   bool has_thr = false;
@@ -156,7 +164,7 @@ struct CleanPlan {
       comp_flux, cbeam, rrad;
 };
 
-struct Plan {
+struct Plan : CacheEntry {
   // key
   std::vector<int64_t> off;
   std::vector<int32_t> n;
@@ -175,7 +183,11 @@ struct Plan {
   // workspace
   // gd: dirty half grids (FP64 complex); gbr: beam half grids (FP64 real), then the beam's
   // transform slots in place; gb: FP64 complex beam grids for mi_grid's full layout
-  DevBuf wts, b0, nkept, cnt, ent_d, ent_b, ts_d, tc_d, ts_b, tc_b, gd, gbr, gb, status_ws, full_off;
+  DevBuf wts, b0, nkept, cnt, ent_d, ent_b, ts_d, tc_d, ts_b, tc_b, gd, gbr, gb, status_ws;
+  // element offsets of each instance's grid in mi_grid's full layout: dirty grids; beam
+  // grids after all dirty grids; beam grids alone (3 n_inst values, uploaded with the plan)
+  DevBuf full_off;
+  DevBuf b0_two;      // 2.0 per grid: pass B then scales by 1/2 (transpose of the prediction)
   std::map<uint64_t, std::unique_ptr<CleanPlan>> cleans;
   // w-projection: plane plan and kernel tables for one (w_max, tolerance) set
   struct WProj {
@@ -192,7 +204,7 @@ struct Plan {
   DevBuf radius_d, corr_n, corr_offs, corr_work, corr_x, corr_d, corr_s, offsets_ws;
 };
 
-struct IfftPlan {
+struct IfftPlan : CacheEntry {
   std::vector<int32_t> n;
   std::vector<int64_t> offs;
   int64_t total = 0;
@@ -212,7 +224,9 @@ struct mi_ctx {
   std::map<uint64_t, std::unique_ptr<mi::IfftPlan>> ifft_plans;
   mi::DevBuf ifft_scratch;
   int fail_inst = -1;
+  int clean_stall = 0;   // failure-path tests (MI_TEST_CLEAN_STALL): CLEAN team waits give up
   int n_cu = 256;
+  uint64_t tick = 0;     // plan-cache clock (least recently used is evicted first)
   // kernel timing: event pairs around launches of the kinds in prof_kinds (MI_PROF_*)
   uint32_t prof_kinds = 0;
   size_t prof_used = 0;
@@ -230,6 +244,34 @@ namespace mi {
 namespace {
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIPCHK(hipStreamIsCapturing(st, &cs));
+  return cs != hipStreamCaptureStatusNone;
+}
+
+// Marks a cached plan as used now (pinned for good when the stream is being captured).
+void touch(mi_ctx* ctx, CacheEntry* e, hipStream_t st) {
+  e->last_use = ++ctx->tick;
+  if (capturing(st)) e->pinned = true;
+}
+
+// Makes room for one more entry in a plan cache of at most `cap` unpinned entries: evicts
+// the least recently used unpinned plan.  A new plan allocates and uploads, which a graph
+// capture cannot record, so creating one while capturing is an error.
+template <class M>
+void make_room(M& cache, size_t cap, hipStream_t st) {
+  if (capturing(st))
+    fail(MI_ERR_UNSUPPORTED, "a call with new arguments cannot be captured: run it once outside the capture first");
+  size_t unpinned = 0;
+  for (auto& kv : cache) unpinned += kv.second->pinned ? 0 : 1;
+  if (unpinned < cap) return;
+  auto victim = cache.end();
+  for (auto it = cache.begin(); it != cache.end(); ++it)
+    if (!it->second->pinned && (victim == cache.end() || it->second->last_use < victim->second->last_use)) victim = it;
+  if (victim != cache.end()) cache.erase(victim);
+}
 
 // Kernel timing: when `kind` is being recorded, record the start event of a fresh pair on
 // the stream and return the pair's end event (to be recorded after the launch); else null.
@@ -273,7 +315,7 @@ void check_batch(const mi_batch* b) {
   }
 }
 
-Plan* get_plan(mi_ctx* ctx, const mi_batch* b) {
+Plan* get_plan(mi_ctx* ctx, const mi_batch* b, hipStream_t st) {
   check_batch(b);
   const int n = b->n_inst;
   uint64_t h = fnv1a(&n, sizeof n);
@@ -286,10 +328,15 @@ Plan* get_plan(mi_ctx* ctx, const mi_batch* b) {
     Plan* p = it->second.get();
     if (p->n_inst == n && std::equal(p->off.begin(), p->off.end(), b->vis_offset) &&
         std::equal(p->n.begin(), p->n.end(), b->n_img) && std::equal(p->cell.begin(), p->cell.end(), b->cell_rad) &&
-        std::equal(p->mode.begin(), p->mode.end(), b->weight_mode))
+        std::equal(p->mode.begin(), p->mode.end(), b->weight_mode)) {
+      touch(ctx, p, st);
       return p;
+    }
+    // another descriptor with the same key (a hash collision): replace it
+    if (p->pinned) fail(MI_ERR_UNSUPPORTED, "plan cache collision with a plan held by a captured graph");
+    ctx->plans.erase(it);
   }
-  if (ctx->plans.size() >= 16) ctx->plans.erase(ctx->plans.begin());
+  make_room(ctx->plans, 16, st);
   auto P = std::make_unique<Plan>();
   P->n_inst = n;
   P->off.assign(b->vis_offset, b->vis_offset + n + 1);
@@ -358,14 +405,27 @@ Plan* get_plan(mi_ctx* ctx, const mi_batch* b) {
   P->n_wb_d = (int)wb_d.size();
   P->n_wa_b = (int)wa_b.size();
   P->n_wb_b = (int)wb_b.size();
+  {
+    // full-layout grid offsets for mi_grid (which = 0 / 2: dirty then beam; which = 1: beam alone)
+    std::vector<int64_t> fo(3 * (size_t)n);
+    int64_t sd = 0, sb = 0;
+    for (int i = 0; i < n; ++i) { fo[i] = sd; sd += (int64_t)P->n[i] * P->n[i]; }
+    for (int i = 0; i < n; ++i) {
+      fo[n + i] = sd + sb;
+      fo[2 * n + i] = sb;
+      sb += 4LL * P->n[i] * P->n[i];
+    }
+    upload(P->full_off, fo);
+  }
   Plan* raw = P.get();
+  touch(ctx, raw, st);
   ctx->plans[h] = std::move(P);
   return raw;
 }
 
 // Prep + weights + B0 + binning (k_bin).  Returns the status pointer used.
 int* run_bin(mi_ctx* ctx, Plan* P, const mi_batch* b, const float* uv, const float* w_in, bool beam,
-             hipStream_t st) {
+             hipStream_t st, bool unit_w = false) {
   float* wts = dev_alloc<float>(P->wts, P->total_vis);
   double* b0 = dev_alloc<double>(P->b0, 2 * P->n_inst);
   int* nk = dev_alloc<int>(P->nkept, P->n_inst);
@@ -379,7 +439,7 @@ int* run_bin(mi_ctx* ctx, Plan* P, const mi_batch* b, const float* uv, const flo
   int* status = b->status ? b->status : dev_alloc<int>(P->status_ws, P->n_inst);
   HIPCHK(launch_bin(static_cast<const InstDesc*>(P->inst.p), P->n_inst, reinterpret_cast<const float2*>(uv), w_in,
                     ctx->T, wts, b0, nk, status, cnt, ed, eb, tsd, tcd, tsb, tcb, ctx->fail_inst, beam ? 1 : 0,
-                    P->bin_lds, st));
+                    unit_w ? 1 : 0, P->bin_lds, st));
   return status;
 }
 
@@ -405,10 +465,10 @@ void run_grid(mi_ctx* ctx, Plan* P, const mi_c64* vis, const float* uv, const fl
 }
 
 // Dirty images from the dirty half grids in P->gd.
-void run_image(mi_ctx* ctx, Plan* P, float* out, hipStream_t st) {
+void run_image(mi_ctx* ctx, Plan* P, float* out, hipStream_t st, const double* b0 = nullptr) {
   const InstDesc* inst = static_cast<const InstDesc*>(P->inst.p);
   double2* g = static_cast<double2*>(P->gd.p);
-  const double* b0 = static_cast<const double*>(P->b0.p);
+  if (!b0) b0 = static_cast<const double*>(P->b0.p);
   hipEvent_t pe = prof_start(ctx, MI_PROF_IFFT, st);
   HIPCHK(launch_fft_a(P->elems_d, ctx->n_cu, inst, static_cast<const FftWork*>(P->wa_d.p), P->n_wa_d, g, ctx->T, st));
   prof_stop(pe, st);
@@ -641,6 +701,8 @@ mi_status mi_ctx_create(mi_ctx** out, int device) {
     ctx->n_cu = prop.multiProcessorCount;
     const char* fi = std::getenv("MI_TEST_FAIL_INSTANCE");
     ctx->fail_inst = fi ? std::atoi(fi) : -1;
+    const char* cs = std::getenv("MI_TEST_CLEAN_STALL");
+    ctx->clean_stall = cs && std::atoi(cs) != 0 ? 1 : 0;
     HostTables H = build_host_tables(W, OS, 1.0, 200);
     ctx->T.tab = upload(ctx->tab, H.tab);
     ctx->T.tsum = upload(ctx->tsum, H.tsum);
@@ -673,7 +735,7 @@ mi_status mi_gmm_levels(mi_ctx* ctx, const mi_batch* batch, const float* images,
     if (n_bins < 2 || n_bins > 4096) fail(MI_ERR_ARG, "n_bins must be in [2, 4096] (got %d)", n_bins);
     if (n_iter < 0 || n_iter > 100000) fail(MI_ERR_ARG, "n_iter must be in [0, 100000] (got %d)", n_iter);
     HIPCHK(hipSetDevice(ctx->device));
-    Plan* P = get_plan(ctx, batch);
+    Plan* P = get_plan(ctx, batch, stream);
     HIPCHK(launch_gmm(static_cast<const InstDesc*>(P->inst.p), P->n_inst, images, n_bins, n_iter, levels_out,
                       mu_a_out, mu_b_out, stream));
   });
@@ -686,7 +748,7 @@ mi_status mi_disk_offsets(mi_ctx* ctx, const mi_batch* batch, const float* image
     need(radius_px, "radius_px");
     need(offsets_out, "offsets_out");
     HIPCHK(hipSetDevice(ctx->device));
-    Plan* P = get_plan(ctx, batch);
+    Plan* P = get_plan(ctx, batch, stream);
     const int n = P->n_inst;
     for (int i = 0; i < n; ++i)
       if (!(radius_px[i] > 0.0) || !(radius_px[i] < 1e6)) fail(MI_ERR_ARG, "radius_px[%d] must be positive", i);
@@ -745,7 +807,7 @@ mi_status mi_phase_shift(mi_ctx* ctx, const mi_batch* batch, mi_c64* vis, const 
     need(uv, "uv");
     need(offsets, "offsets");
     HIPCHK(hipSetDevice(ctx->device));
-    Plan* P = get_plan(ctx, batch);
+    Plan* P = get_plan(ctx, batch, stream);
     HIPCHK(launch_phase_shift(static_cast<const InstDesc*>(P->inst.p), P->n_inst, P->max_nvis,
                               reinterpret_cast<float2*>(vis), reinterpret_cast<const float2*>(uv), offsets, stream));
   });
@@ -797,24 +859,16 @@ mi_status mi_grid(mi_ctx* ctx, const mi_batch* batch, const mi_c64* vis, const f
     if (which != 1) need(vis, "vis");
     if (reinterpret_cast<uintptr_t>(grid_out) % 16) fail(MI_ERR_ARG, "grid_out must be 16-byte aligned");
     HIPCHK(hipSetDevice(ctx->device));
-    Plan* P = get_plan(ctx, batch);
+    Plan* P = get_plan(ctx, batch, stream);
     const bool want_d = which != 1, want_b = which != 0;
     run_bin(ctx, P, batch, uv, w_in, want_b, stream);
     float2* out = reinterpret_cast<float2*>(grid_out);
-    const int64_t full_d = [&] { int64_t s = 0; for (int N : P->n) s += (int64_t)N * N; return s; }();
     if (layout == MI_LAYOUT_HALF) {
       if (want_d) run_grid<float2>(ctx, P, vis, uv, w_in, false, out, 0, stream);
       if (want_b) run_grid<float2>(ctx, P, vis, uv, w_in, true, out + (want_d ? P->total_gd : 0), 0, stream);
     } else {
-      std::vector<int64_t> offs(P->n_inst);
-      int64_t* offd = dev_alloc<int64_t>(P->full_off, 2 * P->n_inst);
-      std::vector<int64_t> h(2 * P->n_inst);
-      int64_t s = 0;
-      for (int i = 0; i < P->n_inst; ++i) { h[i] = s; s += (int64_t)P->n[i] * P->n[i]; }
-      int64_t s2 = want_d ? full_d : 0;
-      for (int i = 0; i < P->n_inst; ++i) { h[P->n_inst + i] = s2; s2 += 4LL * P->n[i] * P->n[i]; }
-      HIPCHK(hipMemcpyAsync(offd, h.data(), sizeof(int64_t) * h.size(), hipMemcpyHostToDevice, stream));
-      HIPCHK(hipStreamSynchronize(stream));   // pageable source: keep it alive until copied
+      // offsets uploaded with the plan: dirty grids, beam grids after them, beam grids alone
+      const int64_t* offd = static_cast<const int64_t*>(P->full_off.p);
       const InstDesc* inst = static_cast<const InstDesc*>(P->inst.p);
       if (want_d) {
         double2* g = dev_alloc<double2>(P->gd, P->total_gd);
@@ -824,7 +878,7 @@ mi_status mi_grid(mi_ctx* ctx, const mi_batch* batch, const mi_c64* vis, const f
       if (want_b) {
         double2* g = dev_alloc<double2>(P->gb, P->total_gb);
         run_grid<double2>(ctx, P, vis, uv, w_in, true, g, 0, stream);
-        HIPCHK(launch_expand_full(inst, P->n_inst, 1, g, out, offd + P->n_inst, stream));
+        HIPCHK(launch_expand_full(inst, P->n_inst, 1, g, out, offd + (want_d ? 1 : 2) * P->n_inst, stream));
       }
     }
     copy_b0(P, b0_out, stream);
@@ -855,8 +909,13 @@ mi_status mi_ifft2(mi_ctx* ctx, mi_c64* data, const int32_t* n, const int64_t* o
     if (it != ctx->ifft_plans.end() && std::equal(it->second->n.begin(), it->second->n.end(), n) &&
         std::equal(it->second->offs.begin(), it->second->offs.end(), offs)) {
       P = it->second.get();
+      touch(ctx, P, stream);
     } else {
-      if (ctx->ifft_plans.size() >= 16) ctx->ifft_plans.erase(ctx->ifft_plans.begin());
+      if (it != ctx->ifft_plans.end()) {            // a hash collision: replace that entry
+        if (it->second->pinned) fail(MI_ERR_UNSUPPORTED, "transform plan collision with a plan held by a captured graph");
+        ctx->ifft_plans.erase(it);
+      }
+      make_room(ctx->ifft_plans, 16, stream);
       auto up = std::make_unique<IfftPlan>();
       up->n.assign(n, n + n_inst);
       up->offs.assign(offs, offs + n_inst);
@@ -877,6 +936,7 @@ mi_status mi_ifft2(mi_ctx* ctx, mi_c64* data, const int32_t* n, const int64_t* o
       upload(up->offs_d, up->offs);
       upload(up->work, work);
       P = up.get();
+      touch(ctx, P, stream);
       ctx->ifft_plans[h] = std::move(up);
     }
     double2* scratch = dev_alloc<double2>(ctx->ifft_scratch, P->total);
@@ -898,7 +958,7 @@ mi_status mi_dirty_image(mi_ctx* ctx, const mi_batch* batch, const mi_c64* vis, 
     need(w_in, "w_in");
     need(dirty_out, "dirty_out");
     HIPCHK(hipSetDevice(ctx->device));
-    Plan* P = get_plan(ctx, batch);
+    Plan* P = get_plan(ctx, batch, stream);
     const bool beam = beam_out != nullptr;
     run_bin(ctx, P, batch, uv, w_in, beam, stream);
     double2* gd = dev_alloc<double2>(P->gd, P->total_gd);
@@ -989,7 +1049,7 @@ mi_status mi_dirty_image_w(mi_ctx* ctx, const mi_batch* batch, const mi_c64* vis
     const double tol = wp->phase_tol > 0.0 ? wp->phase_tol : 0.1;
     if (!std::isfinite(tol)) fail(MI_ERR_ARG, "phase_tol must be finite");
     HIPCHK(hipSetDevice(ctx->device));
-    Plan* P = get_plan(ctx, batch);
+    Plan* P = get_plan(ctx, batch, stream);
     for (int i = 0; i < P->n_inst; ++i)
       if (!(wp->w_max[i] >= 0.0) || !std::isfinite(wp->w_max[i])) fail(MI_ERR_ARG, "w_max[%d] must be finite and >= 0", i);
     if (!P->wproj || P->wproj->tol != tol ||
@@ -1025,7 +1085,7 @@ mi_status mi_dirty_beam(mi_ctx* ctx, const mi_batch* batch, const float* uv, con
     need(w_in, "w_in");
     need(beam_out, "beam_out");
     HIPCHK(hipSetDevice(ctx->device));
-    Plan* P = get_plan(ctx, batch);
+    Plan* P = get_plan(ctx, batch, stream);
     run_bin(ctx, P, batch, uv, w_in, true, stream);
     run_beam(ctx, P, uv, w_in, beam_out, stream);
   });
@@ -1044,11 +1104,10 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
     if ((comp_idx == nullptr) != (comp_flux == nullptr)) fail(MI_ERR_ARG, "comp_idx and comp_flux: both or neither");
     if (!(prm->gain > 0.0f && prm->gain <= 1.0f)) fail(MI_ERR_ARG, "gain must be in (0, 1]");
     HIPCHK(hipSetDevice(ctx->device));
-    Plan* P = get_plan(ctx, batch);
+    Plan* P = get_plan(ctx, batch, stream);
     const int n = P->n_inst;
     for (int i = 0; i < n; ++i)
       if (prm->niter[i] < 0) fail(MI_ERR_ARG, "niter[%d] < 0", i);
-    if (P->max_N > 1024) fail(MI_ERR_UNSUPPORTED, "CLEAN supports N <= 1024 (got %d)", P->max_N);
     const int req = prm->team_size;
     if (req != 0 && (!is_pow2(req) || req > 256)) fail(MI_ERR_ARG, "team_size must be 0 or a power of two <= 256");
     // clean plan: team shapes, XCD packing, LPT assignment, device copies of niter / thresholds
@@ -1076,8 +1135,13 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
         it->second->win.size() == n_win &&
         std::equal(it->second->win.begin(), it->second->win.end(), prm->window)) {
       C = it->second.get();
+      touch(ctx, C, stream);
     } else {
-      if (P->cleans.size() >= 8) P->cleans.erase(P->cleans.begin());
+      if (it != P->cleans.end()) {                  // a hash collision: replace that entry
+        if (it->second->pinned) fail(MI_ERR_UNSUPPORTED, "CLEAN plan collision with a plan held by a captured graph");
+        P->cleans.erase(it);
+      }
+      make_room(P->cleans, 8, stream);
       auto up = std::make_unique<CleanPlan>();
       C = up.get();
       C->team_req = req;
@@ -1086,6 +1150,7 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
       if (has_thr) C->thr.assign(prm->threshold, prm->threshold + n);
       if (n_win) C->win.assign(prm->window, prm->window + n_win);
       build_clean_schedule(ctx, P, C, req);
+      touch(ctx, C, stream);
       P->cleans[h] = std::move(up);
     }
     int* status = batch->status;
@@ -1135,6 +1200,8 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
     A.slots = static_cast<unsigned long long*>(C->slots.p);
     A.asym = asym;
     A.status = status;
+    A.poll_limit = ctx->clean_stall ? 256u : 0u;
+    A.test_stall = ctx->clean_stall;
     hipEvent_t pe = prof_start(ctx, MI_PROF_CLEAN, stream);
     HIPCHK(launch_clean(A, C->ppt, C->local != 0, C->n_blocks, C->lds, stream));
     prof_stop(pe, stream);
@@ -1150,7 +1217,7 @@ mi_status mi_degrid(mi_ctx* ctx, const mi_batch* batch, const float* image, cons
     need(vis_out, "vis_out");
     if (adjoint != 0 && adjoint != 1) fail(MI_ERR_ARG, "adjoint must be 0 or 1");
     HIPCHK(hipSetDevice(ctx->device));
-    Plan* P = get_plan(ctx, batch);
+    Plan* P = get_plan(ctx, batch, stream);
     run_bin(ctx, P, batch, uv, w_in, false, stream);
     double2* g = dev_alloc<double2>(P->gd, P->total_gd);
     const InstDesc* inst = static_cast<const InstDesc*>(P->inst.p);
@@ -1160,6 +1227,25 @@ mi_status mi_degrid(mi_ctx* ctx, const mi_batch* batch, const float* image, cons
     HIPCHK(launch_degrid(inst, P->n_inst, P->max_nvis, reinterpret_cast<const float2*>(uv), w_in,
                          static_cast<const float*>(P->wts.p), static_cast<const double*>(P->b0.p), g, ctx->T,
                          adjoint, reinterpret_cast<float2*>(vis_out), stream));
+  });
+}
+
+mi_status mi_predict_transpose(mi_ctx* ctx, const mi_batch* batch, const mi_c64* vis, const float* uv,
+                               const float* w_in, float* image_out, hipStream_t stream) {
+  return guard(ctx, [&] {
+    need(vis, "vis");
+    need(uv, "uv");
+    need(w_in, "w_in");
+    need(image_out, "image_out");
+    HIPCHK(hipSetDevice(ctx->device));
+    Plan* P = get_plan(ctx, batch, stream);
+    if (!P->b0_two.p) upload(P->b0_two, std::vector<double>(2 * (size_t)P->n_inst, 2.0));
+    // unit weights on the kept samples, the dirty-image transform, then 1/(2 corr) per axis
+    // pair instead of 1/(corr B0): Re I_raw / (2 corr) = P^T v
+    run_bin(ctx, P, batch, uv, w_in, false, stream, true);
+    double2* gd = dev_alloc<double2>(P->gd, P->total_gd);
+    run_grid<double2>(ctx, P, vis, uv, w_in, false, gd, 1, stream);
+    run_image(ctx, P, image_out, stream, static_cast<const double*>(P->b0_two.p));
   });
 }
 

@@ -87,6 +87,8 @@ struct CleanArgs {
   unsigned long long* slots;  // per team: 2 x G keys
   const int* asym;         // per instance: nonzero unless the beam is exactly point-symmetric
   int* status;             // may be null
+  unsigned poll_limit;     // polls per team wait before giving up (0: the default)
+  int test_stall;          // failure-path tests: member 0 never publishes, every wait times out
 };
 
 // Round half away from zero, written as sign(x) floor(|x| + 1/2) in FP64 (identical

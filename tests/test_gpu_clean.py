@@ -225,3 +225,154 @@ def test_profile_hook_times_each_hogbom_launch():
     ms = api.profile_end()
     assert len(ms) == 3 and all(t > 0.0 for t in ms), ms
     assert api.profile_end() == []            # recording stopped and cleared
+
+
+def test_clean_c3_headline_depth_5000_iterations():
+    log("[clean] one C3 channel at 1024^2, 5000 iterations: GPU dirty image + beam, GPU CLEAN + restore, "
+        "every pick replayed by the oracle")
+    require_gpu()
+    from paper_1712_06913_amd import api
+    wl = synth.c3_muser2(chans=[3])
+    b = api.Batch.from_workload(wl)
+    vis, uv, w = api.workload_tensors(wl)
+    dirty, beam, _ = api.dirty_image(b, vis, uv, w, beam=True)
+    res = api.hogbom_clean(b, dirty, beam, wl.niter, gain=wl.gain, restore=True)
+    torch.cuda.synchronize()
+    v, uvi, wi = wl.instance(0)
+    N, cell = int(wl.n_img[0]), float(wl.cell_rad[0])
+    D = dirty.cpu().numpy().reshape(N, N).astype(np.float64)
+    B = beam.cpu().numpy().reshape(2 * N, 2 * N).astype(np.float64)
+    ref = imager.dirty_image(v, uvi, wi, N, cell, 0)
+    peak = float(np.max(np.abs(ref)))
+    assert max_abs(D, ref) <= 1e-4 * peak
+    assert max_abs(B, imager.dirty_beam(uvi, wi, N, cell, 0)) <= 1e-4
+    n = int(res["n_comp"][0])
+    assert n == 5000 and int(b.status[0]) == 0
+    ok, bad, R, M = clean.replay(D, B, res["comp_idx"].cpu().numpy()[:n], res["comp_flux"].cpu().numpy()[:n])
+    assert ok, f"replay rejected pick {bad}"
+    e_r = max_abs(res["residual"].cpu().numpy().reshape(N, N), R)
+    e_m = max_abs(res["model"].cpu().numpy().reshape(N, N), M)
+    abc = clean.fit_clean_beam(B)
+    rest = clean.restore_conv(R, M, abc)
+    e_s = max_abs(res["restored"].cpu().numpy().reshape(N, N), rest)
+    log(f"  residual {e_r / peak:.2e}, model {e_m / peak:.2e}, restored {e_s / peak:.2e} of the peak")
+    assert e_r <= 1e-4 * peak and e_m <= 1e-5 * peak and e_s <= 1e-4 * peak
+
+
+def test_clean_c2_slice_full_depth_2000():
+    log("[clean] C2 slice at its full depth: 512^2, 2000 iterations")
+    wl = synth.c2_muser1_batch(n_chan=1, n_snap=2)
+    _check(wl, wl.niter)
+
+
+def _tie_case(N, coords, vals, extra):
+    """A map with |value| ties at `coords` (mixed signs) and distinct smaller values at `extra`."""
+    D = np.zeros((N, N), np.float32)
+    for (y, x), v in zip(coords, vals):
+        D[y, x] = v
+    for k, (y, x) in enumerate(extra):
+        D[y, x] = 0.5 - 0.01 * k
+    return D
+
+
+@pytest.mark.parametrize("N,team", [(1024, 16), (1024, 32), (256, 0), (256, 4)])
+@pytest.mark.parametrize("positive_only", [False, True])
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_clean_exact_ties_pick_lowest_index(N, team, positive_only, symmetric):
+    """Equal |values| of mixed sign spread over lanes, 4-pixel groups, waves and team members:
+    with a delta beam and gain 1 each pick removes one pixel, so the pick order is the tie
+    rule itself (lowest y N + x first), compared exactly with the oracle."""
+    log(f"[clean] exact ties N={N} team={team} positive_only={positive_only} symmetric={symmetric}")
+    require_gpu()
+    from paper_1712_06913_amd import api
+    s = N // 1024 if N >= 1024 else 1
+    coords = [(5 * s, 8), (5 * s, 9),            # one 4-pixel group
+              (5 * s, 20),                      # another lane of the same wave
+              (5 * s, N // 4 + 44),             # another wave, same row
+              (N // 16, 0),                     # first pixel of another member (teams of 16)
+              (N // 2 + 3, N - 1), (N - 1, 3),   # far members
+              (N // 3, N // 2)]
+    vals = [1.0, -1.0, 1.0, -1.0, 1.0, -1.0, 1.0, 1.0]
+    extra = [(N // 2, N // 2 + 7), (7, 7), (N - 2, N - 9)]
+    D = _tie_case(N, coords, vals, extra)
+    B = np.zeros((2 * N, 2 * N), np.float32)
+    B[N, N] = 1.0
+    if not symmetric:
+        B[1, 1] = 1e-3                          # reached by no pick here; breaks the point symmetry
+    wl = synth.random_instances(29, [N], m_range=(10, 10))
+    b = api.Batch.from_workload(wl)
+    niter = np.array([20], np.int32)
+    res = api.hogbom_clean(b, torch.from_numpy(D.ravel()).cuda(), torch.from_numpy(B.ravel()).cuda(), niter,
+                           gain=1.0, positive_only=positive_only, team_size=team)
+    torch.cuda.synchronize()
+    R0, M0, idx0, flux0 = clean.hogbom(D.astype(np.float64), B.astype(np.float64), gain=1.0, niter=20,
+                                       positive_only=positive_only)
+    n = int(res["n_comp"][0])
+    gi = res["comp_idx"].cpu().numpy()[:n]
+    log(f"  gpu picks {gi.tolist()}")
+    assert n == len(idx0) and np.array_equal(gi, idx0)
+    assert np.array_equal(res["comp_flux"].cpu().numpy()[:n], flux0)
+    assert np.array_equal(res["residual"].cpu().numpy().reshape(N, N), R0.astype(np.float32))
+
+
+@pytest.mark.parametrize("team", [64, 128, 256])
+def test_clean_non_local_team_sizes_match_oracle(team):
+    """Teams spread over several XCDs (what the autotuner may pick for few images)."""
+    log(f"[clean] 1024^2 with teams of {team} workgroups (non-local), replayed by the oracle")
+    wl = synth.c3_muser2(chans=[11], niter=120)
+    _check(wl, np.array([120], np.int32), team_size=team)
+
+
+@pytest.mark.parametrize("N,niter", [(2048, 120), (4096, 40)])
+def test_clean_large_images(N, niter):
+    log(f"[clean] {N}^2 images ({N * N // 65536} workgroups per image), replayed by the oracle")
+    require_gpu()
+    from paper_1712_06913_amd import api
+    wl = synth.random_instances(30, [N], m_range=(600, 600), uniform_frac=0.0)
+    b = api.Batch.from_workload(wl)
+    vis, uv, w = api.workload_tensors(wl)
+    dirty, beam, _ = api.dirty_image(b, vis, uv, w, beam=True)
+    res = api.hogbom_clean(b, dirty, beam, np.array([niter], np.int32), restore=True)
+    torch.cuda.synchronize()
+    assert int(b.status[0]) & 16 == 0
+    D = dirty.cpu().numpy().reshape(N, N).astype(np.float64)
+    B = beam.cpu().numpy().reshape(2 * N, 2 * N).astype(np.float64)
+    del dirty, beam
+    n = int(res["n_comp"][0])
+    assert n == niter
+    ok, bad, R, M = clean.replay(D, B, res["comp_idx"].cpu().numpy()[:n], res["comp_flux"].cpu().numpy()[:n])
+    assert ok, f"replay rejected pick {bad}"
+    peak = float(np.max(np.abs(D)))
+    assert max_abs(res["residual"].cpu().numpy().reshape(N, N), R) <= 1e-4 * peak
+    assert max_abs(res["model"].cpu().numpy().reshape(N, N), M) <= 1e-5 * peak
+    rest = clean.restore_conv(R, M, clean.fit_clean_beam(B), radius=256)
+    assert max_abs(res["restored"].cpu().numpy().reshape(N, N), rest) <= 1e-4 * peak
+
+
+def test_clean_abort_flags_every_image_of_the_team():
+    """Failure path forced from the host: with MI_TEST_CLEAN_STALL set when the context is
+    made, one team member never publishes and every team wait gives up after a few polls.
+    All images of a team that owns several must come back flagged MI_INST_ABORTED."""
+    log("[clean] forced team-wait timeout: every image of the team is flagged")
+    require_gpu()
+    import os
+    from paper_1712_06913_amd import api
+    os.environ["MI_TEST_CLEAN_STALL"] = "1"
+    try:
+        ctx = api.Context(0)
+    finally:
+        del os.environ["MI_TEST_CLEAN_STALL"]
+    try:
+        wl = synth.random_instances(33, [256] * 5, m_range=(100, 200))
+        dirty, beams = _inputs(wl)
+        b = api.Batch.from_workload(wl, ctx=ctx)
+        d_t = torch.from_numpy(np.concatenate([x.ravel() for x in dirty])).cuda()
+        b_t = torch.from_numpy(np.concatenate([x.ravel() for x in beams])).cuda()
+        # one team of 256 workgroups (the whole device at 256^2) owns all five images
+        api.hogbom_clean(b, d_t, b_t, np.full(5, 30, np.int32), team_size=256)
+        torch.cuda.synchronize()
+        st = b.status.cpu().numpy()
+        log(f"  status {st.tolist()}")
+        assert np.all(st & 16)
+    finally:
+        ctx.close()

@@ -90,3 +90,72 @@ def test_dot_product_identity_on_gpu():
     rhs = float(torch.sum(vis.real.double() * aty.real.double() + vis.imag.double() * aty.imag.double()))
     log(f"  <Av,y>={lhs:.9e} <v,ATy>={rhs:.9e} rel={abs(lhs - rhs) / abs(lhs):.2e}")
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+@pytest.mark.parametrize("adj", [False, True])
+def test_degrid_at_c5_size_matches_oracle(adj):
+    """C5's shape: 1024^2 images, the full MUSER-II-like baseline set, two channels."""
+    log(f"[degrid] C5 shape 1024^2, adjoint={adj}")
+    api = _api()
+    wl = synth.c5_differentiable(n_chan=2, N=1024)
+    b = api.Batch.from_workload(wl)
+    vis, uv, w = api.workload_tensors(wl)
+    rng = np.random.default_rng(7)
+    imgs = [rng.standard_normal((1024, 1024)).astype(np.float32) for _ in range(wl.n_inst)]
+    y = torch.from_numpy(np.concatenate([x.ravel() for x in imgs])).cuda()
+    out = api.degrid(b, y, uv, w, adjoint=adj)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    for i in range(wl.n_inst):
+        v, uvi, wi = wl.instance(i)
+        N, cell, mode = 1024, float(wl.cell_rad[i]), int(wl.weight_mode[i])
+        yi = imgs[i].astype(np.float64)
+        ref = adjoint.adjoint(yi, uvi, wi, N, cell, mode) if adj else adjoint.predict(yi, uvi, wi, N, cell)
+        got = out[wl.vis_offset[i]: wl.vis_offset[i + 1]]
+        scale = np.max(np.abs(ref))
+        err = np.max(np.abs(got - ref))
+        log(f"  inst {i}: err/max={err / scale:.2e}")
+        assert err <= 1e-5 * scale * np.log2(N)
+
+
+def test_dot_product_identity_at_c5_size():
+    log("[degrid] dot-product tests at C5's 1024^2 shape: imaging operator and prediction")
+    api = _api()
+    wl = synth.c5_differentiable(n_chan=4, N=1024)
+    b = api.Batch.from_workload(wl)
+    vis, uv, w = api.workload_tensors(wl)
+    rng = np.random.default_rng(8)
+    y = torch.from_numpy(rng.standard_normal(int(b.img_off[-1])).astype(np.float32)).cuda()
+    dirty, _, _ = api.dirty_image(b, vis, uv, w, beam=False)
+    aty = api.degrid(b, y, uv, w, adjoint=True)
+    py = api.degrid(b, y, uv, w, adjoint=False)
+    ptv = api.predict_transpose(b, vis, uv, w)
+    torch.cuda.synchronize()
+    dot = lambda a, c: float(torch.sum(a.real.double() * c.real.double() + a.imag.double() * c.imag.double()))
+    lhs, rhs = float(torch.dot(dirty.double(), y.double())), dot(vis, aty)
+    log(f"  <Av,y>={lhs:.9e} <v,ATy>={rhs:.9e} rel={abs(lhs - rhs) / abs(lhs):.2e}")
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+    lhs, rhs = dot(py, vis), float(torch.dot(y.double(), ptv.double()))
+    log(f"  <Py,v>={lhs:.9e} <y,PTv>={rhs:.9e} rel={abs(lhs - rhs) / abs(lhs):.2e}")
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+def test_predict_transpose_is_the_scaled_unit_weight_image():
+    """P^T v = (B0 / 2) x the dirty image of v with unit weights (natural weighting)."""
+    log("[degrid] predict transpose vs the oracle's unit-weight imager")
+    api = _api()
+    wl = synth.random_instances(34, [64, 128, 256], m_range=(80, 300))
+    b = api.Batch.from_workload(wl)
+    vis, uv, w = api.workload_tensors(wl)
+    img = api.predict_transpose(b, vis, uv, w)
+    torch.cuda.synchronize()
+    got = b.split(img)
+    for i in range(wl.n_inst):
+        v, uvi, wi = wl.instance(i)
+        N, cell = int(wl.n_img[i]), float(wl.cell_rad[i])
+        unit = (wi > 0).astype(np.float32)
+        prep = imager.Prep(uvi, unit, N, cell)
+        ref = imager.dirty_image(v, uvi, unit, N, cell, 0) * imager.b0(prep, imager.weights(prep, 0)) / 2.0
+        err = np.max(np.abs(got[i].cpu().numpy() - ref))
+        log(f"  inst {i} N={N} err/max={err / np.max(np.abs(ref)):.2e}")
+        assert err <= 1e-5 * np.max(np.abs(ref))

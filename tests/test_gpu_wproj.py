@@ -108,3 +108,24 @@ def test_wproj_mixed_sizes_and_uniform_weighting():
         log(f"  inst {i} N={N} mode={mode}: planes {n_planes[i]} / {np_ref}, max|err| {err:.3e}")
         assert n_planes[i] == np_ref
         assert err <= 1e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("chan", [0, 130])
+def test_wproj_c3_channel_at_1024_with_the_arrays_own_w(chan):
+    """A C3 channel at its full size (1024^2) with the MUSER-II-like array's own w coordinates,
+    w_max over the kept visibilities as in the benchmark (60+ planes, supports up to 15 cells)."""
+    log(f"[wproj] C3 channel {chan} at 1024^2 with the array's w")
+    require_gpu()
+    wl = synth.c3_muser2(chans=[chan])
+    wl.w_lambda = synth.c3_w_lambda(chans=[chan])
+    v, uv, w_in = wl.instance(0)
+    N, cell = int(wl.n_img[0]), float(wl.cell_rad[0])
+    keep = imager.Prep(uv, w_in, N, cell).keep
+    w_max = np.array([float(np.abs(wl.w_lambda[keep].astype(np.float64)).max())])
+    b, imgs, b0, n_planes = _gpu(wl, w_max)
+    ref, (dw, np_ref, sup) = wproj.dirty_image_w(v, uv, wl.instance_w(0), w_in, N, cell, 0, w_max[0])
+    err = max_abs(imgs[0].cpu().numpy(), ref)
+    log(f"  planes gpu {n_planes[0]} oracle {np_ref}, largest support {max(sup)} cells, "
+        f"max|err| {err:.3e} of peak {np.abs(ref).max():.3e}")
+    assert n_planes[0] == np_ref and np_ref >= 60
+    assert err <= 1e-5 * np.abs(ref).max()

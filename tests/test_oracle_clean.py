@@ -183,3 +183,30 @@ def test_full_window_equals_no_window():
     a = clean.hogbom(dirty, beam, niter=40)
     b = clean.hogbom(dirty, beam, niter=40, window=(0, 0, N, N))
     assert np.array_equal(a[2], b[2]) and np.array_equal(a[0], b[0])
+
+
+def test_restore_conv_is_the_direct_restore():
+    rng = np.random.default_rng(61)
+    N = 48
+    R = rng.standard_normal((N, N))
+    M = np.zeros((N, N))
+    M.flat[rng.choice(N * N, 9, replace=False)] = rng.standard_normal(9)
+    abc = (0.31, 0.07, 0.22)
+    ref = clean.restore(R, M, abc)
+    assert np.max(np.abs(clean.restore_conv(R, M, abc) - ref)) < 1e-12
+    # a Gaussian this narrow is below 1e-12 of its peak beyond 12 pixels
+    assert np.max(np.abs(clean.restore_conv(R, M, abc, radius=12) - ref)) < 1e-10
+
+
+def test_replay_rejects_picks_below_the_threshold():
+    N = 32
+    yy, xx = np.mgrid[0:2 * N, 0:2 * N]
+    B = np.exp(-((xx - N) ** 2 + (yy - N) ** 2) / 3.0)
+    D = 2.0 * B[N - 10: 2 * N - 10, N - 12: 2 * N - 12]
+    R, M, idx, flux = clean.hogbom(D, B, gain=0.1, niter=30)
+    # the peak falls as 2 (0.9)^k: a threshold between steps 20 and 21 ends a valid run at 21 picks
+    thr = 2.0 * 0.9 ** 20.5
+    ok, bad, _, _ = clean.replay(D, B, idx[:21], flux[:21], threshold=thr)
+    assert ok
+    ok, bad, _, _ = clean.replay(D, B, idx, flux, threshold=thr)
+    assert not ok and bad == 21
