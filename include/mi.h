@@ -112,6 +112,18 @@ typedef struct {
                                   maps (the paper does not window its CLEAN)           */
 } mi_clean_params;
 
+/* Steer CLEAN parameters (the Steer-Dewdney-Ito CLEAN of Sec. 2 and Sec. 4.3; Algorithm 1
+ * runs it with gain 0.1 until the peak reaches the sky level). */
+typedef struct {
+  float gain;                  /* loop gain in (0, 1]: the largest subtracted value is
+                                  gain x peak                                          */
+  float trim;                  /* (0, 1]: pixels with |R| >= trim x peak are components  */
+  const int32_t* ncycle;       /* host, n_inst, iteration cap per instance (>= 0)       */
+  const float* threshold;      /* host, n_inst, stop when the peak <= threshold; or NULL */
+  const float* threshold_dev;  /* device, n_inst, or NULL; overrides `threshold`         */
+  int32_t positive_only;       /* 0: peak and selection on |R|; 1: on R                 */
+} mi_steer_params;
+
 /* Create / destroy a context on HIP device `device`.  The context owns plans,
  * workspaces and constant tables. */
 mi_status mi_ctx_create(mi_ctx** ctx, int device);
@@ -212,6 +224,31 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
                           float* residual_out, double* model_out, int32_t* comp_idx,
                           double* comp_flux, int32_t* n_comp_out, float* restored_out,
                           double* cbeam_out, hipStream_t stream);
+
+/* Steer CLEAN with restore (Sec. 2, Sec. 4.3; Algorithm 1's deconvolver).  Per iteration:
+ *   peak = max |R| (max R with positive_only); stop if peak <= threshold;
+ *   C = R on the pixels with |R| >= trim peak (R >= trim peak), 0 elsewhere (FP64 test);
+ *   D[y][x] = sum_q C[q] beam[y - q_y + N][x - q_x + N]  (linear convolution, FP64 FFTs);
+ *   alpha = gain peak / max |D| (stop if D = 0);  model += alpha C;  R -= alpha D.
+ * So an isolated point is subtracted exactly as a Hogbom step, and a selection covering an
+ * extended source never removes more than gain x peak at any pixel.
+ *   dirty: float32 N*N per instance; beam: float32 (2N)^2 per instance (peak at (N, N));
+ *   N: powers of two in [64, 4096].  Pointers to float images must be 16-byte aligned.
+ *   residual_out: float32 N*N; model_out: double N*N (optional);
+ *   n_cycle_out (optional): int32 [n_inst], iterations done;
+ *   log_out (optional): double [sum ncycle][3] = (peak, alpha, selected pixels) per
+ *     iteration, instances back to back;
+ *   mask_out (optional): uint32 [sum ncycle_i N_i^2 / 32], the selection of each iteration
+ *     as bits (bit b of word w = pixel 32 w + b), instances back to back;
+ *   restored_out (optional): R + model convolved with the clean beam (the Gaussian fitted
+ *     to the beam's main lobe, as in mi_hogbom_clean, over the whole map);
+ *   cbeam_out (optional): double [n_inst][6] as in mi_hogbom_clean.
+ * Every image of the batch advances one iteration per launch sequence (four launches per
+ * iteration, up to the largest ncycle); workspace per N x N image: about 68 N^2 bytes.  */
+mi_status mi_steer_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty, const float* beam,
+                         const mi_steer_params* params, float* residual_out, double* model_out,
+                         int32_t* n_cycle_out, double* log_out, uint32_t* mask_out, float* restored_out,
+                         double* cbeam_out, hipStream_t stream);
 
 /* Adjoint of the imaging operator: FFT, then degrid.
  *   image: float32 N*N per instance.  vis_out: complex, one per input visibility.

@@ -18,7 +18,7 @@ MI_PROF_CLEAN, MI_PROF_GRID, MI_PROF_IFFT = 1, 2, 4
 EXPORTS = ("mi_ctx_create", "mi_ctx_destroy", "mi_last_error", "mi_version", "mi_grid", "mi_ifft2",
            "mi_dirty_image", "mi_dirty_beam", "mi_hogbom_clean", "mi_degrid", "mi_gmm_levels", "mi_disk_offsets", "mi_phase_shift", "mi_profile_begin",
            "mi_profile_end", "mi_dirty_image_w", "mi_profile_begin_kinds", "mi_profile_end_kinds",
-           "mi_predict_transpose")
+           "mi_predict_transpose", "mi_steer_clean")
 
 
 class MiBatch(ctypes.Structure):
@@ -30,6 +30,11 @@ class MiCleanParams(ctypes.Structure):
     _fields_ = [("gain", c_float), ("niter", c_void_p), ("threshold", c_void_p), ("positive_only", c_int32),
                 ("team_size", c_int32), ("threshold_dev", c_void_p),
                 ("window", c_void_p)]
+
+
+class MiSteerParams(ctypes.Structure):
+    _fields_ = [("gain", c_float), ("trim", c_float), ("ncycle", c_void_p), ("threshold", c_void_p),
+                ("threshold_dev", c_void_p), ("positive_only", c_int32)]
 
 
 class MiWprojParams(ctypes.Structure):
@@ -72,6 +77,8 @@ def lib():
     L.mi_dirty_image_w.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, vp, POINTER(MiWprojParams), vp, vp, vp, vp]
     L.mi_degrid.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, c_int, vp, vp]
     L.mi_predict_transpose.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, vp, vp]
+    L.mi_steer_clean.argtypes = [vp, POINTER(MiBatch), vp, vp, POINTER(MiSteerParams), vp, vp, vp, vp, vp, vp, vp,
+                                 vp]
     L.mi_profile_begin_kinds.argtypes = [vp, ctypes.c_uint32]
     L.mi_profile_end_kinds.argtypes = [vp, vp, vp, c_int32, vp]
     for name in EXPORTS:

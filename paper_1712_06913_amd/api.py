@@ -243,6 +243,52 @@ def hogbom_clean(batch: Batch, dirty, beam, niter, gain: float = 0.1, threshold=
     return res
 
 
+def steer_clean(batch: Batch, dirty, beam, ncycle, gain: float = 0.1, trim: float = 0.9, threshold=None,
+                positive_only=False, restore: bool = True, want_model: bool = True, want_log: bool = True,
+                want_masks: bool = False, out=None):
+    """mi_steer_clean; returns a dict of device tensors (reused when `out` is a previous result):
+    residual, model, n_cycle, log ([sum ncycle, 3]: peak, alpha, selected), masks (uint32 bit
+    masks per iteration, when asked), restored, cbeam; `log_off` / `mask_off` index them."""
+    dev = batch.device
+    ncycle = np.ascontiguousarray(ncycle, dtype=np.int32)
+    thr_dev = None
+    if torch.is_tensor(threshold) and threshold.is_cuda:
+        if threshold.dtype != torch.float32 or threshold.numel() != batch.n_inst:
+            raise ValueError("device thresholds must be float32, one per instance")
+        thr_dev, thr = threshold.contiguous(), None
+    else:
+        thr = None if threshold is None else np.ascontiguousarray(threshold, dtype=np.float32)
+    nimg = int(batch.img_off[-1])
+    res = out
+    if res is None:
+        words = ncycle.astype(np.int64) * batch.n_img.astype(np.int64) ** 2 // 32
+        res = {"residual": torch.empty(nimg, dtype=torch.float32, device=dev),
+               "model": torch.empty(nimg, dtype=torch.float64, device=dev) if want_model else None,
+               "n_cycle": torch.zeros(batch.n_inst, dtype=torch.int32, device=dev),
+               "log": torch.zeros(max(1, int(ncycle.sum())) * 3, dtype=torch.float64, device=dev) if want_log else None,
+               "masks": torch.zeros(max(1, int(words.sum())), dtype=torch.int32, device=dev) if want_masks else None,
+               "restored": torch.empty(nimg, dtype=torch.float32, device=dev) if restore else None,
+               "cbeam": torch.zeros(6 * batch.n_inst, dtype=torch.float64, device=dev) if restore else None,
+               "log_off": np.concatenate([[0], np.cumsum(ncycle.astype(np.int64))]),
+               "mask_off": np.concatenate([[0], np.cumsum(words)])}
+    prm = nat.MiSteerParams(float(gain), float(trim), ncycle.ctypes.data, None if thr is None else thr.ctypes.data,
+                            None if thr_dev is None else thr_dev.data_ptr(), 1 if positive_only else 0)
+    nat.check(batch.ctx, nat.lib().mi_steer_clean(
+        batch.ctx, batch.c, _ptr(dirty), _ptr(beam), ctypes.byref(prm), _ptr(res["residual"]), _ptr(res["model"]),
+        _ptr(res["n_cycle"]), _ptr(res["log"]), _ptr(res["masks"]), _ptr(res["restored"]), _ptr(res["cbeam"]),
+        _stream(dev)))
+    return res
+
+
+def steer_masks(res, batch: Batch, i: int, n: int):
+    """Selection masks of instance i's first n iterations as bool [n, N, N] (host)."""
+    N = int(batch.n_img[i])
+    w = N * N // 32
+    words = res["masks"][int(res["mask_off"][i]): int(res["mask_off"][i]) + n * w].cpu().numpy()
+    bits = np.unpackbits(words.view(np.uint8), bitorder="little")
+    return bits.reshape(n, N, N).astype(bool)
+
+
 def degrid(batch: Batch, image, uv, w, adjoint: bool = False, out=None):
     """mi_degrid: prediction P(y) (adjoint=False) or A^T y (adjoint=True), complex64 per visibility."""
     dev = batch.device

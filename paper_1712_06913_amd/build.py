@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmi.so")
 
-SOURCES = ["mi_api.hip", "k_grid.hip", "k_fft.hip", "k_clean.hip", "k_beam.hip", "k_adjoint.hip", "k_gmm.hip", "k_center.hip", "k_wproj.hip",
+SOURCES = ["mi_api.hip", "k_grid.hip", "k_fft.hip", "k_clean.hip", "k_beam.hip", "k_adjoint.hip", "k_gmm.hip", "k_center.hip", "k_wproj.hip", "k_steer.hip",
            "mi_tables.cpp"]
 ARCH = os.environ.get("MI_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]

@@ -1,0 +1,135 @@
+// LDS-resident Stockham FFT primitives shared by the transform kernels (internal header,
+// not part of the ABI).  Everything sits in an unnamed namespace: each kernel source that
+// includes it gets its own inlined copy.
+//
+// A radix-R pass over nl lines of P points in LDS (line stride P, one padding element per
+// 8 against bank conflicts) reads butterfly b's inputs x[b + m P/R] and writes
+// y[(b/L) L R + b%L + q L] after twiddling by w^m, w = exp(s 2 pi i (b%L)/(L R)); twiddles
+// come from the FP64 table exp(+2 pi i t / 8192) and their powers by recurrence.
+#pragma once
+
+#include "mi_internal.h"
+
+namespace mi {
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+// multiply by s*i (s = +1 or -1)
+__device__ __forceinline__ double2 mul_si(double2 a, double s) { return make_double2(-s * a.y, s * a.x); }
+
+template <int R> __device__ __forceinline__ void small_dft(double2* x, double s);
+
+template <> __device__ __forceinline__ void small_dft<2>(double2* x, double) {
+  double2 a = x[0], b = x[1];
+  x[0] = cadd(a, b);
+  x[1] = csub(a, b);
+}
+
+template <> __device__ __forceinline__ void small_dft<4>(double2* x, double s) {
+  double2 t0 = cadd(x[0], x[2]), t1 = csub(x[0], x[2]);
+  double2 t2 = cadd(x[1], x[3]), t3 = mul_si(csub(x[1], x[3]), s);
+  x[0] = cadd(t0, t2);
+  x[2] = csub(t0, t2);
+  x[1] = cadd(t1, t3);
+  x[3] = csub(t1, t3);
+}
+
+template <> __device__ __forceinline__ void small_dft<8>(double2* x, double s) {
+  double2 e[4] = {x[0], x[2], x[4], x[6]};
+  double2 o[4] = {x[1], x[3], x[5], x[7]};
+  small_dft<4>(e, s);
+  small_dft<4>(o, s);
+  const double r = 0.70710678118654752440;
+  // w8^q = exp(s i pi q / 4)
+  double2 o1 = cmul(o[1], make_double2(r, s * r));
+  double2 o2 = mul_si(o[2], s);
+  double2 o3 = cmul(o[3], make_double2(-r, s * r));
+  x[0] = cadd(e[0], o[0]);
+  x[4] = csub(e[0], o[0]);
+  x[1] = cadd(e[1], o1);
+  x[5] = csub(e[1], o1);
+  x[2] = cadd(e[2], o2);
+  x[6] = csub(e[2], o2);
+  x[3] = cadd(e[3], o3);
+  x[7] = csub(e[3], o3);
+}
+
+// LDS index with one padding element per 8: strided butterfly stores of 16-byte elements
+// otherwise land on the same banks.  (A further element per line, against conflicts in
+// the staging and the transposed stores, measured slower overall.)
+__device__ __forceinline__ int pd(int i) { return i + (i >> 3); }
+
+// One Stockham radix-R pass over nl lines of P points held in LDS (line stride P).
+// L = product of the radices already applied.  Butterfly b of a line reads x[b + m P/R]
+// and writes y[(b/L) L R + b%L + q L] after twiddling by w^m, w = exp(s 2 pi i (b%L)/(L R));
+// w comes from the FP64 table and its powers by recurrence.
+template <int R, int ELEMS, int THREADS>
+__device__ __forceinline__ void stockham_pass(double2* buf, int log2P, int log2L, int nl, double s,
+                                              const double2* __restrict__ tw) {
+  constexpr int BPT = (ELEMS / THREADS / R) > 0 ? ELEMS / THREADS / R : 1;
+  constexpr int LOG2R = R == 8 ? 3 : (R == 4 ? 2 : 1);
+  const int log2nb = log2P - LOG2R;
+  const int nb = 1 << log2nb;
+  const int total = nl << log2nb;
+  const int L = 1 << log2L;
+  const int tw_shift = (13 - log2L - LOG2R);   // table length 8192 = 2^13
+  double2 x[BPT][R];
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int b = threadIdx.x + q * THREADS;
+    if (b < total) {
+      const int line = b >> log2nb, bb = b & (nb - 1);
+      const int base = (line << log2P) + bb;
+#pragma unroll
+      for (int m = 0; m < R; ++m) x[q][m] = buf[pd(base + (m << log2nb))];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int b = threadIdx.x + q * THREADS;
+    if (b < total) {
+      const int line = b >> log2nb, bb = b & (nb - 1);
+      const int j = bb & (L - 1), blk = bb >> log2L;
+      if (L > 1) {
+        double2 w1 = tw[j << tw_shift];
+        w1.y *= s;
+        double2 w = w1;
+        x[q][1] = cmul(x[q][1], w);
+#pragma unroll
+        for (int m = 2; m < R; ++m) {
+          w = cmul(w, w1);
+          x[q][m] = cmul(x[q][m], w);
+        }
+      }
+      small_dft<R>(x[q], s);
+      const int base = (line << log2P) + (blk << (log2L + LOG2R)) + j;
+#pragma unroll
+      for (int m = 0; m < R; ++m) buf[pd(base + (m << log2L))] = x[q][m];
+    }
+  }
+  __syncthreads();
+}
+
+// Full length-P FFT (sign s) of nl lines in LDS; nl * P <= ELEMS.
+template <int ELEMS, int THREADS>
+__device__ __forceinline__ void lds_fft(double2* buf, int log2P, int nl, double s, const double2* __restrict__ tw) {
+  int done = 0, rem = log2P;
+  while (rem > 0) {
+    const int r = (rem == 4 || rem == 2) ? 2 : (rem == 1 ? 1 : 3);
+    if (r == 3) stockham_pass<8, ELEMS, THREADS>(buf, log2P, done, nl, s, tw);
+    else if (r == 2) stockham_pass<4, ELEMS, THREADS>(buf, log2P, done, nl, s, tw);
+    else stockham_pass<2, ELEMS, THREADS>(buf, log2P, done, nl, s, tw);
+    done += r;
+    rem -= r;
+  }
+}
+
+__device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
+
+}  // namespace
+}  // namespace mi

@@ -73,6 +73,11 @@ hipError_t launch_phase_shift(const InstDesc*, int, int, float2*, const float2*,
 hipError_t launch_beam_symcheck(const InstDesc*, int, int, const float*, int*, hipStream_t);
 hipError_t launch_degrid(const InstDesc*, int, int, const float2*, const float*, const float*, const double*,
                          const double2*, const Tables&, int, float2*, hipStream_t);
+hipError_t launch_st_rows(int mode, int n_blocks, const SteerArgs& A, hipStream_t st);
+hipError_t launch_st_cols(int mode, int n_blocks, const SteerArgs& A, hipStream_t st);
+hipError_t launch_st_rows_inv(int mode, int n_blocks, const SteerArgs& A, hipStream_t st);
+hipError_t launch_st_init(int n_blocks, const SteerArgs& A, hipStream_t st);
+hipError_t launch_st_update(int n_blocks, const SteerArgs& A, hipStream_t st);
 
 // LDS block (complex doubles) used by the FFT kernels for a transform of length P, and
 // the lines (pass A) / rows (pass B) it holds.
@@ -164,6 +169,26 @@ struct CleanPlan : CacheEntry {
       comp_flux, cbeam, rrad;
 };
 
+// Steer CLEAN: per batch, the work lists of its passes and the workspaces; per parameter
+// set (iteration caps, host thresholds), the per-instance descriptors and control words.
+struct SteerBase {
+  DevBuf rows, rows2, cols, inv, pix;    // FftWork lists: N rows, 2N rows, columns, N rows, pixel blocks
+  int n_rows = 0, n_rows2 = 0, n_cols = 0, n_inv = 0, n_pix = 0;
+  std::vector<int64_t> x_off, s_off;
+  std::vector<int32_t> rb;
+  int64_t total_x = 0, total_s = 0;
+  DevBuf X, S, D, model_ws;
+};
+
+struct SteerPlan : CacheEntry {
+  std::vector<int32_t> ncycle;
+  std::vector<float> thr;
+  bool has_thr = false;
+  int kmax = 0;
+  int64_t total_ctl = 0;
+  DevBuf sti, ctl, cbeam, rrad;
+};
+
 struct Plan : CacheEntry {
   // key
   std::vector<int64_t> off;
@@ -197,6 +222,8 @@ struct Plan : CacheEntry {
     DevBuf planes, rows, winst, screen, dft, tabs, ent, ts, tc;
   };
   std::unique_ptr<WProj> wproj;
+  std::unique_ptr<SteerBase> steer;
+  std::map<uint64_t, std::unique_ptr<SteerPlan>> steers;
   // disk centering: radii (host copy for change detection), 2-D transform work list, buffers
   std::vector<double> radius;
   int corr_elems = 0, corr_nwork = 0;
@@ -1205,6 +1232,175 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
     hipEvent_t pe = prof_start(ctx, MI_PROF_CLEAN, stream);
     HIPCHK(launch_clean(A, C->ppt, C->local != 0, C->n_blocks, C->lds, stream));
     prof_stop(pe, stream);
+  });
+}
+
+mi_status mi_steer_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty, const float* beam,
+                         const mi_steer_params* prm, float* residual_out, double* model_out, int32_t* n_cycle_out,
+                         double* log_out, uint32_t* mask_out, float* restored_out, double* cbeam_out,
+                         hipStream_t stream) {
+  return guard(ctx, [&] {
+    need(dirty, "dirty");
+    need(beam, "beam");
+    need(prm, "params");
+    need(residual_out, "residual_out");
+    need(prm->ncycle, "params->ncycle");
+    if (!(prm->gain > 0.0f && prm->gain <= 1.0f)) fail(MI_ERR_ARG, "gain must be in (0, 1]");
+    if (!(prm->trim > 0.0f && prm->trim <= 1.0f)) fail(MI_ERR_ARG, "trim must be in (0, 1]");
+    for (const void* q : {static_cast<const void*>(dirty), static_cast<const void*>(residual_out),
+                          static_cast<const void*>(restored_out), static_cast<const void*>(model_out)})
+      if (reinterpret_cast<uintptr_t>(q) % 16) fail(MI_ERR_ARG, "image pointers must be 16-byte aligned");
+    HIPCHK(hipSetDevice(ctx->device));
+    Plan* P = get_plan(ctx, batch, stream);
+    const int n = P->n_inst;
+    for (int i = 0; i < n; ++i)
+      if (prm->ncycle[i] < 0) fail(MI_ERR_ARG, "ncycle[%d] < 0", i);
+    if (!P->steer) {                                   // work lists and workspaces of the batch
+      if (capturing(stream)) fail(MI_ERR_UNSUPPORTED, "the first Steer CLEAN call on a batch cannot be captured");
+      auto B = std::make_unique<SteerBase>();
+      std::vector<FftWork> rows, rows2, cols, pix;
+      for (int i = 0; i < n; ++i) {
+        const int N = P->n[i], Pn = 2 * N;
+        const int rb = std::min(8, 2 * 8192 / Pn), ncol = 8192 / Pn;
+        B->rb.push_back(rb);
+        B->x_off.push_back(B->total_x);
+        B->s_off.push_back(B->total_s);
+        B->total_x += 2LL * N * (N + 1);
+        B->total_s += (int64_t)(N + 1) * Pn;
+        for (int y = 0; y < N; y += rb) rows.push_back({i, y});
+        for (int y = 0; y < Pn; y += rb) rows2.push_back({i, y});
+        for (int kx = 0; kx <= N; kx += ncol) cols.push_back({i, kx});
+        for (int p = 0; p < N * N; p += 4096) pix.push_back({i, p});
+      }
+      upload(B->rows, rows);
+      upload(B->rows2, rows2);
+      upload(B->cols, cols);
+      upload(B->pix, pix);
+      B->n_rows = B->n_inv = (int)rows.size();
+      B->n_rows2 = (int)rows2.size();
+      B->n_cols = (int)cols.size();
+      B->n_pix = (int)pix.size();
+      dev_alloc<double2>(B->X, (size_t)B->total_x);
+      dev_alloc<double2>(B->S, (size_t)B->total_s);
+      dev_alloc<float>(B->D, (size_t)P->total_img);
+      P->steer = std::move(B);
+    }
+    SteerBase* B = P->steer.get();
+    // per parameter set: descriptors (offsets, caps, host thresholds) and control words
+    const bool has_thr = prm->threshold != nullptr && prm->threshold_dev == nullptr;
+    uint64_t h = fnv1a(prm->ncycle, sizeof(int32_t) * n);
+    if (has_thr) h = fnv1a(prm->threshold, sizeof(float) * n, h ^ 0x9e3779b97f4a7c15ull);
+    auto it = P->steers.find(h);
+    SteerPlan* S = nullptr;
+    if (it != P->steers.end() && it->second->has_thr == has_thr &&
+        std::equal(it->second->ncycle.begin(), it->second->ncycle.end(), prm->ncycle) &&
+        (!has_thr || std::equal(it->second->thr.begin(), it->second->thr.end(), prm->threshold))) {
+      S = it->second.get();
+      touch(ctx, S, stream);
+    } else {
+      if (it != P->steers.end()) {
+        if (it->second->pinned) fail(MI_ERR_UNSUPPORTED, "Steer plan collision with a plan held by a captured graph");
+        P->steers.erase(it);
+      }
+      make_room(P->steers, 8, stream);
+      auto up = std::make_unique<SteerPlan>();
+      S = up.get();
+      S->ncycle.assign(prm->ncycle, prm->ncycle + n);
+      S->has_thr = has_thr;
+      if (has_thr) S->thr.assign(prm->threshold, prm->threshold + n);
+      std::vector<SteerInst> si(n);
+      int64_t ctl = 0, lg = 0, mk = 0;
+      for (int i = 0; i < n; ++i) {
+        const int N = P->n[i];
+        SteerInst& d = si[i];
+        std::memset(&d, 0, sizeof d);
+        d.x_off = B->x_off[i];
+        d.s_off = B->s_off[i];
+        d.ctl_off = ctl;
+        d.log_off = lg;
+        d.mask_off = mk;
+        d.ncycle = prm->ncycle[i];
+        d.rb = B->rb[i];
+        d.thr = has_thr ? prm->threshold[i] : 0.0f;
+        ctl += 4 + d.ncycle;
+        lg += 3LL * d.ncycle;
+        mk += (int64_t)d.ncycle * N * N / 32;
+        S->kmax = std::max(S->kmax, d.ncycle);
+      }
+      S->total_ctl = ctl;
+      upload(S->sti, si);
+      dev_alloc<unsigned>(S->ctl, (size_t)ctl);
+      dev_alloc<double>(S->cbeam, 6 * (size_t)n);
+      dev_alloc<int>(S->rrad, (size_t)n);
+      touch(ctx, S, stream);
+      P->steers[h] = std::move(up);
+    }
+    int* status = batch->status;
+    if (status) HIPCHK(launch_fill_u32(reinterpret_cast<unsigned*>(status), n, 0u, stream));
+    HIPCHK(launch_fill_u32(static_cast<unsigned*>(S->ctl.p), S->total_ctl, 0u, stream));
+    SteerArgs A{};
+    A.inst = static_cast<const InstDesc*>(P->inst.p);
+    A.sti = static_cast<const SteerInst*>(S->sti.p);
+    A.thr_dev = prm->threshold_dev;
+    A.gain = prm->gain;
+    A.trim = prm->trim;
+    A.posonly = prm->positive_only ? 1 : 0;
+    A.dirty = dirty;
+    A.beam = beam;
+    A.R = residual_out;
+    A.model = model_out ? model_out : dev_alloc<double>(B->model_ws, (size_t)P->total_img);
+    A.D = static_cast<float*>(B->D.p);
+    A.X = static_cast<double2*>(B->X.p);
+    A.S = static_cast<double2*>(B->S.p);
+    A.ctl = static_cast<unsigned*>(S->ctl.p);
+    A.log = log_out;
+    A.mask = mask_out;
+    A.ncyc_out = n_cycle_out;
+    A.restored = restored_out;
+    A.T = ctx->T;
+    const FftWork* w_rows = static_cast<const FftWork*>(B->rows.p);
+    const FftWork* w_rows2 = static_cast<const FftWork*>(B->rows2.p);
+    const FftWork* w_cols = static_cast<const FftWork*>(B->cols.p);
+    const FftWork* w_pix = static_cast<const FftWork*>(B->pix.p);
+    // the beam's spectrum, then R = dirty and the first peaks
+    A.iter = 0;
+    A.work = w_rows2;
+    HIPCHK(launch_st_rows(2, B->n_rows2, A, stream));
+    A.work = w_cols;
+    HIPCHK(launch_st_cols(0, B->n_cols, A, stream));
+    A.work = w_pix;
+    HIPCHK(launch_st_init(B->n_pix, A, stream));
+    A.iter = 1;
+    for (int k = 0; k < S->kmax; ++k) {
+      A.k = k;
+      A.work = w_rows;
+      HIPCHK(launch_st_rows(0, B->n_rows, A, stream));
+      A.work = w_cols;
+      HIPCHK(launch_st_cols(1, B->n_cols, A, stream));
+      A.work = w_rows;
+      HIPCHK(launch_st_rows_inv(0, B->n_inv, A, stream));
+      A.work = w_pix;
+      HIPCHK(launch_st_update(B->n_pix, A, stream));
+    }
+    if (restored_out || cbeam_out) {
+      double* cb = cbeam_out ? cbeam_out : static_cast<double*>(S->cbeam.p);
+      HIPCHK(launch_beamfit(A.inst, n, beam, cb, static_cast<int*>(S->rrad.p), status, stream));
+      if (restored_out) {
+        // the clean beam's spectrum replaces the dirty beam's; restored = R + model (*) Gaussian
+        A.iter = 0;
+        A.cbeam = cb;
+        A.work = w_rows2;
+        HIPCHK(launch_st_rows(3, B->n_rows2, A, stream));
+        A.work = w_cols;
+        HIPCHK(launch_st_cols(0, B->n_cols, A, stream));
+        A.work = w_rows;
+        HIPCHK(launch_st_rows(1, B->n_rows, A, stream));
+        A.work = w_cols;
+        HIPCHK(launch_st_cols(1, B->n_cols, A, stream));
+        A.work = w_rows;
+        HIPCHK(launch_st_rows_inv(1, B->n_inv, A, stream));
+      }
+    }
   });
 }
 

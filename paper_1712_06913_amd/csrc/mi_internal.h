@@ -91,6 +91,46 @@ struct CleanArgs {
   int test_stall;          // failure-path tests: member 0 never publishes, every wait times out
 };
 
+// Steer CLEAN: per-instance layout of the workspaces (built on the host per plan).
+struct SteerInst {
+  int64_t x_off;     // blocked row spectra (complex FP64): 2N blocks of rows x (N+1) columns
+  int64_t s_off;     // spectrum of the beam / clean beam (complex FP64): (N+1) columns x 2N
+  int64_t ctl_off;   // u32 control words: [0], [1] peak keys by iteration parity, [2] max |D| key,
+                     // [3] unused, [4 + k] pixels selected in iteration k
+  int64_t log_off;   // doubles: (peak, alpha, count) per iteration
+  int64_t mask_off;  // u32 words: N^2 / 32 per iteration (selection bit masks)
+  int32_t ncycle;    // iteration cap
+  int32_t rb;        // rows per block of the blocked spectra (power of two)
+  float thr;         // host threshold (device thresholds override it)
+  int32_t pad;
+};
+
+// Arguments of the Steer CLEAN kernels (one struct for all of them; each reads its part).
+struct SteerArgs {
+  const InstDesc* inst;
+  const SteerInst* sti;
+  const FftWork* work;     // this launch's work items
+  const float* thr_dev;    // device thresholds or null
+  float gain, trim;
+  int posonly;
+  int k;                   // iteration of this launch
+  int iter;                // 1: an iteration launch (inactive instances skip it), 0: set-up / restore
+  const float* dirty;
+  const float* beam;
+  const double* cbeam;     // clean-beam Gaussian (a, b, c, ...) per instance
+  float* R;                // residual (the caller's output, updated in place)
+  double* model;
+  float* D;                // convolution of this iteration's components with the beam, N^2
+  double2* X;
+  double2* S;
+  unsigned* ctl;
+  double* log;             // or null
+  unsigned* mask;          // or null
+  int* ncyc_out;           // or null
+  float* restored;
+  Tables T;
+};
+
 // Round half away from zero, written as sign(x) floor(|x| + 1/2) in FP64 (identical
 // arithmetic on every side that needs the same cell decisions).
 __device__ __forceinline__ double rhaz(double x) {

@@ -225,11 +225,12 @@ def test_captured_plans_survive_cache_pressure():
                                      cf[off[i]: off[i] + nc[i]])
         assert ok, f"inst {i}: pick {bad} rejected"
     # a call that would build a plan cannot be recorded into a graph: it fails before any launch
-    o = synth.random_instances(400, [64], m_range=(20, 40))
+    # (a descriptor no other test uses: three instances, 64/128/64, 123 visibilities each)
+    o = synth.random_instances(400, [64, 128, 64], m_range=(123, 123))
     ob = api.Batch.from_workload(o)
     ov, ouv, ow = api.workload_tensors(o)
-    out = torch.empty(64 * 64, dtype=torch.float32, device="cuda")
-    b0 = torch.empty(2, dtype=torch.float64, device="cuda")
+    out = torch.empty(2 * 64 * 64 + 128 * 128, dtype=torch.float32, device="cuda")
+    b0 = torch.empty(6, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with pytest.raises(nat.MiError) as ei:
