@@ -43,6 +43,11 @@ def parse():
     ap.add_argument("--plain-subset", type=int, default=8)
     ap.add_argument("--team-size", type=int, default=0,
                     help="CLEAN workgroups per image (0: the library's policy)")
+    ap.add_argument("--cpu-baseline-full", action="store_true",
+                    help="also time the oracle on 16 C2, 4 C3 and 16 C4 instances (1 core, all cores)")
+    ap.add_argument("--no-parity", action="store_true", help="skip the instance-0 check against the oracle")
+    ap.add_argument("--steer-cycles", type=int, default=40,
+                    help="Steer CLEAN stage: iterations per image (0: skip the stage)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the steps, copy this many MiB device-to-device with a plain kernel "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -105,35 +110,113 @@ def measured_traffic(workload, team_size):
         return None
 
 
-def cpu_baseline(wl, restore_sample=300):
-    """The FP64 oracle on a bounded sample of the workload, single process (numpy, 1 thread):
-    one instance's dirty image and beam, its full CLEAN and the beam fit, and the restore of
-    the first `restore_sample` model pixels.  The oracle's restore adds one full-image
-    Gaussian per model pixel, so its time is scaled by the instance's model-pixel count."""
+def oracle_image(args):
+    """One instance through the FP64 oracle: dirty image and beam, CLEAN, beam fit, restore
+    (the oracle's FFT-convolution form of the restore, equal to its direct sum).  Returns
+    (stage seconds, dirty, beam, residual, model, clean-beam fit)."""
+    from threadpoolctl import threadpool_limits
     from oracle import clean, imager
-    i = 0
+    v, uv, w, N, cell, mode, niter, gain = args
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        dirty = imager.dirty_image(v, uv, w, N, cell, mode)
+        beam = imager.dirty_beam(uv, w, N, cell, mode)
+        t1 = time.perf_counter()
+        R, model, idx, flux = clean.hogbom(dirty, beam, gain=gain, niter=niter)
+        abc = clean.fit_clean_beam(beam)
+        t2 = time.perf_counter()
+        clean.restore_conv(R, model, abc)
+        t3 = time.perf_counter()
+    return (t1 - t0, t2 - t1, t3 - t2), dirty, beam, R, model, abc
+
+
+def _oracle_args(wl, i):
     v, uv, w = wl.instance(i)
-    N, cell, mode, niter = int(wl.n_img[i]), float(wl.cell_rad[i]), int(wl.weight_mode[i]), int(wl.niter[i])
+    return (v, uv, w, int(wl.n_img[i]), float(wl.cell_rad[i]), int(wl.weight_mode[i]), int(wl.niter[i]), wl.gain)
+
+
+def host_cores():
+    """Worker processes for the oracle: the host's cores, at most 16 (one GPU's share of a box)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(wl, n_sample=4):
+    """The FP64 oracle (numpy, one thread per process) on a bounded sample of the workload: the
+    first instance in one process, then the first `n_sample` instances over a process pool of
+    the host's cores.  Returns (the baseline record, instance 0's oracle outputs)."""
+    import concurrent.futures as cf
     t0 = time.perf_counter()
-    dirty = imager.dirty_image(v, uv, w, N, cell, mode)
-    beam = imager.dirty_beam(uv, w, N, cell, mode)
-    t1 = time.perf_counter()
-    R, model, idx, flux = clean.hogbom(dirty, beam, gain=wl.gain, niter=niter)
-    abc = clean.fit_clean_beam(beam)
-    t2 = time.perf_counter()
-    nz = np.flatnonzero(model)
-    k = min(restore_sample, len(nz))
-    sub = np.zeros_like(model)
-    sub.flat[nz[:k]] = model.flat[nz[:k]]
-    clean.restore(R, sub, abc)
-    t3 = time.perf_counter()
-    scale = len(nz) / max(k, 1)
-    per_image = (t2 - t0) + scale * (t3 - t2)
-    return {"value": 1.0 / per_image, "unit": "images/s", "cores": 1, "kind": "oracle",
-            "sample": f"instance 0 of {wl.name} (N={N}, {len(v)} baselines, {niter} iterations): dirty+beam "
-                      f"{t1 - t0:.1f} s, CLEAN + beam fit {t2 - t1:.1f} s, restore of {k} of its {len(nz)} model "
-                      f"pixels {t3 - t2:.1f} s scaled x{scale:.2f} -> {per_image:.1f} s per image; FP64 numpy, "
-                      f"single process, 1 thread"}
+    st, dirty, beam, R, model, abc = oracle_image(_oracle_args(wl, 0))
+    one = time.perf_counter() - t0
+    k = min(n_sample, wl.n_inst)
+    cores = min(host_cores(), k)
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(oracle_image, [_oracle_args(wl, i) for i in range(k)]))
+    many = time.perf_counter() - t0
+    N, niter = int(wl.n_img[0]), int(wl.niter[0])
+    rec = {"value": k / many, "unit": "images/s", "cores": cores, "kind": "oracle",
+           "single_core_images_per_s": 1.0 / one,
+           "sample": f"first {k} instances of {wl.name} (N={N}, {niter} iterations each) over {cores} processes, "
+                     f"one thread each: {many:.1f} s; instance 0 alone in one process: dirty+beam {st[0]:.1f} s, "
+                     f"CLEAN + beam fit {st[1]:.1f} s, restore {st[2]:.1f} s; FP64 numpy"}
+    return rec, (dirty, beam, R, model, abc)
+
+
+def cpu_baseline_full():
+    """Oracle timing on the subsets the measurement plan names (C2: 16, C3: 4, C4: 16 instances),
+    one process and then all host cores, extrapolated linearly to the full workloads (and
+    labelled so).  Several minutes of host time: run with --cpu-baseline-full."""
+    import concurrent.futures as cf
+    from paper_1712_06913_amd import synth
+    out = {}
+    for name, wl, k in (("c2", synth.c2_muser1_batch(), 16), ("c3", synth.c3_muser2(), 4), ("c4", synth.c4_uneven(), 16)):
+        jobs = [_oracle_args(wl, i) for i in range(k)]
+        t0 = time.perf_counter()
+        for a in jobs:
+            oracle_image(a)
+        t1 = time.perf_counter() - t0
+        cores = min(host_cores(), k)
+        t0 = time.perf_counter()
+        with cf.ProcessPoolExecutor(max_workers=cores) as ex:
+            list(ex.map(oracle_image, jobs))
+        tn = time.perf_counter() - t0
+        out[name] = {"instances_timed": k, "of": wl.n_inst, "one_core_s": t1, "one_core_images_per_s": k / t1,
+                     "cores": cores, "all_cores_s": tn, "all_cores_images_per_s": k / tn,
+                     "full_workload_one_core_s_extrapolated": t1 * wl.n_inst / k,
+                     "full_workload_all_cores_s_extrapolated": tn * wl.n_inst / k}
+        log(f"oracle {name}: {k} instances, 1 core {t1:.1f} s, {cores} cores {tn:.1f} s")
+    return out
+
+
+def parity_instance0(ref, dirty, beam, res, b, gain):
+    """The GPU's instance 0 against the oracle run the CPU baseline made of it: the maps
+    within 1e-4 of the peak, every CLEAN pick accepted by the oracle's replay on the GPU's
+    maps, residual (1e-4), model (1e-5) and restored (1e-4) against the replay."""
+    from oracle import clean
+    o_dirty, o_beam = ref[0], ref[1]
+    N = o_dirty.shape[0]
+    D = b.split(dirty)[0].cpu().numpy().astype(np.float64)
+    B = b.split(beam, beam=True)[0].cpu().numpy().astype(np.float64)
+    peak = float(np.max(np.abs(o_dirty)))
+    n = int(res["n_comp"][0])
+    off = res["comp_off"]
+    ok, bad, R, M = clean.replay(D, B, res["comp_idx"][off[0]: off[0] + n].cpu().numpy(),
+                                 res["comp_flux"][off[0]: off[0] + n].cpu().numpy(), gain=gain)
+    rest = clean.restore_conv(R, M, clean.fit_clean_beam(B))
+    e = {"dirty": float(np.max(np.abs(D - o_dirty))) / peak,
+         "beam": float(np.max(np.abs(B - o_beam))),
+         "residual": float(np.max(np.abs(b.split(res["residual"])[0].cpu().numpy() - R))) / peak,
+         "model": float(np.max(np.abs(b.split(res["model"])[0].cpu().numpy() - M))) / peak,
+         "restored": float(np.max(np.abs(b.split(res["restored"])[0].cpu().numpy() - rest))) / peak}
+    passed = bool(ok and e["dirty"] <= 1e-4 and e["beam"] <= 1e-4 and e["residual"] <= 1e-4 and e["model"] <= 1e-5
+                  and e["restored"] <= 1e-4)
+    return {"instance": 0, "components": n, "replay_accepts_every_pick": bool(ok), "first_rejected": int(bad),
+            "max_err_over_peak": e, "pass": passed}
 
 
 def main():
@@ -145,14 +228,14 @@ def main():
     log(f"generating workload {args.workload}")
     wl = make_workload(args.workload)
     log(f"workload {wl.name}: {wl.n_inst} instances, {int(wl.vis_offset[-1])} visibilities")
-    cpu = None
+    cpu, oracle0, cpu_full = None, None, None
     if not args.no_cpu_baseline and not args.only_steps:
         # host-only work, done before anything touches the GPU
         log("timing the CPU oracle baseline")
-        from threadpoolctl import threadpool_limits
-        with threadpool_limits(1):
-            cpu = cpu_baseline(wl)
-        log(f"CPU oracle: {cpu['value']:.4f} images/s")
+        cpu, oracle0 = cpu_baseline(wl)
+        log(f"CPU oracle: {cpu['value']:.4f} images/s on {cpu['cores']} cores")
+        if args.cpu_baseline_full:
+            cpu_full = cpu_baseline_full()
 
     import torch
     from paper_1712_06913_amd import _native as nat, api
@@ -383,9 +466,59 @@ def main():
                         "batched_images_per_s_same_subset": k / tb, "batched_over_plain_same_subset": tp / tb,
                         "full_batch_over_plain": out["value"] / (k / tp)}
 
+    # the same step captured once into a HIP graph and replayed (one launch sequence per stage)
+    from paper_1712_06913_amd import pipeline
+    pl = pipeline.ImagingPipeline(wl, dev, team_size=args.team_size)
+    pl.capture()
+    torch.cuda.synchronize()
+    gsteps = max(1, min(args.steps, 3))
+    t0 = time.perf_counter()
+    for _ in range(gsteps):
+        pl.replay()
+    torch.cuda.synchronize()
+    gms = (time.perf_counter() - t0) * 1e3 / gsteps
+    out["graph_replay"] = {"steps": gsteps, "ms_per_step": gms, "images_per_s": n_inst / (gms * 1e-3),
+                           "components_total": int(pl.res["n_comp"].sum())}
+    del pl
+    log("graph-replayed steps done")
+
+    # Steer CLEAN (the paper's deconvolver) on the same dirty maps and beams
+    if args.steer_cycles > 0:
+        nc = np.full(n_inst, args.steer_cycles, np.int32)
+        sres = api.steer_clean(b, dirty, beam, nc, gain=wl.gain, restore=True)
+        torch.cuda.synchronize()
+        ge[0].record(stream)
+        sres = api.steer_clean(b, dirty, beam, nc, gain=wl.gain, restore=True, out=sres)
+        ge[1].record(stream)
+        torch.cuda.synchronize()
+        sms = ge[0].elapsed_time(ge[1])
+        cyc = sres["n_cycle"].cpu().numpy().astype(np.float64)
+        # algorithmic bytes of this design (FP64 spectra): per iteration the residual read
+        # twice and written once, D written and read, the N (N+1) complex row spectra written
+        # and read twice each, and the 2N (N+1) complex beam spectrum read; once per call the
+        # beam's spectrum, the initial copy and the restore through the clean beam's spectrum
+        Nf = b.n_img.astype(np.float64)
+        H = Nf * (Nf + 1) * 16.0
+        per_it = 20.0 * Nf ** 2 + 6.0 * H
+        once = (16.0 * Nf ** 2 + 6.0 * H) + 16.0 * Nf ** 2 + (12.0 * H + 16.0 * Nf ** 2)
+        st_bytes = float(np.sum(per_it * cyc + once))
+        st_ach = st_bytes / (sms * 1e-3) / 1e9
+        out["steer_clean"] = {"ms": sms, "images_per_s": n_inst / (sms * 1e-3), "cycles_cap": args.steer_cycles,
+                              "cycles_total": int(cyc.sum()), "ms_per_cycle_batch": sms / max(1, int(cyc.max())),
+                              "trim": 0.9, "restore": True, "algorithmic_bytes": st_bytes, "achieved_GBps": st_ach,
+                              "frac_of_hbm_peak": st_ach / HBM_PEAK_GBS}
+        del sres
+        log("Steer CLEAN stage done")
+
+    if oracle0 is not None and not args.no_parity:
+        out["parity"] = parity_instance0(oracle0, dirty, beam, res, b, wl.gain)
+        log(f"instance-0 parity: {out['parity']}")
     if cpu is not None:
         out["cpu_baseline"] = cpu
+    if cpu_full is not None:
+        out["cpu_baseline_subsets"] = cpu_full
     print(json.dumps(out), flush=True)
+    api.close()
 
 
 if __name__ == "__main__":
