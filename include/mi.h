@@ -225,6 +225,26 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
                           double* comp_flux, int32_t* n_comp_out, float* restored_out,
                           double* cbeam_out, hipStream_t stream);
 
+/* Hogbom CLEAN that allocates nothing, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid it).  Same
+ * arguments and results as mi_hogbom_clean; every table it needs (instance descriptors,
+ * team schedule, exchange slots, symmetry flags, clean-beam parameters and, when restoring
+ * without component outputs, the component lists) lives in one fixed device array of
+ * 8 MiB per GPU, held until the process ends and reached through the address the library
+ * takes once per device when a context is created.  The schedule is passed to a set-up
+ * kernel by value, so the call also makes no host-to-device copy and never synchronises.
+ * Limits (MI_ERR_UNSUPPORTED beyond them, before any launch): one image size per batch,
+ * at most 64 instances, no peak-search windows, and the tables within 8 MiB (component
+ * lists take 12 bytes per iteration cap when restoring without component outputs).
+ * Every call on one GPU shares that GPU's array and the array keeps the previous call's
+ * contents (the call clears what must start at zero): calls that overlap on one GPU, on
+ * different streams or from different threads, race and must be serialised by the caller. */
+mi_status mi_hogbom_clean_noalloc(mi_ctx* ctx, const mi_batch* batch, const float* dirty,
+                                  const float* beam, const mi_clean_params* params,
+                                  float* residual_out, double* model_out, int32_t* comp_idx,
+                                  double* comp_flux, int32_t* n_comp_out, float* restored_out,
+                                  double* cbeam_out, hipStream_t stream);
+
 /* Steer CLEAN with restore (Sec. 2, Sec. 4.3; Algorithm 1's deconvolver).  Per iteration:
  *   peak = max |R| (max R with positive_only); stop if peak <= threshold;
  *   C = R on the pixels with |R| >= trim peak (R >= trim peak), 0 elsewhere (FP64 test);

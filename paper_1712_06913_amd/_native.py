@@ -18,7 +18,7 @@ MI_PROF_CLEAN, MI_PROF_GRID, MI_PROF_IFFT = 1, 2, 4
 EXPORTS = ("mi_ctx_create", "mi_ctx_destroy", "mi_last_error", "mi_version", "mi_grid", "mi_ifft2",
            "mi_dirty_image", "mi_dirty_beam", "mi_hogbom_clean", "mi_degrid", "mi_gmm_levels", "mi_disk_offsets", "mi_phase_shift", "mi_profile_begin",
            "mi_profile_end", "mi_dirty_image_w", "mi_profile_begin_kinds", "mi_profile_end_kinds",
-           "mi_predict_transpose", "mi_steer_clean")
+           "mi_predict_transpose", "mi_steer_clean", "mi_hogbom_clean_noalloc")
 
 
 class MiBatch(ctypes.Structure):
@@ -74,6 +74,7 @@ def lib():
     L.mi_dirty_beam.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, vp]
     L.mi_hogbom_clean.argtypes = [vp, POINTER(MiBatch), vp, vp, POINTER(MiCleanParams), vp, vp, vp, vp, vp, vp,
                                   vp, vp]
+    L.mi_hogbom_clean_noalloc.argtypes = L.mi_hogbom_clean.argtypes
     L.mi_dirty_image_w.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, vp, POINTER(MiWprojParams), vp, vp, vp, vp]
     L.mi_degrid.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, c_int, vp, vp]
     L.mi_predict_transpose.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, vp, vp]

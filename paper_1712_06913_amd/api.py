@@ -201,12 +201,14 @@ def ifft2(data: torch.Tensor, n, offs, device: int = 0):
 
 def hogbom_clean(batch: Batch, dirty, beam, niter, gain: float = 0.1, threshold=None, positive_only=False,
                  restore: bool = True, want_model: bool = True, want_components: bool = True, team_size: int = 0,
-                 out=None, window=None):
+                 out=None, window=None, no_alloc: bool = False):
     """mi_hogbom_clean; returns a dict of device tensors (reused when `out` is a previous result).
 
     `threshold`: None, a host array (one per instance), or a float32 device tensor (read on
     the device, e.g. the mu_a of gmm_levels).  `window`: None (whole maps) or an
-    [n_inst, 4] array of peak-search boxes (x0, y0, x1, y1), half-open."""
+    [n_inst, 4] array of peak-search boxes (x0, y0, x1, y1), half-open.  `no_alloc`: call
+    mi_hogbom_clean_noalloc, which works in the library's fixed device scratch array (one
+    image size per batch, at most 64 instances, no windows)."""
     dev = batch.device
     niter = np.ascontiguousarray(niter, dtype=np.int32)
     thr_dev = None
@@ -236,7 +238,8 @@ def hogbom_clean(batch: Batch, dirty, beam, niter, gain: float = 0.1, threshold=
                             1 if positive_only else 0, int(team_size),
                             None if thr_dev is None else thr_dev.data_ptr(),
                             None if win is None else win.ctypes.data)
-    nat.check(batch.ctx, nat.lib().mi_hogbom_clean(
+    fn = nat.lib().mi_hogbom_clean_noalloc if no_alloc else nat.lib().mi_hogbom_clean
+    nat.check(batch.ctx, fn(
         batch.ctx, batch.c, _ptr(dirty), _ptr(beam), ctypes.byref(prm), _ptr(res["residual"]), _ptr(res["model"]),
         _ptr(res["comp_idx"]), _ptr(res["comp_flux"]), _ptr(res["n_comp"]), _ptr(res["restored"]),
         _ptr(res["cbeam"]), _stream(dev)))

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -250,6 +251,7 @@ struct mi_ctx {
   std::map<uint64_t, std::unique_ptr<mi::Plan>> plans;
   std::map<uint64_t, std::unique_ptr<mi::IfftPlan>> ifft_plans;
   mi::DevBuf ifft_scratch;
+  unsigned char* noalloc_scratch = nullptr;   // this device's copy of the static CLEAN scratch
   int fail_inst = -1;
   int clean_stall = 0;   // failure-path tests (MI_TEST_CLEAN_STALL): CLEAN team waits give up
   int n_cu = 256;
@@ -700,6 +702,86 @@ void need(const void* p, const char* name) {
 }  // namespace
 }  // namespace mi
 
+namespace mi {
+namespace {
+
+// ---- CLEAN without allocation (mi_hogbom_clean_noalloc) --------------------------------
+// A file-scope device array holds everything the CLEAN kernels need beyond the caller's
+// inputs and outputs: instance descriptors, team tables, exchange slots, symmetry flags,
+// the clean-beam parameters and, when asked to restore without component outputs, the
+// component lists.  Each device holds its own copy; host code reaches it only through the
+// address hipGetSymbolAddress returns for the device (kept per device at context creation).
+constexpr int NA_MAX_INST = 64;
+constexpr size_t NA_SCRATCH_BYTES = 8u << 20;
+constexpr int NA_MAX_DEVICES = 64;
+__device__ __align__(256) unsigned char scratch[NA_SCRATCH_BYTES];
+std::atomic<unsigned char*> g_noalloc_ptr[NA_MAX_DEVICES];
+
+// Everything the set-up kernel writes, passed by value (so the call needs no host-to-device
+// copy of its own), with the byte offsets of each table in the scratch array.
+struct NaSetup {
+  int n, N, log2N, G, T, local, n_blocks, has_thr;
+  int32_t niter[NA_MAX_INST];
+  float thr[NA_MAX_INST];
+  int16_t team_off[NA_MAX_INST + 1];
+  int16_t team_imgs[NA_MAX_INST];
+  int64_t o_inst, o_team_off, o_team_imgs, o_blk, o_team_G, o_team_slot, o_niter, o_thr, o_comp_off, o_slots,
+      o_asym, o_rrad, o_cbeam, o_cidx, o_cflx;
+  int n_slots;
+  int32_t* status;
+};
+
+// Writes the tables and clears what must start at zero (exchange slots, symmetry flags,
+// status): the array keeps whatever the previous call on this device left in it.
+__global__ void __launch_bounds__(256) k_noalloc_setup(unsigned char* base, NaSetup S) {
+  const int tid = threadIdx.x;
+  InstDesc* inst = reinterpret_cast<InstDesc*>(base + S.o_inst);
+  const int64_t n2 = (int64_t)S.N * S.N;
+  for (int i = tid; i < S.n; i += 256) {
+    InstDesc d{};
+    d.img_off = i * n2;
+    d.beam_off = 4 * i * n2;
+    d.N = S.N;
+    d.log2N = S.log2N;
+    inst[i] = d;
+    reinterpret_cast<int*>(base + S.o_team_imgs)[i] = S.team_imgs[i];
+    reinterpret_cast<int*>(base + S.o_niter)[i] = S.niter[i];
+    reinterpret_cast<float*>(base + S.o_thr)[i] = S.has_thr ? S.thr[i] : 0.0f;
+    reinterpret_cast<int*>(base + S.o_asym)[i] = 0;
+    if (S.status) S.status[i] = 0;
+  }
+  for (int t = tid; t <= S.T; t += 256) reinterpret_cast<int*>(base + S.o_team_off)[t] = S.team_off[t];
+  for (int t = tid; t < S.T; t += 256) {
+    reinterpret_cast<int*>(base + S.o_team_G)[t] = S.G;
+    reinterpret_cast<int64_t*>(base + S.o_team_slot)[t] = 2LL * S.G * t;
+  }
+  // block roles: teams of up to 32 dealt round-robin over the 8 XCDs (block b runs on XCD
+  // b % 8), members of a team in consecutive rows of its XCD; larger teams in order
+  int2* blk = reinterpret_cast<int2*>(base + S.o_blk);
+  for (int b = tid; b < S.n_blocks; b += 256) {
+    int team, member;
+    if (S.local) {
+      const int x = b & 7, r = b >> 3;
+      team = (r / S.G) * 8 + x;
+      member = r % S.G;
+    } else {
+      team = b / S.G;
+      member = b % S.G;
+    }
+    blk[b] = team < S.T ? make_int2(team, member) : make_int2(-1, 0);
+  }
+  unsigned long long* slots = reinterpret_cast<unsigned long long*>(base + S.o_slots);
+  for (int q = tid; q < S.n_slots; q += 256) slots[q] = 0ull;
+  if (tid == 0) {
+    int64_t* coff = reinterpret_cast<int64_t*>(base + S.o_comp_off);
+    int64_t acc = 0;
+    for (int i = 0; i < S.n; ++i) { coff[i] = acc; acc += S.niter[i]; }
+  }
+}
+
+}  // namespace
+}  // namespace mi
+
 using namespace mi;
 
 extern "C" {
@@ -726,6 +808,17 @@ mi_status mi_ctx_create(mi_ctx** out, int device) {
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, device));
     ctx->n_cu = prop.multiProcessorCount;
+    if (device < NA_MAX_DEVICES) {
+      // the device's copy of the no-allocation CLEAN scratch array (device current)
+      unsigned char* sp = g_noalloc_ptr[device].load();
+      if (!sp) {
+        void* a = nullptr;
+        HIPCHK(hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)));
+        sp = static_cast<unsigned char*>(a);
+        g_noalloc_ptr[device].store(sp);
+      }
+      ctx->noalloc_scratch = sp;
+    }
     const char* fi = std::getenv("MI_TEST_FAIL_INSTANCE");
     ctx->fail_inst = fi ? std::atoi(fi) : -1;
     const char* cs = std::getenv("MI_TEST_CLEAN_STALL");
@@ -1232,6 +1325,162 @@ mi_status mi_hogbom_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty
     hipEvent_t pe = prof_start(ctx, MI_PROF_CLEAN, stream);
     HIPCHK(launch_clean(A, C->ppt, C->local != 0, C->n_blocks, C->lds, stream));
     prof_stop(pe, stream);
+  });
+}
+
+mi_status mi_hogbom_clean_noalloc(mi_ctx* ctx, const mi_batch* batch, const float* dirty, const float* beam,
+                                  const mi_clean_params* prm, float* residual_out, double* model_out,
+                                  int32_t* comp_idx, double* comp_flux, int32_t* n_comp_out, float* restored_out,
+                                  double* cbeam_out, hipStream_t stream) {
+  return guard(ctx, [&] {
+    need(dirty, "dirty");
+    need(beam, "beam");
+    need(prm, "params");
+    need(residual_out, "residual_out");
+    need(prm->niter, "params->niter");
+    if ((comp_idx == nullptr) != (comp_flux == nullptr)) fail(MI_ERR_ARG, "comp_idx and comp_flux: both or neither");
+    if (!(prm->gain > 0.0f && prm->gain <= 1.0f)) fail(MI_ERR_ARG, "gain must be in (0, 1]");
+    if (prm->window) fail(MI_ERR_UNSUPPORTED, "the no-allocation CLEAN takes no peak-search windows");
+    check_batch(batch);
+    const int n = batch->n_inst;
+    if (n > NA_MAX_INST) fail(MI_ERR_UNSUPPORTED, "the no-allocation CLEAN takes at most %d instances (got %d)",
+                              NA_MAX_INST, n);
+    const int N = batch->n_img[0];
+    for (int i = 0; i < n; ++i) {
+      if (batch->n_img[i] != N) fail(MI_ERR_UNSUPPORTED, "the no-allocation CLEAN needs one image size per batch");
+      if (prm->niter[i] < 0) fail(MI_ERR_ARG, "niter[%d] < 0", i);
+    }
+    const int req = prm->team_size;
+    if (req != 0 && (!is_pow2(req) || req > 256)) fail(MI_ERR_ARG, "team_size must be 0 or a power of two <= 256");
+    if (!ctx->noalloc_scratch) fail(MI_ERR_UNSUPPORTED, "no scratch array for device %d", ctx->device);
+    HIPCHK(hipSetDevice(ctx->device));
+    // team shape: the allocating entry point's policy for a batch of one image size
+    const int g_min = std::max(1, (N * N) / 65536), g_cap = std::min(256, N);
+    if (g_min > g_cap) fail(MI_ERR_UNSUPPORTED, "CLEAN team too large for N = %d", N);
+    int G = g_min;
+    if (req) {
+      G = 1;
+      while (G * 2 <= req) G *= 2;
+      G = std::min(std::max(G, g_min), g_cap);
+    } else {
+      while (G * 2 <= std::min(32, g_cap) && G * 2 * n <= 256) G *= 2;
+    }
+    int ppt = 4;
+    while ((int64_t)ppt * 1024 * G < (int64_t)N * N) ppt *= 2;
+    const bool local = G <= 32;
+    const int sub_px = (int)std::min<int64_t>((int64_t)N * N / G, CLEAN_RESTORE_SUB_PX);
+    const size_t lds = (size_t)sub_px * sizeof(float);
+    int per_cu = 0;
+    HIPCHK(clean_max_blocks_per_cu(ppt, local, false, lds, &per_cu));
+    int cap = per_cu * ctx->n_cu;
+    if (local) cap -= cap % 8;
+    // teams of up to 32 are dealt over the 8 XCDs a row of teams at a time
+    const int t_max = local ? 8 * ((cap / G) / 8) : cap / G;
+    if (t_max < 1) fail(MI_ERR_UNSUPPORTED, "CLEAN teams of %d workgroups do not fit the device", G);
+    const int T = std::min(n, t_max);
+    // images to teams: longest first, each to the least-loaded team (fixed-size host arrays)
+    NaSetup S;
+    std::memset(&S, 0, sizeof S);
+    S.n = n;
+    S.N = N;
+    S.log2N = ilog2i(N);
+    S.G = G;
+    S.T = T;
+    S.local = local ? 1 : 0;
+    S.n_blocks = local ? 8 * ((T + 7) / 8) * G : T * G;
+    S.has_thr = prm->threshold != nullptr && prm->threshold_dev == nullptr;
+    S.status = batch->status;
+    int order[NA_MAX_INST], team_of[NA_MAX_INST], fill[NA_MAX_INST + 1];
+    double load[NA_MAX_INST];
+    for (int i = 0; i < n; ++i) {
+      order[i] = i;
+      S.niter[i] = prm->niter[i];
+      S.thr[i] = S.has_thr ? prm->threshold[i] : 0.0f;
+    }
+    for (int k = 1; k < n; ++k)               // stable insertion sort, longest first
+      for (int j = k; j > 0 && prm->niter[order[j - 1]] < prm->niter[order[j]]; --j) std::swap(order[j - 1], order[j]);
+    for (int t = 0; t < T; ++t) load[t] = 0.0;
+    for (int k = 0; k < n; ++k) {
+      int t = 0;
+      for (int u = 1; u < T; ++u)
+        if (load[u] < load[t]) t = u;
+      team_of[order[k]] = t;
+      load[t] += (double)prm->niter[order[k]] + 1.0;
+    }
+    for (int t = 0; t <= T; ++t) fill[t] = 0;
+    for (int i = 0; i < n; ++i) ++fill[team_of[i] + 1];
+    for (int t = 0; t < T; ++t) fill[t + 1] += fill[t];
+    for (int t = 0; t <= T; ++t) S.team_off[t] = (int16_t)fill[t];
+    for (int k = 0; k < n; ++k) {             // keep the LPT order within each team
+      const int i = order[k];
+      S.team_imgs[fill[team_of[i]]++] = (int16_t)i;
+    }
+    int64_t total_comp = 0;
+    for (int i = 0; i < n; ++i) total_comp += prm->niter[i];
+    const bool restore = restored_out != nullptr;
+    const bool own_comp = restore && comp_idx == nullptr;
+    // scratch layout (256-byte aligned pieces)
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) { const int64_t o = off; off += (bytes + 255) / 256 * 256; return o; };
+    S.o_inst = take((int64_t)sizeof(InstDesc) * n);
+    S.o_team_off = take(4LL * (T + 1));
+    S.o_team_imgs = take(4LL * n);
+    S.o_blk = take(8LL * S.n_blocks);
+    S.o_team_G = take(4LL * T);
+    S.o_team_slot = take(8LL * T);
+    S.o_niter = take(4LL * n);
+    S.o_thr = take(4LL * n);
+    S.o_comp_off = take(8LL * n);
+    S.n_slots = 2 * G * T;
+    S.o_slots = take(8LL * S.n_slots);
+    S.o_asym = take(4LL * n);
+    S.o_rrad = take(4LL * n);
+    S.o_cbeam = take(48LL * n);
+    S.o_cidx = own_comp ? take(4 * std::max<int64_t>(total_comp, 1)) : 0;
+    S.o_cflx = own_comp ? take(8 * std::max<int64_t>(total_comp, 1)) : 0;
+    if ((size_t)off > NA_SCRATCH_BYTES)
+      fail(MI_ERR_UNSUPPORTED, "the call needs %lld bytes of scratch, more than the %zu the no-allocation CLEAN has "
+           "(restore with component outputs of your own, or fewer iterations)", (long long)off, NA_SCRATCH_BYTES);
+    unsigned char* base = ctx->noalloc_scratch;
+    hipLaunchKernelGGL(k_noalloc_setup, dim3(1), dim3(256), 0, stream, base, S);
+    HIPCHK(hipGetLastError());
+    const InstDesc* inst = reinterpret_cast<const InstDesc*>(base + S.o_inst);
+    int* rrad = reinterpret_cast<int*>(base + S.o_rrad);
+    double* cbeam = cbeam_out ? cbeam_out : reinterpret_cast<double*>(base + S.o_cbeam);
+    if (restore || cbeam_out) HIPCHK(launch_beamfit(inst, n, beam, cbeam, rrad, batch->status, stream));
+    int* asym = reinterpret_cast<int*>(base + S.o_asym);
+    HIPCHK(launch_beam_symcheck(inst, n, N, beam, asym, stream));
+    CleanArgs A{};
+    A.inst = inst;
+    A.team_off = reinterpret_cast<const int*>(base + S.o_team_off);
+    A.team_imgs = reinterpret_cast<const int*>(base + S.o_team_imgs);
+    A.blk = reinterpret_cast<const int2*>(base + S.o_blk);
+    A.team_G = reinterpret_cast<const int*>(base + S.o_team_G);
+    A.team_slot = reinterpret_cast<const int64_t*>(base + S.o_team_slot);
+    A.sub_px = sub_px;
+    A.dirty = dirty;
+    A.beam = beam;
+    A.niter = reinterpret_cast<const int*>(base + S.o_niter);
+    A.thr = prm->threshold_dev ? prm->threshold_dev : (S.has_thr ? reinterpret_cast<const float*>(base + S.o_thr)
+                                                                  : nullptr);
+    A.win = nullptr;
+    A.gain = prm->gain;
+    A.posonly = prm->positive_only ? 1 : 0;
+    A.cbeam = restore ? cbeam : nullptr;
+    A.rrad = rrad;
+    A.resid = residual_out;
+    A.model = model_out;
+    A.comp_off = reinterpret_cast<const int64_t*>(base + S.o_comp_off);
+    A.comp_idx = own_comp ? reinterpret_cast<int*>(base + S.o_cidx) : comp_idx;
+    A.comp_flux = own_comp ? reinterpret_cast<double*>(base + S.o_cflx) : comp_flux;
+    A.ncomp = n_comp_out;
+    A.restored = restored_out;
+    A.slots = reinterpret_cast<unsigned long long*>(base + S.o_slots);
+    A.asym = asym;
+    A.status = batch->status;
+    A.poll_limit = ctx->clean_stall ? 256u : 0u;
+    A.test_stall = ctx->clean_stall;
+    HIPCHK(launch_clean(A, ppt, local, S.n_blocks, lds, stream));
   });
 }
 
