@@ -144,15 +144,16 @@ def host_cores():
     return max(1, min(16, n))
 
 
-def cpu_baseline(wl, n_sample=4):
+def cpu_baseline(wl, n_sample=None):
     """The FP64 oracle (numpy, one thread per process) on a bounded sample of the workload: the
-    first instance in one process, then the first `n_sample` instances over a process pool of
-    the host's cores.  Returns (the baseline record, instance 0's oracle outputs)."""
+    first instance in one process, then the first `n_sample` instances (default: one per host
+    core) over a process pool of the host's cores.  Returns (the baseline record, instance
+    0's oracle outputs)."""
     import concurrent.futures as cf
     t0 = time.perf_counter()
     st, dirty, beam, R, model, abc = oracle_image(_oracle_args(wl, 0))
     one = time.perf_counter() - t0
-    k = min(n_sample, wl.n_inst)
+    k = min(host_cores() if n_sample is None else n_sample, wl.n_inst)
     cores = min(host_cores(), k)
     t0 = time.perf_counter()
     with cf.ProcessPoolExecutor(max_workers=cores) as ex:
@@ -284,7 +285,7 @@ def main():
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     # HIP events around each Hogbom, gridder and inverse-transform launch
-    api.profile_begin(dev.index or 0, kinds=nat.MI_PROF_CLEAN | nat.MI_PROF_GRID | nat.MI_PROF_IFFT)
+    api.profile_begin(dev.index or 0, kinds=nat.MI_PROF_CLEAN | nat.MI_PROF_GRID | nat.MI_PROF_IFFT | nat.MI_PROF_GRID_FFT)
     t0 = time.perf_counter()
     for k in range(args.steps):
         res = step(evs[k])
@@ -293,6 +294,7 @@ def main():
     kernel_times = [t for t, k in zip(prof_ms, prof_kind) if k == nat.MI_PROF_CLEAN]
     grid_k_ms = sum(t for t, k in zip(prof_ms, prof_kind) if k == nat.MI_PROF_GRID) / args.steps
     ifft_k_ms = sum(t for t, k in zip(prof_ms, prof_kind) if k == nat.MI_PROF_IFFT) / args.steps
+    fused_k_ms = sum(t for t, k in zip(prof_ms, prof_kind) if k == nat.MI_PROF_GRID_FFT) / args.steps
     log(f"{args.steps} timed steps done")
     wall = time.perf_counter() - t0
     ms_step = wall * 1e3 / args.steps
@@ -379,29 +381,41 @@ def main():
             "traffic_unit": "HBM-side bytes per launch (L2 read and write requests by size)",
             "traffic_over_algorithmic": (traffic / clean_bytes) if traffic else None}
 
-    # gridding and inverse transforms of the step, timed by the same events: algorithmic
-    # bytes of this design per step (FP64 complex dirty half grid N/2 x N, FP64 real beam
-    # half grid N x 2N, float32 maps; the gridders also read 24 B (dirty) and 16 B (beam)
-    # per visibility; the transform's two passes move each half grid in and out of HBM)
+    # gridding and inverse transforms of the step, timed by the same events.  With the fused
+    # gridding + first pass (every size here), the dirty image moves per instance: 24 B read
+    # per visibility, the FP64 complex half grid (N/2 x N) written once after the v
+    # transforms and read once by pass B, the float32 image written; the beam likewise with
+    # 16 B per visibility, its FP64 real half grid (N x 2N, as N complex slots) and the
+    # (2N)^2 float32 beam.  The survey's information-minimal bytes (visibilities in, FP32
+    # half grids in, maps out, no intermediate) are reported beside them.
     Nf = b.n_img.astype(np.float64)
     hd = float(np.sum(Nf / 2 * Nf * 16.0))
     hbr = float(np.sum(Nf * 2 * Nf * 8.0))
     im, bm = float(np.sum(4.0 * Nf ** 2)), float(np.sum(16.0 * Nf ** 2))
     M = float(wl.vis_offset[-1])
-    grid_alg = hd + 24.0 * M + hbr + 16.0 * M
-    fft_alg = 2 * hd + (hd + im) + 2 * hbr + (hbr + bm)
-    fft_min = (hd + im) + (hbr + bm)
     def _roof(alg, ms):
         a = alg / (ms * 1e-3) / 1e9
         return {"bound": "hbm", "ms": ms, "algorithmic_bytes": alg, "achieved": a, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": a / HBM_PEAK_GBS}
-    imaging_roof = {
-        "gridding": dict(_roof(grid_alg, grid_k_ms), kernels="k_grid: dirty FP64 complex + beam FP64 real half grids"),
-        "inverse_transform": dict(_roof(fft_alg, ifft_k_ms),
-                                  kernels="k_fft_a, k_fft_b_c2r (dirty), k_fft_a_real, k_fft_b_c2r_sym (beam)",
-                                  information_minimal_bytes=fft_min,
-                                  frac_information_minimal=fft_min / (ifft_k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS),
-    }
+    survey_min = 20.0 * M + float(np.sum(Nf * (Nf / 2 + 1) * 8.0)) + float(np.sum(2 * Nf * (Nf + 1) * 4.0)) + im + bm
+    if fused_k_ms > 0.0:
+        stage_alg = (24.0 * M + 2 * hd + im) + (16.0 * M + 2 * hbr + bm)
+        stage_ms = fused_k_ms + ifft_k_ms
+        imaging_roof = {
+            "imaging_stage": dict(_roof(stage_alg, stage_ms),
+                                  kernels="k_grid_fft_a + k_fft_b_c2r (dirty), k_grid_fft_a_real + k_fft_b_c2r_sym (beam)",
+                                  fused_grid_and_first_pass_ms=fused_k_ms, second_pass_ms=ifft_k_ms,
+                                  survey_minimal_bytes=survey_min,
+                                  frac_survey_minimal=survey_min / (stage_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)}
+    else:
+        grid_alg = hd + 24.0 * M + hbr + 16.0 * M
+        fft_alg = 2 * hd + (hd + im) + 2 * hbr + (hbr + bm)
+        imaging_roof = {
+            "gridding": dict(_roof(grid_alg, grid_k_ms), kernels="k_grid: dirty FP64 complex + beam FP64 real half grids"),
+            "inverse_transform": dict(_roof(fft_alg, ifft_k_ms),
+                                      kernels="k_fft_a, k_fft_b_c2r (dirty), k_fft_a_real, k_fft_b_c2r_sym (beam)"),
+            "imaging_stage": {"ms": grid_k_ms + ifft_k_ms, "survey_minimal_bytes": survey_min,
+                              "frac_survey_minimal": survey_min / ((grid_k_ms + ifft_k_ms) * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
     out = {
         "metric": "images/s (grid+iFFT+Hogbom CLEAN, 1024^2, batched)",
@@ -427,7 +441,8 @@ def main():
     }
 
     if not args.no_plain:
-        # plain path: one instance per call, CLEAN spread over the whole GPU for that image
+        # plain path: one instance per call (a lone image gets the library's team for one
+        # image of its size: 32 workgroups on one XCD at 1024^2)
         k = min(args.plain_subset, n_inst)
         sub = wl.subset(range(k))
         sb = api.Batch.from_workload(sub, dev)

@@ -322,6 +322,21 @@ mi_status mi_disk_offsets(mi_ctx* ctx, const mi_batch* batch, const float* image
 mi_status mi_phase_shift(mi_ctx* ctx, const mi_batch* batch, mi_c64* vis, const float* uv,
                          const double* offsets, hipStream_t stream);
 
+/* ---- tuning (schedules picked by an autotuner; results do not depend on them) -------
+ * grid_chunk: gridder tiles (16 x 64 cells) per workgroup, 1..32, 0 = 8 (the default).
+ * fft_elems:  complex FP64 points each transform workgroup stages in LDS, which sets the
+ *             lines (first pass) and rows (second pass) per workgroup: 0 = by size (4096,
+ *             or 8192 for 8192-point lines), 4096 or 8192.  Plans are keyed by it, so a
+ *             change builds (and caches) new plans.
+ * mi_set_tuning applies to every later call on the context; MI_ERR_ARG for values outside
+ * these ranges.  mi_get_tuning reports the values in use.                            */
+typedef struct {
+  int32_t grid_chunk;
+  int32_t fft_elems;
+} mi_tuning;
+mi_status mi_set_tuning(mi_ctx* ctx, const mi_tuning* tuning);
+mi_status mi_get_tuning(mi_ctx* ctx, mi_tuning* tuning);
+
 /* ---- kernel timing (measurement hook, not part of the imaging path) ----------------
  * mi_profile_begin: from now on, every mi_hogbom_clean call records a pair of HIP events
  *   on its stream around its Hogbom kernel launch (the beam fit, symmetry check and fills
@@ -337,11 +352,16 @@ mi_status mi_profile_end(mi_ctx* ctx, float* ms_out, int32_t cap, int32_t* n_out
 /* Kernel kinds for mi_profile_begin_kinds (bit mask). */
 enum {
   MI_PROF_CLEAN = 1,  /* the Hogbom kernel of mi_hogbom_clean (what mi_profile_begin records)  */
-  MI_PROF_GRID = 2,   /* each FP64 tiled gridder launch: the dirty half grid (mi_dirty_image,
-                         mi_grid with MI_LAYOUT_HALF) and the real beam half grid
-                         (mi_dirty_image with beams, mi_dirty_beam)                           */
-  MI_PROF_IFFT = 4    /* each inverse transform pass: two per dirty-image batch (mi_dirty_image,
-                         mi_dirty_image_w), two per beam batch                                */
+  MI_PROF_GRID = 2,   /* each FP64 tiled gridder launch: the dirty half grid (mi_grid with
+                         MI_LAYOUT_HALF; mi_dirty_image unfused) and the real beam half grid
+                         (mi_dirty_image with beams, mi_dirty_beam, unfused)                  */
+  MI_PROF_IFFT = 4,   /* each inverse transform pass: two per dirty-image batch (mi_dirty_image,
+                         mi_dirty_image_w), two per beam batch; with fused gridding only the
+                         second pass of each                                                  */
+  MI_PROF_GRID_FFT = 8 /* each fused gridding + first transform pass (mi_dirty_image,
+                         mi_dirty_beam, mi_predict_transpose when every image's transform
+                         blocks hold at least two lines, i.e. N <= 2048 at the default
+                         block size): one for the dirty images, one for the beams           */
 };
 
 /* mi_profile_begin_kinds: as mi_profile_begin, for every launch of the kernel kinds in the

@@ -12,13 +12,13 @@ MI_OK, MI_ERR_ARG, MI_ERR_SHAPE, MI_ERR_UNSUPPORTED, MI_ERR_NOMEM, MI_ERR_DEVICE
 MI_INST_EMPTY, MI_INST_LOBE_CLIPPED, MI_INST_RESTORE_CLIPPED, MI_INST_TEST_FAILED, MI_INST_ABORTED = 1, 2, 4, 8, 16
 MI_NATURAL, MI_UNIFORM = 0, 1
 MI_LAYOUT_FULL, MI_LAYOUT_HALF = 0, 1
-MI_PROF_CLEAN, MI_PROF_GRID, MI_PROF_IFFT = 1, 2, 4
+MI_PROF_CLEAN, MI_PROF_GRID, MI_PROF_IFFT, MI_PROF_GRID_FFT = 1, 2, 4, 8
 
 # every entry point declared in include/mi.h
 EXPORTS = ("mi_ctx_create", "mi_ctx_destroy", "mi_last_error", "mi_version", "mi_grid", "mi_ifft2",
            "mi_dirty_image", "mi_dirty_beam", "mi_hogbom_clean", "mi_degrid", "mi_gmm_levels", "mi_disk_offsets", "mi_phase_shift", "mi_profile_begin",
            "mi_profile_end", "mi_dirty_image_w", "mi_profile_begin_kinds", "mi_profile_end_kinds",
-           "mi_predict_transpose", "mi_steer_clean", "mi_hogbom_clean_noalloc")
+           "mi_predict_transpose", "mi_steer_clean", "mi_hogbom_clean_noalloc", "mi_set_tuning", "mi_get_tuning")
 
 
 class MiBatch(ctypes.Structure):
@@ -30,6 +30,10 @@ class MiCleanParams(ctypes.Structure):
     _fields_ = [("gain", c_float), ("niter", c_void_p), ("threshold", c_void_p), ("positive_only", c_int32),
                 ("team_size", c_int32), ("threshold_dev", c_void_p),
                 ("window", c_void_p)]
+
+
+class MiTuning(ctypes.Structure):
+    _fields_ = [("grid_chunk", c_int32), ("fft_elems", c_int32)]
 
 
 class MiSteerParams(ctypes.Structure):
@@ -75,6 +79,8 @@ def lib():
     L.mi_hogbom_clean.argtypes = [vp, POINTER(MiBatch), vp, vp, POINTER(MiCleanParams), vp, vp, vp, vp, vp, vp,
                                   vp, vp]
     L.mi_hogbom_clean_noalloc.argtypes = L.mi_hogbom_clean.argtypes
+    L.mi_set_tuning.argtypes = [vp, POINTER(MiTuning)]
+    L.mi_get_tuning.argtypes = [vp, POINTER(MiTuning)]
     L.mi_dirty_image_w.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, vp, POINTER(MiWprojParams), vp, vp, vp, vp]
     L.mi_degrid.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, c_int, vp, vp]
     L.mi_predict_transpose.argtypes = [vp, POINTER(MiBatch), vp, vp, vp, vp, vp]

@@ -341,6 +341,19 @@ def phase_shift(batch: Batch, vis, uv, offsets):
     return vis
 
 
+def set_tuning(ctx, grid_chunk: int = 0, fft_elems: int = 0):
+    """mi_set_tuning on a context handle (e.g. batch.ctx): gridder tiles per workgroup and
+    transform points per workgroup (0 = the library's defaults)."""
+    nat.check(ctx, nat.lib().mi_set_tuning(ctx, ctypes.byref(nat.MiTuning(int(grid_chunk), int(fft_elems)))))
+
+
+def get_tuning(ctx):
+    """(grid_chunk, fft_elems) in use on a context handle."""
+    t = nat.MiTuning()
+    nat.check(ctx, nat.lib().mi_get_tuning(ctx, ctypes.byref(t)))
+    return int(t.grid_chunk), int(t.fft_elems)
+
+
 def profile_begin(device: int = 0, kinds: int = nat.MI_PROF_CLEAN):
     """mi_profile_begin_kinds: record HIP events around every following launch of the kernel
     kinds in the mask (MI_PROF_CLEAN: the Hogbom kernel; MI_PROF_GRID: the FP64 gridders;

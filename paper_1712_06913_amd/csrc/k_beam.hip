@@ -155,8 +155,7 @@ k_beamfit(const InstDesc* __restrict__ inst, const float* __restrict__ beam, dou
   }
 }
 
-// Degrid (prediction / adjoint): one thread per visibility of instance blockIdx.y; FP64
-// tap sums over the FP64 forward spectrum (same cancellation argument as the imager).
+// Clean-beam fit: one workgroup per instance.
 hipError_t launch_beamfit(const InstDesc* inst, int n_inst, const float* beam, double* cbeam, int* rrad,
                           int* status, hipStream_t st) {
   hipLaunchKernelGGL(k_beamfit, dim3(n_inst), dim3(FIT_THREADS), 0, st, inst, beam, cbeam, rrad, status);

@@ -205,6 +205,167 @@ k_fft_b_c2r(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
   }
 }
 
+// Fused gridding + pass A.  A workgroup owns one block of whole half-grid lines: it
+// accumulates the block's gridded samples (7 x 7 prolate-spheroidal taps, FP64 LDS atomics)
+// straight into the LDS lines, each tap already carrying the (-1)^(i+j) modulation,
+// transforms along v and writes the block once in pass A's blocked layout, so the half grid never goes to HBM and
+// back.  The block's entries are self-contained records (cells, offsets, weight, value)
+// written by k_bin; work item w is block w, so its entry range is tstart[w], tcount[w].
+// Thread t of a round takes entry t / 7 and v tap t % 7 - 3 and adds that cell in each of
+// the sample's seven lines: the seven threads of a sample touch seven consecutive cells of
+// a line (different LDS banks).  The next work item's range and its first round of records
+// are loaded into registers before the current transform, so their latency hides behind it.
+struct RecRegs { int4 a; float4 b; };
+
+__device__ __forceinline__ RecRegs load_rec(const GridRec* __restrict__ rec, int i) {
+  const int4* p = reinterpret_cast<const int4*>(rec + i);
+  RecRegs r;
+  r.a = p[0];
+  r.b = __builtin_bit_cast(float4, p[1]);
+  return r;
+}
+
+template <bool REAL>
+__device__ __forceinline__ void grid_rec(double2* buf, const double* tab, const RecRegs& r, int dv, int h, int first,
+                                         int lines, int log2P) {
+  const int cu = r.a.x >> 16, cv = (int)(short)(r.a.x & 0xffff);
+  const int ou = ((r.a.y >> 8) & 0xff) - OS / 2, ov = (r.a.y & 0xff) - OS / 2;
+  const double w = (double)__int_as_float(r.a.z);
+  const double wr = w * (double)r.b.x, wim = w * (double)r.b.y;
+  const double tv = tab[dv * OS - ov + TAB_CENTRE];
+  const int j = cv + dv + h;
+  // REAL: real line l is the real (l even) or imaginary (l odd) part of complex line l / 2
+  double* row = reinterpret_cast<double*>(buf);
+#pragma unroll
+  for (int du = -HALF_W; du <= HALF_W; ++du) {
+    const int kp = cu + du + h - 1, l = kp - first;
+    if (l < 0 || l >= lines || kp > h - 1) continue;
+    // the (-1)^(i + j) modulation of the transform (u index i = kp + 1) goes with each tap
+    const double kk = ((kp + 1 + j) & 1) ? -(tab[du * OS - ou + TAB_CENTRE] * tv) : tab[du * OS - ou + TAB_CENTRE] * tv;
+    if (REAL) {
+      atomicAdd(row + 2 * pd(((l >> 1) << log2P) + j) + (l & 1), wr * kk);
+    } else {
+      double* a = row + 2 * pd((l << log2P) + j);
+      atomicAdd(a, wr * kk);
+      atomicAdd(a + 1, wim * kk);
+    }
+  }
+}
+
+// One work item's gridding: round 0 from the prefetched registers, later rounds loaded here.
+template <int THREADS, bool REAL>
+__device__ __forceinline__ void grid_block(double2* buf, const double* tab, const GridRec* __restrict__ rec,
+                                           const RecRegs& r0, int st, int cnt, int P, int first, int lines) {
+  constexpr int PER = THREADS / W;
+  const int h = P / 2, log2P = ilog2(P);
+  const int eo = threadIdx.x / W, dv = threadIdx.x - eo * W - HALF_W;
+  if (eo < PER && eo < cnt) grid_rec<REAL>(buf, tab, r0, dv, h, first, lines, log2P);
+  for (int e = PER + eo; e - eo < cnt; e += PER)
+    if (eo < PER && e < cnt) grid_rec<REAL>(buf, tab, load_rec(rec, st + e), dv, h, first, lines, log2P);
+}
+
+template <int ELEMS, int THREADS>
+__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES_PER_EU(ELEMS))))
+k_grid_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int n_work,
+             const GridRec* __restrict__ rec, const int* __restrict__ tstart, const int* __restrict__ tcount,
+             double2* grid, Tables T) {
+  __shared__ double2 buf[LDS_PADDED(ELEMS)];
+  __shared__ double tab[TAB_LEN];
+  for (int t = threadIdx.x; t < TAB_LEN; t += THREADS) tab[t] = T.tab[t];
+  constexpr int PER = THREADS / W;
+  const int eo = threadIdx.x / W;
+  int w = blockIdx.x;
+  int st = 0, cnt = 0;
+  RecRegs r0{};
+  if (w < n_work) {
+    st = tstart[w];
+    cnt = tcount[w];
+    if (eo < PER && eo < cnt) r0 = load_rec(rec, st + eo);
+  }
+  for (; w < n_work; w += gridDim.x) {
+    const int wn = w + gridDim.x;
+    const int stn = wn < n_work ? tstart[wn] : 0, cntn = wn < n_work ? tcount[wn] : 0;
+    const FftWork wk = work[w];
+    const InstDesc d = inst[wk.inst];
+    const int P = d.N, log2P = ilog2(P);
+    const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
+    const int n = nl * P;
+    for (int q = threadIdx.x; q < n; q += THREADS) buf[pd(q)] = make_double2(0.0, 0.0);
+    __syncthreads();
+    grid_block<THREADS, false>(buf, tab, rec, r0, st, cnt, P, wk.first, nl);
+    if (eo < PER && eo < cntn) r0 = load_rec(rec, stn + eo);       // the next item's first round
+    st = stn;
+    cnt = cntn;
+    __syncthreads();
+    lds_fft<ELEMS, THREADS>(buf, log2P, nl, +1.0, T.twiddle);
+    double2* blk = grid + d.gd_off + (int64_t)wk.first * P;
+    for (int q = threadIdx.x; q < n; q += THREADS) {
+      const int y = q >> log2nl, l = q & (nl - 1);
+      blk[q] = buf[pd((l << log2P) + y)];
+    }
+    __syncthreads();
+  }
+}
+
+// The beam's fused gridding + pass A: real lines accumulated two per complex LDS line, then
+// the same transform and slot separation as k_fft_a_real.
+template <int ELEMS, int THREADS>
+__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES_PER_EU(ELEMS))))
+k_grid_fft_a_real(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int n_work,
+                  const GridRec* __restrict__ rec, const int* __restrict__ tstart, const int* __restrict__ tcount,
+                  double* grid, Tables T) {
+  __shared__ double2 buf[LDS_PADDED(ELEMS)];
+  __shared__ double tab[TAB_LEN];
+  for (int t = threadIdx.x; t < TAB_LEN; t += THREADS) tab[t] = T.tab[t];
+  constexpr int PER = THREADS / W;
+  const int eo = threadIdx.x / W;
+  int w = blockIdx.x;
+  int st = 0, cnt = 0;
+  RecRegs r0{};
+  if (w < n_work) {
+    st = tstart[w];
+    cnt = tcount[w];
+    if (eo < PER && eo < cnt) r0 = load_rec(rec, st + eo);
+  }
+  for (; w < n_work; w += gridDim.x) {
+    const int wn = w + gridDim.x;
+    const int stn = wn < n_work ? tstart[wn] : 0, cntn = wn < n_work ? tcount[wn] : 0;
+    const FftWork wk = work[w];
+    const InstDesc d = inst[wk.inst];
+    const int P = 2 * d.N, log2P = ilog2(P), h = P / 2;
+    const int nr = real_lines_per_block<ELEMS>(P), log2nr = ilog2(nr), nc = nr / 2;
+    const int n = nc * P;
+    for (int q = threadIdx.x; q < n; q += THREADS) buf[pd(q)] = make_double2(0.0, 0.0);
+    __syncthreads();
+    grid_block<THREADS, true>(buf, tab, rec, r0, st, cnt, P, wk.first, nr);
+    if (eo < PER && eo < cntn) r0 = load_rec(rec, stn + eo);
+    st = stn;
+    cnt = cntn;
+    __syncthreads();
+    lds_fft<ELEMS, THREADS>(buf, log2P, nc, +1.0, T.twiddle);
+    double2* o = reinterpret_cast<double2*>(grid + d.gb_off + (int64_t)wk.first * P);   // nr x P/2 complex
+    const int log2nc = log2nr - 1;
+    for (int q = threadIdx.x; q < nc * h; q += THREADS) {   // slot sl of lines 2c and 2c + 1
+      const int sl = q >> log2nc, c = q & (nc - 1);
+      const int row = c << log2P;
+      const double2 Z = buf[pd(row + sl)];
+      double2 ya, yb;
+      if (sl == 0) {
+        const double2 Zh = buf[pd(row + h)];
+        ya = make_double2(Z.x, Zh.x);
+        yb = make_double2(Z.y, Zh.y);
+      } else {
+        const double2 Zm = buf[pd(row + P - sl)];
+        ya = make_double2(0.5 * (Z.x + Zm.x), 0.5 * (Z.y - Zm.y));
+        yb = make_double2(0.5 * (Z.y + Zm.y), 0.5 * (Zm.x - Z.x));
+      }
+      o[(sl << log2nr) + 2 * c] = ya;
+      o[(sl << log2nr) + 2 * c + 1] = yb;
+    }
+    __syncthreads();
+  }
+}
+
 // The beam: its grid is real and even (w K at the samples and their mirrors), so
 //  * each half-grid line g_k(v) is real, and its transform along v has Y_k(P - y) =
 //    conj Y_k(y): rows y = 0..P/2 carry everything, and Y_k(0), Y_k(P/2) are real;
@@ -591,6 +752,20 @@ hipError_t launch_fft_a(int elems, int n_cu, const InstDesc* inst, const FftWork
                         const Tables& T, hipStream_t st) {
   if (n_work <= 0) return hipSuccess;
   MI_FFT_PERSISTENT(k_fft_a, inst, work, n_work, grid, T);
+  return hipGetLastError();
+}
+hipError_t launch_grid_fft_a(int elems, int n_cu, const InstDesc* inst, const FftWork* work, int n_work,
+                             const GridRec* rec, const int* tstart, const int* tcount, double2* grid, const Tables& T,
+                             hipStream_t st) {
+  if (n_work <= 0) return hipSuccess;
+  MI_FFT_PERSISTENT(k_grid_fft_a, inst, work, n_work, rec, tstart, tcount, grid, T);
+  return hipGetLastError();
+}
+hipError_t launch_grid_fft_a_real(int elems, int n_cu, const InstDesc* inst, const FftWork* work, int n_work,
+                                  const GridRec* rec, const int* tstart, const int* tcount, double* grid,
+                                  const Tables& T, hipStream_t st) {
+  if (n_work <= 0) return hipSuccess;
+  MI_FFT_PERSISTENT(k_grid_fft_a_real, inst, work, n_work, rec, tstart, tcount, grid, T);
   return hipGetLastError();
 }
 hipError_t launch_fft_b_c2r(int elems, int n_cu, const InstDesc* inst, const FftWork* work, int n_work,

@@ -11,7 +11,7 @@
 // floor of one bin width squared; a component with zero responsibility keeps its values.
 //
 // One workgroup per instance: min/max pass, LDS histogram pass, then the EM iterations on
-// the B bin counts (FP64, block reductions).  HBM traffic: the map is read twice.
+// the B bin counts (FP64, workgroup sums).  HBM traffic: the map is read twice.
 #include <algorithm>
 
 #include "mi_internal.h"
@@ -21,7 +21,6 @@ namespace mi {
 constexpr int GMM_THREADS = 256;
 constexpr int GMM_WAVES = GMM_THREADS / 64;
 constexpr int GMM_MAX_BINS = 4096;
-constexpr int GMM_BPT = GMM_MAX_BINS / GMM_THREADS;   // bins per thread at most
 
 namespace {
 
@@ -30,33 +29,41 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum of NV doubles over the workgroup; every thread gets the totals.
+// Sum of NV doubles over the workgroup with one barrier: wave sums go to one of two
+// scratch buffers (alternating between calls, so a buffer is rewritten only after a later
+// barrier has passed); every thread then adds the wave sums in wave order.
 template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double (*scratch)[GMM_WAVES]) {
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (*scratch)[4][GMM_WAVES], int& parity) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     const double s = wave_sum(v[k]);
-    if (lane == 0) scratch[k][wave] = s;
+    if (lane == 0) scratch[parity][k][wave] = s;
   }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < GMM_WAVES; ++w) t += scratch[k][w];
+    for (int w = 0; w < GMM_WAVES; ++w) t += scratch[parity][k][w];
     v[k] = t;
   }
-  __syncthreads();
+  parity ^= 1;
 }
 
 }  // namespace
 
+// One workgroup of 256 threads per map, BPT bins per thread (8 for up to 2048 bins, so
+// that three workgroups share a compute unit and all maps of a 520-map batch are resident
+// at once).  The E step needs one exponential per bin (the larger of the two log terms
+// gives exp(0) = 1 exactly), and each of the two workgroup sums per iteration takes one
+// barrier.
+template <int GMM_BPT>
 __global__ void __launch_bounds__(GMM_THREADS)
 k_gmm(const InstDesc* __restrict__ inst, const float* __restrict__ images, int n_bins, int n_iter,
       double* __restrict__ levels, float* __restrict__ mu_a_out, float* __restrict__ mu_b_out) {
   __shared__ unsigned hist[GMM_MAX_BINS];
-  __shared__ double scratch[4][GMM_WAVES];
+  __shared__ double scratch[2][4][GMM_WAVES];
   __shared__ float mm[2][GMM_WAVES];
   __shared__ int qbin[2];
   const int i = blockIdx.x;
@@ -64,15 +71,20 @@ k_gmm(const InstDesc* __restrict__ inst, const float* __restrict__ images, int n
   const int64_t n = (int64_t)d.N * d.N;
   const float* img = images + d.img_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int parity = 0;
 
-  // pass 1: range of the finite values
+  // pass 1: range of the finite values (16-byte loads; N^2 is a multiple of 4)
   float mn = INFINITY, mx = -INFINITY;
-  for (int64_t q = tid; q < n; q += GMM_THREADS) {
-    const float v = img[q];
-    if (isfinite(v)) {
-      mn = fminf(mn, v);
-      mx = fmaxf(mx, v);
-    }
+  const float4* img4 = reinterpret_cast<const float4*>(img);
+  for (int64_t q = tid; q < n / 4; q += GMM_THREADS) {
+    const float4 v4 = img4[q];
+    const float v[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (isfinite(v[j])) {
+        mn = fminf(mn, v[j]);
+        mx = fmaxf(mx, v[j]);
+      }
   }
   for (int o = 32; o > 0; o >>= 1) {
     mn = fminf(mn, __shfl_xor(mn, o));
@@ -97,18 +109,23 @@ k_gmm(const InstDesc* __restrict__ inst, const float* __restrict__ images, int n
   }
   // pass 2: histogram
   const double span = hi - lo, B = (double)n_bins;
-  for (int64_t q = tid; q < n; q += GMM_THREADS) {
-    const float v = img[q];
-    if (!isfinite(v)) continue;
-    int j = (int)floor(((double)v - lo) / span * B);
-    j = min(j, n_bins - 1);
-    atomicAdd(&hist[j], 1u);
+  for (int64_t q = tid; q < n / 4; q += GMM_THREADS) {
+    const float4 v4 = img4[q];
+    const float v[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (!isfinite(v[j])) continue;
+      int b = (int)floor(((double)v[j] - lo) / span * B);
+      b = min(b, n_bins - 1);
+      atomicAdd(&hist[b], 1u);
+    }
   }
   __syncthreads();
 
   // bin centres and counts owned by this thread
   const double h = span / B;
   double cnt[GMM_BPT], xc[GMM_BPT];
+  const int nb = (n_bins + GMM_THREADS - 1) / GMM_THREADS;   // bins per thread in use (uniform)
 #pragma unroll
   for (int b = 0; b < GMM_BPT; ++b) {
     const int j = tid + b * GMM_THREADS;
@@ -129,15 +146,17 @@ k_gmm(const InstDesc* __restrict__ inst, const float* __restrict__ images, int n
     qbin[0] = q5;
     qbin[1] = q9;
   }
-  double s[3] = {0.0, 0.0, 0.0};
+  double s[2] = {0.0, 0.0};
 #pragma unroll
-  for (int b = 0; b < GMM_BPT; ++b) { s[0] += cnt[b]; s[1] += cnt[b] * xc[b]; }
-  block_sum<3>(s, scratch);
+  for (int b = 0; b < GMM_BPT; ++b)
+    if (b < nb) { s[0] += cnt[b]; s[1] += cnt[b] * xc[b]; }
+  block_sum<2>(s, scratch, parity);
   const double total = s[0], mean_all = s[1] / total;
   double v1[1] = {0.0};
 #pragma unroll
-  for (int b = 0; b < GMM_BPT; ++b) v1[0] += cnt[b] * (xc[b] - mean_all) * (xc[b] - mean_all);
-  block_sum<1>(v1, scratch);
+  for (int b = 0; b < GMM_BPT; ++b)
+    if (b < nb) v1[0] += cnt[b] * (xc[b] - mean_all) * (xc[b] - mean_all);
+  block_sum<1>(v1, scratch, parity);
   const double floor_var = h * h;
   const double var_all = fmax(v1[0] / total, floor_var);
   double mu[2] = {lo + ((double)qbin[0] + 0.5) * h, lo + ((double)qbin[1] + 0.5) * h};
@@ -145,36 +164,49 @@ k_gmm(const InstDesc* __restrict__ inst, const float* __restrict__ images, int n
   double pi[2] = {0.5, 0.5};
   const double LOG2PI = 1.8378770664093454836;
   for (int t = 0; t < n_iter; ++t) {
-    double c0[2];
-    for (int k = 0; k < 2; ++k) c0[k] = log(pi[k]) - 0.5 * (LOG2PI + log(var[k]));
+    double c0[2], iv[2];
+    for (int k = 0; k < 2; ++k) {
+      c0[k] = log(pi[k]) - 0.5 * (LOG2PI + log(var[k]));
+      iv[k] = 0.5 / var[k];
+    }
     double r0[GMM_BPT], r1[GMM_BPT];
     double a[4] = {0.0, 0.0, 0.0, 0.0};              // n r_0, n r_0 x, n r_1, n r_1 x
 #pragma unroll
     for (int b = 0; b < GMM_BPT; ++b) {
-      const double d0 = xc[b] - mu[0], d1 = xc[b] - mu[1];
-      const double l0 = c0[0] - d0 * d0 / (2.0 * var[0]);
-      const double l1 = c0[1] - d1 * d1 / (2.0 * var[1]);
-      const double m = fmax(l0, l1);
-      const double e0 = exp(l0 - m), e1 = exp(l1 - m);
-      const double es = e0 + e1;
-      r0[b] = e0 / es;
-      r1[b] = e1 / es;
-      a[0] += cnt[b] * r0[b];
-      a[1] += cnt[b] * r0[b] * xc[b];
-      a[2] += cnt[b] * r1[b];
-      a[3] += cnt[b] * r1[b] * xc[b];
+      r0[b] = r1[b] = 0.0;
+      // an empty bin adds nothing to any sum; a wave whose 64 bins are all empty (the long
+      // bright tail of a dirty map's histogram) skips the exponential altogether
+      if (b < nb && cnt[b] > 0.0) {
+        const double d0 = xc[b] - mu[0], d1 = xc[b] - mu[1];
+        const double l0 = c0[0] - d0 * d0 * iv[0];
+        const double l1 = c0[1] - d1 * d1 * iv[1];
+        const double e = exp(fmin(l0, l1) - fmax(l0, l1));   // the other term is exp(0) = 1
+        // 1 / (1 + e) from the hardware reciprocal and two Newton steps (1 + e is in [1, 2])
+        const double den = 1.0 + e;
+        double inv = __builtin_amdgcn_rcp(den);
+        inv = fma(inv, fma(-den, inv, 1.0), inv);
+        inv = fma(inv, fma(-den, inv, 1.0), inv);
+        r0[b] = l0 >= l1 ? inv : e * inv;
+        r1[b] = l0 >= l1 ? e * inv : inv;
+        a[0] += cnt[b] * r0[b];
+        a[1] += cnt[b] * r0[b] * xc[b];
+        a[2] += cnt[b] * r1[b];
+        a[3] += cnt[b] * r1[b] * xc[b];
+      }
     }
-    block_sum<4>(a, scratch);
+    block_sum<4>(a, scratch, parity);
     const double nk[2] = {a[0], a[2]};
     const double mk[2] = {nk[0] > 0.0 ? a[1] / nk[0] : mu[0], nk[1] > 0.0 ? a[3] / nk[1] : mu[1]};
     double v[2] = {0.0, 0.0};
 #pragma unroll
     for (int b = 0; b < GMM_BPT; ++b) {
-      const double d0 = xc[b] - mk[0], d1 = xc[b] - mk[1];
-      v[0] += cnt[b] * r0[b] * d0 * d0;
-      v[1] += cnt[b] * r1[b] * d1 * d1;
+      if (b < nb && cnt[b] > 0.0) {
+        const double d0 = xc[b] - mk[0], d1 = xc[b] - mk[1];
+        v[0] += cnt[b] * r0[b] * d0 * d0;
+        v[1] += cnt[b] * r1[b] * d1 * d1;
+      }
     }
-    block_sum<2>(v, scratch);
+    block_sum<2>(v, scratch, parity);
     for (int k = 0; k < 2; ++k) {
       if (!(nk[k] > 0.0)) continue;
       mu[k] = mk[k];
@@ -194,8 +226,12 @@ k_gmm(const InstDesc* __restrict__ inst, const float* __restrict__ images, int n
 hipError_t launch_gmm(const InstDesc* inst, int n_inst, const float* images, int n_bins, int n_iter,
                       double* levels, float* mu_a, float* mu_b, hipStream_t st) {
   if (n_inst <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gmm, dim3(n_inst), dim3(GMM_THREADS), 0, st, inst, images, n_bins, n_iter, levels, mu_a,
-                     mu_b);
+  if (n_bins <= 8 * GMM_THREADS)
+    hipLaunchKernelGGL(k_gmm<8>, dim3(n_inst), dim3(GMM_THREADS), 0, st, inst, images, n_bins, n_iter, levels, mu_a,
+                       mu_b);
+  else
+    hipLaunchKernelGGL(k_gmm<GMM_MAX_BINS / GMM_THREADS>, dim3(n_inst), dim3(GMM_THREADS), 0, st, inst, images, n_bins,
+                       n_iter, levels, mu_a, mu_b);
   return hipGetLastError();
 }
 

@@ -11,7 +11,7 @@
 //   k_bin   one workgroup per instance: keep/cell decisions, uniform counts (sparse
 //           scratch grid, touched cells only), per-visibility weights, B0 sums, and a
 //           counting sort of (sample, tile) entries for the dirty and the beam half grids.
-//   k_grid  GRID_CHUNK consecutive tiles of TK lines x TJ cells of a half grid per
+//   k_grid  a chunk of consecutive tiles of TK lines x TJ cells of a half grid per
 //           workgroup: accumulate each tile's samples into LDS (no global atomics), then one
 //           coalesced flush of nontemporal 16-byte stores that writes every cell of the
 //           tile (zeros included), so no separate memset pass.
@@ -78,26 +78,66 @@ __device__ __forceinline__ bool tile_range(int cu, int cv, int P, int& tk0, int&
   return true;
 }
 
-// Count (pass 0) or scatter (pass 1) the entries of one half grid.
+// Line blocks of lb whole lines touched by a sample centred on cell (cu, cv): the
+// half-plane lines k' = cu + du + P/2 - 1 <= P/2 - 1 it reaches, in blocks of lb.
+__device__ __forceinline__ bool block_range(int cu, int P, int lb, int& b0, int& b1) {
+  if (cu - HALF_W > 0) return false;
+  const int h = P / 2;
+  const int kp_lo = max(0, cu - HALF_W + h - 1);
+  const int kp_hi = min(h - 1, cu + HALF_W + h - 1);
+  b0 = kp_lo / lb;
+  b1 = kp_hi / lb;
+  return true;
+}
+
+// Count (pass 0) or scatter (pass 1) the entries of one half grid: per tile of TK x TJ
+// cells (lb = 0), or per block of lb whole lines (the fused gridding + transform passes).
+// With rec (line blocks only), the scatter pass writes self-contained records instead.
 __device__ void bin_pass(const InstDesc& d, const float2* __restrict__ uv, const float* __restrict__ w_in,
-                         bool beam, int pass, int* cnt, int* __restrict__ ent) {
+                         bool beam, int pass, int* cnt, int* __restrict__ ent, int lb,
+                         GridRec* __restrict__ rec = nullptr, const float2* __restrict__ vis = nullptr,
+                         const float* __restrict__ wts = nullptr) {
   const int N = d.N, P = beam ? 2 * N : N;
-  const int ntj = P / TJ;
+  const int ntj = lb ? 1 : P / TJ;
   for (int k = threadIdx.x; k < d.n_vis; k += blockDim.x) {
     const float2 q = uv[d.vis_off + k];
     const Sample s = prep_sample(q.x, q.y, w_in[d.vis_off + k], d.scale, N);
     if (!s.keep) continue;
     const int cu = beam ? s.cu2 : s.cu, cv = beam ? s.cv2 : s.cv;
+    const int ou = beam ? s.ou2 : s.ou, ov = beam ? s.ov2 : s.ov;
+    float2 v = make_float2(1.f, 0.f);
+    float wk = 0.f;
+    if (rec && pass) {
+      wk = wts[d.vis_off + k];
+      if (!beam) v = vis ? vis[d.vis_off + k] : make_float2(0.f, 0.f);
+    }
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const int su = m ? -cu : cu, sv = m ? -cv : cv;
       int tk0, tk1, tj0, tj1;
-      if (!tile_range(su, sv, P, tk0, tk1, tj0, tj1)) continue;
+      if (lb) {
+        if (!block_range(su, P, lb, tk0, tk1)) continue;
+        tj0 = tj1 = 0;
+      } else if (!tile_range(su, sv, P, tk0, tk1, tj0, tj1)) {
+        continue;
+      }
       for (int tk = tk0; tk <= tk1; ++tk)
         for (int tj = tj0; tj <= tj1; ++tj) {
           const int t = tk * ntj + tj;
           const int slot = atomicAdd(&cnt[t], 1);
-          if (pass) ent[slot] = (k << 1) | m;
+          if (pass && rec) {
+            GridRec r;
+            r.cucv = (int)(((unsigned)su << 16) | ((unsigned)sv & 0xffffu));
+            r.ouov = (((m ? -ou : ou) + OS / 2) << 8) | ((m ? -ov : ov) + OS / 2);
+            r.w = wk;
+            r.pad0 = 0;
+            r.vr = v.x;
+            r.vi = m ? -v.y : v.y;
+            r.pad1 = r.pad2 = 0.f;
+            rec[slot] = r;
+          } else if (pass) {
+            ent[slot] = (k << 1) | m;
+          }
         }
     }
   }
@@ -111,7 +151,9 @@ k_bin(const InstDesc* __restrict__ inst, const float2* __restrict__ uv, const fl
       int* __restrict__ status, float* __restrict__ cnt_scratch,
       int* __restrict__ ent_d, int* __restrict__ ent_b,
       int* __restrict__ tstart_d, int* __restrict__ tcount_d,
-      int* __restrict__ tstart_b, int* __restrict__ tcount_b, int fail_inst, int do_beam, int unit_w) {
+      int* __restrict__ tstart_b, int* __restrict__ tcount_b, int fail_inst, int do_beam, int unit_w,
+      int lb_elems_d, int lb_elems_b, const float2* __restrict__ vis, GridRec* __restrict__ rec_d,
+      GridRec* __restrict__ rec_b) {
   extern __shared__ int lds[];
   __shared__ int wave_tot[BIN_THREADS / 64 + 1];
   __shared__ double red_d[2][BIN_THREADS / 64];
@@ -160,6 +202,7 @@ k_bin(const InstDesc* __restrict__ inst, const float2* __restrict__ uv, const fl
     }
     wts[d.vis_off + k] = w;
   }
+  __threadfence_block();      // the records written below read these weights back
   sd = wave_sum_d(sd);
   sb = wave_sum_d(sb);
   nk = wave_sum_i(nk);
@@ -179,38 +222,44 @@ k_bin(const InstDesc* __restrict__ inst, const float2* __restrict__ uv, const fl
     if (status) status[i] = (n == 0 ? 1 : 0) | (i == fail_inst ? 8 : 0);
   }
 
-  // ---- counting sort of (sample, tile) entries, dirty grid then beam grid
+  // ---- counting sort of (sample, tile) entries, dirty grid then beam grid; with
+  // lb_elems_* > 0, of (sample, line block) entries for the fused gridding + transform
+  // passes, blocks of the lines one transform workgroup of that many points holds
   for (int g = 0; g < (do_beam ? 2 : 1); ++g) {
     const bool beam = g == 1;
     const int P = beam ? 2 * N : N;
-    const int nt = (P / 2 / TK) * (P / TJ);
+    const int le = beam ? lb_elems_b : lb_elems_d;
+    int lb = 0;
+    if (le) lb = beam ? min(2 * le / P, P / 2) : min(le / P, P / 2);   // real lines (beam) / lines
+    const int nt = lb ? (P / 2) / lb : (P / 2 / TK) * (P / TJ);
+    const int base = lb ? (beam ? d.blk_base_b : d.blk_base_d) : (beam ? d.tile_base_b : d.tile_base_d);
     int* ent = (beam ? ent_b : ent_d) + d.ent_off;
-    int* tstart = (beam ? tstart_b : tstart_d) + (beam ? d.tile_base_b : d.tile_base_d);
-    int* tcount = (beam ? tcount_b : tcount_d) + (beam ? d.tile_base_b : d.tile_base_d);
+    int* tstart = (beam ? tstart_b : tstart_d) + base;
+    int* tcount = (beam ? tcount_b : tcount_d) + base;
     for (int t = tid; t < nt; t += blockDim.x) lds[t] = 0;
     __syncthreads();
-    bin_pass(d, uv, w_in, beam, 0, lds, nullptr);
+    bin_pass(d, uv, w_in, beam, 0, lds, nullptr, lb);
     __syncthreads();
     for (int t = tid; t < nt; t += blockDim.x) tcount[t] = lds[t];
     __syncthreads();
     block_exclusive_scan(lds, nt, wave_tot);
     for (int t = tid; t < nt; t += blockDim.x) tstart[t] = (int)(d.ent_off) + lds[t];
     __syncthreads();
-    bin_pass(d, uv, w_in, beam, 1, lds, ent);
+    bin_pass(d, uv, w_in, beam, 1, lds, ent, lb, lb ? (beam ? rec_b : rec_d) + d.ent_off : nullptr, vis, wts);
     __syncthreads();
   }
 }
 
-// Tiles of TK x TJ cells, GRID_CHUNK consecutive tiles per workgroup (their metadata
+// Tiles of TK x TJ cells, `chunk` consecutive tiles per workgroup (their metadata
 // staged in LDS, so a run of empty tiles is a stream of stores with no dependent global
 // loads).  A non-empty tile stages up to GRID_EB of its samples' parameters in LDS, then
 // spreads (sample, tap row) pairs over all threads; accumulation is FP64 in LDS (the grid
-// correction later amplifies grid rounding by up to ~1e6 in the map corners).  Eight
-// tiles per workgroup measured fastest (32: 1.1 ms slower per 520 x 1024^2 dirty + beam
-// batch, the few dense tiles near each uv centre holding their workgroup longer; 2-4:
-// more per-workgroup setup).
+// correction later amplifies grid rounding by up to ~1e6 in the map corners).  The chunk
+// is chosen per context (mi_set_tuning; 8 by default): on a 520 x 1024^2 dirty + beam batch
+// 8 measured fastest (32: 1.1 ms slower, the few dense tiles near each uv centre holding
+// their workgroup longer; 2-4: more per-workgroup setup).
 constexpr int GRID_THREADS = 256;
-constexpr int GRID_CHUNK = 8;
+constexpr int GRID_CHUNK_MAX = 32;   // tiles per workgroup: a tuning choice up to this
 constexpr int GRID_EB = 256;
 // Row stride of the LDS accumulator.  The seven lanes of one sample add into seven tile
 // rows at the same column, which a 64-cell stride puts in one LDS bank; one cell of
@@ -239,20 +288,20 @@ k_grid(const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst, int
        const float2* __restrict__ vis, const float2* __restrict__ uv, const float* __restrict__ w_in,
        const float* __restrict__ wts, const int* __restrict__ ent,
        const int* __restrict__ tstart, const int* __restrict__ tcount, Tables T,
-       OutT* __restrict__ grid, int modulate) {
+       OutT* __restrict__ grid, int modulate, int chunk) {
   constexpr bool REAL = std::is_same<OutT, double>::value;
   constexpr int RS = acc_stride<REAL>();
   __shared__ double2 acc[REAL ? TK * RS / 2 : TK * RS];
   double* accr = reinterpret_cast<double*>(acc);       // real grids: one double per cell
   static_assert(!REAL || RS % 2 == 0, "real cell pairs are read as 16 bytes");
   __shared__ double tab[TAB_LEN];
-  __shared__ int m_inst[GRID_CHUNK], m_start[GRID_CHUNK], m_cnt[GRID_CHUNK];
+  __shared__ int m_inst[GRID_CHUNK_MAX], m_start[GRID_CHUNK_MAX], m_cnt[GRID_CHUNK_MAX];
   __shared__ int s_kp[GRID_EB], s_j[GRID_EB], s_ou[GRID_EB], s_ov[GRID_EB];
   __shared__ double s_wr[GRID_EB], s_wi[GRID_EB];
   const int tid = threadIdx.x;
-  const int g0 = blockIdx.x * GRID_CHUNK;
+  const int g0 = blockIdx.x * chunk;
   if (g0 >= n_tiles) return;
-  const int gn = min(GRID_CHUNK, n_tiles - g0);
+  const int gn = min(chunk, n_tiles - g0);
   for (int t = tid; t < TAB_LEN; t += GRID_THREADS) tab[t] = T.tab[t];
   for (int t = tid; t < gn; t += GRID_THREADS) {
     m_inst[t] = tile_inst[g0 + t];
@@ -390,41 +439,46 @@ __global__ void k_expand_full(const InstDesc* __restrict__ inst, int n_inst, int
 hipError_t launch_bin(const InstDesc* inst, int n_inst, const float2* uv, const float* w_in, const Tables& T,
                       float* wts, double* b0, int* nkept, int* status, float* cnt, int* ent_d, int* ent_b,
                       int* tstart_d, int* tcount_d, int* tstart_b, int* tcount_b, int fail_inst, int do_beam,
-                      int unit_w, size_t lds_bytes, hipStream_t st) {
+                      int unit_w, int lb_elems_d, int lb_elems_b, const float2* vis, GridRec* rec_d,
+                      GridRec* rec_b, size_t lds_bytes, hipStream_t st) {
   hipLaunchKernelGGL(k_bin, dim3(n_inst), dim3(BIN_THREADS), lds_bytes, st, inst, uv, w_in, T, wts, b0, nkept,
-                     status, cnt, ent_d, ent_b, tstart_d, tcount_d, tstart_b, tcount_b, fail_inst, do_beam, unit_w);
+                     status, cnt, ent_d, ent_b, tstart_d, tcount_d, tstart_b, tcount_b, fail_inst, do_beam, unit_w,
+                     lb_elems_d, lb_elems_b, vis, rec_d, rec_b);
   return hipGetLastError();
 }
 
 template <class OutT>
 hipError_t launch_grid_t(const InstDesc* inst, const int* tile_inst, int n_tiles, int beam, const float2* vis,
                          const float2* uv, const float* w_in, const float* wts, const int* ent, const int* tstart,
-                         const int* tcount, const Tables& T, OutT* grid, int modulate, hipStream_t st) {
+                         const int* tcount, const Tables& T, OutT* grid, int modulate, int chunk, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  const int blocks = (n_tiles + GRID_CHUNK - 1) / GRID_CHUNK;
+  if (chunk < 1 || chunk > GRID_CHUNK_MAX) return hipErrorInvalidValue;
+  const int blocks = (n_tiles + chunk - 1) / chunk;
   hipLaunchKernelGGL((k_grid<OutT>), dim3(blocks), dim3(GRID_THREADS), 0, st, inst, tile_inst, n_tiles, beam, vis,
-                     uv, w_in, wts, ent, tstart, tcount, T, grid, modulate);
+                     uv, w_in, wts, ent, tstart, tcount, T, grid, modulate, chunk);
   return hipGetLastError();
 }
 
 hipError_t launch_grid(const InstDesc* inst, const int* tile_inst, int n_tiles, int beam, const float2* vis,
                        const float2* uv, const float* w_in, const float* wts, const int* ent, const int* tstart,
-                       const int* tcount, const Tables& T, double2* grid, int modulate, hipStream_t st) {
+                       const int* tcount, const Tables& T, double2* grid, int modulate, int chunk, hipStream_t st) {
   return launch_grid_t(inst, tile_inst, n_tiles, beam, vis, uv, w_in, wts, ent, tstart, tcount, T, grid, modulate,
-                       st);
+                       chunk, st);
 }
 
 hipError_t launch_grid_f32(const InstDesc* inst, const int* tile_inst, int n_tiles, int beam, const float2* vis,
                            const float2* uv, const float* w_in, const float* wts, const int* ent, const int* tstart,
-                           const int* tcount, const Tables& T, float2* grid, int modulate, hipStream_t st) {
+                           const int* tcount, const Tables& T, float2* grid, int modulate, int chunk,
+                           hipStream_t st) {
   return launch_grid_t(inst, tile_inst, n_tiles, beam, vis, uv, w_in, wts, ent, tstart, tcount, T, grid, modulate,
-                       st);
+                       chunk, st);
 }
 
 hipError_t launch_grid_real(const InstDesc* inst, const int* tile_inst, int n_tiles, const float2* uv,
                             const float* w_in, const float* wts, const int* ent, const int* tstart, const int* tcount,
-                            const Tables& T, double* grid, hipStream_t st) {
-  return launch_grid_t(inst, tile_inst, n_tiles, 1, nullptr, uv, w_in, wts, ent, tstart, tcount, T, grid, 1, st);
+                            const Tables& T, double* grid, int chunk, hipStream_t st) {
+  return launch_grid_t(inst, tile_inst, n_tiles, 1, nullptr, uv, w_in, wts, ent, tstart, tcount, T, grid, 1, chunk,
+                       st);
 }
 
 hipError_t launch_expand_full(const InstDesc* inst, int n_inst, int beam, const double2* half, float2* full,

@@ -29,12 +29,12 @@
 
 namespace mi {
 
-constexpr int ST_THREADS = 1024;
-constexpr int ST_ELEMS = 8192;   // complex doubles staged per workgroup (144 KB with padding)
+constexpr int ST_THREADS = 512;
+// Complex doubles staged per workgroup: 4096 (72 KB with padding, two workgroups per compute
+// unit) for transforms up to 4096 points, 8192 (144 KB) for 8192-point ones (N = 4096).
+constexpr int st_lds(int elems) { return elems + elems / 8; }
 
 namespace {
-
-constexpr int ST_LDS = ST_ELEMS + ST_ELEMS / 8;
 
 __device__ __forceinline__ unsigned fkey(float v) {
   const unsigned b = __float_as_uint(v);
@@ -85,9 +85,9 @@ __device__ __forceinline__ bool st_sel(float v, double tp, int posonly) {
 //   MODE 2: the dirty beam (2N rows of 2N);
 //   MODE 3: the clean-beam Gaussian exp(-(a dx^2 + b dx dy + c dy^2)) at dx = x - N,
 //           dy = y - N (2N rows of 2N).
-template <int MODE>
+template <int MODE, int ST_ELEMS>
 __global__ void __launch_bounds__(ST_THREADS) k_st_rows(SteerArgs A) {
-  __shared__ double2 buf[ST_LDS];
+  __shared__ double2 buf[st_lds(ST_ELEMS)];
   __shared__ unsigned n_sel;
   const FftWork wk = A.work[blockIdx.x];
   const int i = wk.inst;
@@ -163,9 +163,9 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_rows(SteerArgs A) {
 //           column in S;
 //   MODE 1: convolution: rows 0..N-1 (the rest is zero), FFT, times S, inverse FFT, rows
 //           N..2N-1 written back over rows 0..N-1 of the same columns.
-template <int MODE>
+template <int MODE, int ST_ELEMS>
 __global__ void __launch_bounds__(ST_THREADS) k_st_cols(SteerArgs A) {
-  __shared__ double2 buf[ST_LDS];
+  __shared__ double2 buf[st_lds(ST_ELEMS)];
   const FftWork wk = A.work[blockIdx.x];
   const int i = wk.inst;
   const InstDesc d = A.inst[i];
@@ -214,9 +214,9 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_cols(SteerArgs A) {
 // complex FFT), keeping columns N..2N-1.
 //   MODE 0: D = the result, and its max |D| into the image's control word;
 //   MODE 1: the restored image R + result.
-template <int MODE>
+template <int MODE, int ST_ELEMS>
 __global__ void __launch_bounds__(ST_THREADS) k_st_rows_inv(SteerArgs A) {
-  __shared__ double2 buf[ST_LDS];
+  __shared__ double2 buf[st_lds(ST_ELEMS)];
   __shared__ unsigned red[ST_THREADS / 64];
   const FftWork wk = A.work[blockIdx.x];
   const int i = wk.inst;
@@ -344,23 +344,24 @@ static hipError_t st_launch(const void* k, int n_blocks, const SteerArgs& A, hip
   return hipLaunchKernel(k, dim3(n_blocks), dim3(ST_THREADS), args, 0, st);
 }
 
-hipError_t launch_st_rows(int mode, int n_blocks, const SteerArgs& A, hipStream_t st) {
-  const void* k = mode == 0   ? reinterpret_cast<const void*>(&k_st_rows<0>)
-                  : mode == 1 ? reinterpret_cast<const void*>(&k_st_rows<1>)
-                  : mode == 2 ? reinterpret_cast<const void*>(&k_st_rows<2>)
-                              : reinterpret_cast<const void*>(&k_st_rows<3>);
+#define MI_ST_PICK(KERNEL, MODE) \
+  (elems == 8192 ? reinterpret_cast<const void*>(&KERNEL<MODE, 8192>) : reinterpret_cast<const void*>(&KERNEL<MODE, 4096>))
+
+hipError_t launch_st_rows(int mode, int elems, int n_blocks, const SteerArgs& A, hipStream_t st) {
+  const void* k = mode == 0   ? MI_ST_PICK(k_st_rows, 0)
+                  : mode == 1 ? MI_ST_PICK(k_st_rows, 1)
+                  : mode == 2 ? MI_ST_PICK(k_st_rows, 2)
+                              : MI_ST_PICK(k_st_rows, 3);
   return st_launch(k, n_blocks, A, st);
 }
 
-hipError_t launch_st_cols(int mode, int n_blocks, const SteerArgs& A, hipStream_t st) {
-  const void* k = mode == 0 ? reinterpret_cast<const void*>(&k_st_cols<0>)
-                            : reinterpret_cast<const void*>(&k_st_cols<1>);
+hipError_t launch_st_cols(int mode, int elems, int n_blocks, const SteerArgs& A, hipStream_t st) {
+  const void* k = mode == 0 ? MI_ST_PICK(k_st_cols, 0) : MI_ST_PICK(k_st_cols, 1);
   return st_launch(k, n_blocks, A, st);
 }
 
-hipError_t launch_st_rows_inv(int mode, int n_blocks, const SteerArgs& A, hipStream_t st) {
-  const void* k = mode == 0 ? reinterpret_cast<const void*>(&k_st_rows_inv<0>)
-                            : reinterpret_cast<const void*>(&k_st_rows_inv<1>);
+hipError_t launch_st_rows_inv(int mode, int elems, int n_blocks, const SteerArgs& A, hipStream_t st) {
+  const void* k = mode == 0 ? MI_ST_PICK(k_st_rows_inv, 0) : MI_ST_PICK(k_st_rows_inv, 1);
   return st_launch(k, n_blocks, A, st);
 }
 

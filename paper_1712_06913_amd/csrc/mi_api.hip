@@ -31,11 +31,12 @@ namespace mi {
 
 // launchers (defined next to their kernels)
 hipError_t launch_bin(const InstDesc*, int, const float2*, const float*, const Tables&, float*, double*, int*, int*,
-                      float*, int*, int*, int*, int*, int*, int*, int, int, int, size_t, hipStream_t);
+                      float*, int*, int*, int*, int*, int*, int*, int, int, int, int, int, const float2*, GridRec*,
+                      GridRec*, size_t, hipStream_t);
 hipError_t launch_grid(const InstDesc*, const int*, int, int, const float2*, const float2*, const float*,
-                       const float*, const int*, const int*, const int*, const Tables&, double2*, int, hipStream_t);
+                       const float*, const int*, const int*, const int*, const Tables&, double2*, int, int, hipStream_t);
 hipError_t launch_grid_f32(const InstDesc*, const int*, int, int, const float2*, const float2*, const float*,
-                           const float*, const int*, const int*, const int*, const Tables&, float2*, int,
+                           const float*, const int*, const int*, const int*, const Tables&, float2*, int, int,
                            hipStream_t);
 hipError_t launch_expand_full(const InstDesc*, int, int, const double2*, float2*, const int64_t*, hipStream_t);
 hipError_t launch_fill_u32(unsigned*, int64_t, unsigned, hipStream_t);
@@ -47,8 +48,12 @@ hipError_t launch_grid_wt(const InstDesc*, const int*, int, const float2*, const
                           const float*, const int*, const int*, const int*, const WInst*, const WPlane*,
                           const double2*, double2*, hipStream_t);
 hipError_t launch_grid_real(const InstDesc*, const int*, int, const float2*, const float*, const float*, const int*,
-                            const int*, const int*, const Tables&, double*, hipStream_t);
+                            const int*, const int*, const Tables&, double*, int, hipStream_t);
 hipError_t launch_fft_a(int, int, const InstDesc*, const FftWork*, int, double2*, const Tables&, hipStream_t);
+hipError_t launch_grid_fft_a(int, int, const InstDesc*, const FftWork*, int, const GridRec*, const int*, const int*,
+                             double2*, const Tables&, hipStream_t);
+hipError_t launch_grid_fft_a_real(int, int, const InstDesc*, const FftWork*, int, const GridRec*, const int*,
+                                  const int*, double*, const Tables&, hipStream_t);
 hipError_t launch_fft_b_c2r(int, int, const InstDesc*, const FftWork*, int, const double2*, const double*,
                             const Tables&, float*, hipStream_t);
 hipError_t launch_fft_a_real(int, int, const InstDesc*, const FftWork*, int, double*, const Tables&, hipStream_t);
@@ -74,9 +79,9 @@ hipError_t launch_phase_shift(const InstDesc*, int, int, float2*, const float2*,
 hipError_t launch_beam_symcheck(const InstDesc*, int, int, const float*, int*, hipStream_t);
 hipError_t launch_degrid(const InstDesc*, int, int, const float2*, const float*, const float*, const double*,
                          const double2*, const Tables&, int, float2*, hipStream_t);
-hipError_t launch_st_rows(int mode, int n_blocks, const SteerArgs& A, hipStream_t st);
-hipError_t launch_st_cols(int mode, int n_blocks, const SteerArgs& A, hipStream_t st);
-hipError_t launch_st_rows_inv(int mode, int n_blocks, const SteerArgs& A, hipStream_t st);
+hipError_t launch_st_rows(int mode, int elems, int n_blocks, const SteerArgs& A, hipStream_t st);
+hipError_t launch_st_cols(int mode, int elems, int n_blocks, const SteerArgs& A, hipStream_t st);
+hipError_t launch_st_rows_inv(int mode, int elems, int n_blocks, const SteerArgs& A, hipStream_t st);
 hipError_t launch_st_init(int n_blocks, const SteerArgs& A, hipStream_t st);
 hipError_t launch_st_update(int n_blocks, const SteerArgs& A, hipStream_t st);
 
@@ -175,6 +180,7 @@ struct CleanPlan : CacheEntry {
 struct SteerBase {
   DevBuf rows, rows2, cols, inv, pix;    // FftWork lists: N rows, 2N rows, columns, N rows, pixel blocks
   int n_rows = 0, n_rows2 = 0, n_cols = 0, n_inv = 0, n_pix = 0;
+  int elems = 4096;                      // complex doubles per workgroup of the transform passes
   std::vector<int64_t> x_off, s_off;
   std::vector<int32_t> rb;
   int64_t total_x = 0, total_s = 0;
@@ -191,7 +197,8 @@ struct SteerPlan : CacheEntry {
 };
 
 struct Plan : CacheEntry {
-  // key
+  // key (with the context's transform block size, which shapes the work lists)
+  int fft_elems_req = 0;
   std::vector<int64_t> off;
   std::vector<int32_t> n;
   std::vector<double> cell;
@@ -210,6 +217,10 @@ struct Plan : CacheEntry {
   // gd: dirty half grids (FP64 complex); gbr: beam half grids (FP64 real), then the beam's
   // transform slots in place; gb: FP64 complex beam grids for mi_grid's full layout
   DevBuf wts, b0, nkept, cnt, ent_d, ent_b, ts_d, tc_d, ts_b, tc_b, gd, gbr, gb, status_ws;
+  // fused gridding + first transform pass (every instance's blocks hold >= 2 lines, so a
+  // sample's 7 lines touch at most 4 blocks): per line block entry lists
+  bool fused = false;
+  DevBuf bs_d, bc_d, bs_b, bc_b, rec_d, rec_b;
   // element offsets of each instance's grid in mi_grid's full layout: dirty grids; beam
   // grids after all dirty grids; beam grids alone (3 n_inst values, uploaded with the plan)
   DevBuf full_off;
@@ -254,6 +265,8 @@ struct mi_ctx {
   unsigned char* noalloc_scratch = nullptr;   // this device's copy of the static CLEAN scratch
   int fail_inst = -1;
   int clean_stall = 0;   // failure-path tests (MI_TEST_CLEAN_STALL): CLEAN team waits give up
+  int grid_chunk = 8;    // gridder tiles per workgroup (mi_set_tuning)
+  int fft_elems = 0;     // transform points per workgroup, 0 = by size (mi_set_tuning)
   int n_cu = 256;
   uint64_t tick = 0;     // plan-cache clock (least recently used is evicted first)
   // kernel timing: event pairs around launches of the kinds in prof_kinds (MI_PROF_*)
@@ -352,10 +365,11 @@ Plan* get_plan(mi_ctx* ctx, const mi_batch* b, hipStream_t st) {
   h = fnv1a(b->n_img, sizeof(int32_t) * n, h);
   h = fnv1a(b->cell_rad, sizeof(double) * n, h);
   h = fnv1a(b->weight_mode, sizeof(int8_t) * n, h);
+  h = fnv1a(&ctx->fft_elems, sizeof ctx->fft_elems, h);
   auto it = ctx->plans.find(h);
   if (it != ctx->plans.end()) {
     Plan* p = it->second.get();
-    if (p->n_inst == n && std::equal(p->off.begin(), p->off.end(), b->vis_offset) &&
+    if (p->n_inst == n && p->fft_elems_req == ctx->fft_elems && std::equal(p->off.begin(), p->off.end(), b->vis_offset) &&
         std::equal(p->n.begin(), p->n.end(), b->n_img) && std::equal(p->cell.begin(), p->cell.end(), b->cell_rad) &&
         std::equal(p->mode.begin(), p->mode.end(), b->weight_mode)) {
       touch(ctx, p, st);
@@ -379,8 +393,10 @@ Plan* get_plan(mi_ctx* ctx, const mi_batch* b, hipStream_t st) {
   int max_tiles = 0;
   int maxN = 0;
   for (int i = 0; i < n; ++i) maxN = std::max(maxN, (int)b->n_img[i]);
-  P->elems_d = fft_elems_for(maxN);
-  P->elems_b = fft_elems_for(2 * maxN);
+  P->fft_elems_req = ctx->fft_elems;
+  P->elems_d = std::max(ctx->fft_elems, fft_elems_for(maxN));
+  P->elems_b = std::max(ctx->fft_elems, fft_elems_for(2 * maxN));
+  bool fused = true;
   for (int i = 0; i < n; ++i) {
     InstDesc& d = P->h_inst[i];
     std::memset(&d, 0, sizeof d);
@@ -412,6 +428,9 @@ Plan* get_plan(mi_ctx* ctx, const mi_batch* b, hipStream_t st) {
     for (int t = 0; t < ntd; ++t) tile_inst_d.push_back(i);
     for (int t = 0; t < ntb; ++t) tile_inst_b.push_back(i);
     const int nld = fft_lines_per_block_host(N, P->elems_d), nrb = fft_real_lines_per_block_host(2 * N, P->elems_b);
+    d.blk_base_d = (int32_t)wa_d.size();
+    d.blk_base_b = (int32_t)wa_b.size();
+    fused = fused && nld >= 2 && nrb >= 2;
     const int nyd = fft_rows_per_block_host(N, P->elems_d), nyb = fft_rows_per_block_host(2 * N, P->elems_b);
     for (int l = 0; l < N / 2; l += nld) wa_d.push_back({i, l});
     for (int y = 0; y < N; y += nyd) wb_d.push_back({i, y});
@@ -430,6 +449,7 @@ Plan* get_plan(mi_ctx* ctx, const mi_batch* b, hipStream_t st) {
   upload(P->wb_d, wb_d);
   upload(P->wa_b, wa_b);
   upload(P->wb_b, wb_b);
+  P->fused = fused;
   P->n_wa_d = (int)wa_d.size();
   P->n_wb_d = (int)wb_d.size();
   P->n_wa_b = (int)wa_b.size();
@@ -453,22 +473,40 @@ Plan* get_plan(mi_ctx* ctx, const mi_batch* b, hipStream_t st) {
 }
 
 // Prep + weights + B0 + binning (k_bin).  Returns the status pointer used.
+// Prep, weights, B0 and the entry lists: per tile for the tiled gridder, or per line block
+// (blocks = true) for the fused gridding + first transform pass.
 int* run_bin(mi_ctx* ctx, Plan* P, const mi_batch* b, const float* uv, const float* w_in, bool beam,
-             hipStream_t st, bool unit_w = false) {
+             hipStream_t st, bool unit_w = false, bool blocks = false, const mi_c64* vis = nullptr) {
   float* wts = dev_alloc<float>(P->wts, P->total_vis);
   double* b0 = dev_alloc<double>(P->b0, 2 * P->n_inst);
   int* nk = dev_alloc<int>(P->nkept, P->n_inst);
   float* cnt = dev_alloc<float>(P->cnt, P->total_cnt);
   int* ed = dev_alloc<int>(P->ent_d, P->total_ent);
   int* eb = beam ? dev_alloc<int>(P->ent_b, P->total_ent) : nullptr;
-  int* tsd = dev_alloc<int>(P->ts_d, P->tiles_d);
-  int* tcd = dev_alloc<int>(P->tc_d, P->tiles_d);
-  int* tsb = beam ? dev_alloc<int>(P->ts_b, P->tiles_b) : nullptr;
-  int* tcb = beam ? dev_alloc<int>(P->tc_b, P->tiles_b) : nullptr;
+  int *tsd, *tcd, *tsb = nullptr, *tcb = nullptr;
+  GridRec *rd = nullptr, *rb = nullptr;
+  if (blocks) {
+    rd = dev_alloc<GridRec>(P->rec_d, P->total_ent);
+    if (beam) rb = dev_alloc<GridRec>(P->rec_b, P->total_ent);
+    tsd = dev_alloc<int>(P->bs_d, P->n_wa_d);
+    tcd = dev_alloc<int>(P->bc_d, P->n_wa_d);
+    if (beam) {
+      tsb = dev_alloc<int>(P->bs_b, P->n_wa_b);
+      tcb = dev_alloc<int>(P->bc_b, P->n_wa_b);
+    }
+  } else {
+    tsd = dev_alloc<int>(P->ts_d, P->tiles_d);
+    tcd = dev_alloc<int>(P->tc_d, P->tiles_d);
+    if (beam) {
+      tsb = dev_alloc<int>(P->ts_b, P->tiles_b);
+      tcb = dev_alloc<int>(P->tc_b, P->tiles_b);
+    }
+  }
   int* status = b->status ? b->status : dev_alloc<int>(P->status_ws, P->n_inst);
   HIPCHK(launch_bin(static_cast<const InstDesc*>(P->inst.p), P->n_inst, reinterpret_cast<const float2*>(uv), w_in,
                     ctx->T, wts, b0, nk, status, cnt, ed, eb, tsd, tcd, tsb, tcb, ctx->fail_inst, beam ? 1 : 0,
-                    unit_w ? 1 : 0, P->bin_lds, st));
+                    unit_w ? 1 : 0, blocks ? P->elems_d : 0, blocks ? P->elems_b : 0,
+                    reinterpret_cast<const float2*>(vis), rd, rb, P->bin_lds, st));
   return status;
 }
 
@@ -486,11 +524,29 @@ void run_grid(mi_ctx* ctx, Plan* P, const mi_c64* vis, const float* uv, const fl
   if constexpr (std::is_same<OutT, double2>::value) {
     hipEvent_t pe = prof_start(ctx, MI_PROF_GRID, st);
     HIPCHK(launch_grid(inst, tmap, nt, beam ? 1 : 0, v, reinterpret_cast<const float2*>(uv), w_in, wts, ent, ts, tc,
-                       ctx->T, out, modulate, st));
+                       ctx->T, out, modulate, ctx->grid_chunk, st));
     prof_stop(pe, st);
   } else
     HIPCHK(launch_grid_f32(inst, tmap, nt, beam ? 1 : 0, v, reinterpret_cast<const float2*>(uv), w_in, wts, ent, ts,
-                           tc, ctx->T, out, modulate, st));
+                           tc, ctx->T, out, modulate, ctx->grid_chunk, st));
+}
+
+// Dirty images straight from the visibilities: the fused gridding + first pass (line-block
+// lists from run_bin with blocks = true), then pass B.
+void run_dirty_fused(mi_ctx* ctx, Plan* P, const mi_c64* vis, const float* uv, const float* w_in, float* out,
+                     hipStream_t st, const double* b0 = nullptr) {
+  const InstDesc* inst = static_cast<const InstDesc*>(P->inst.p);
+  double2* g = dev_alloc<double2>(P->gd, P->total_gd);
+  if (!b0) b0 = static_cast<const double*>(P->b0.p);
+  hipEvent_t pe = prof_start(ctx, MI_PROF_GRID_FFT, st);
+  HIPCHK(launch_grid_fft_a(P->elems_d, ctx->n_cu, inst, static_cast<const FftWork*>(P->wa_d.p), P->n_wa_d,
+                           static_cast<const GridRec*>(P->rec_d.p), static_cast<const int*>(P->bs_d.p),
+                           static_cast<const int*>(P->bc_d.p), g, ctx->T, st));
+  prof_stop(pe, st);
+  pe = prof_start(ctx, MI_PROF_IFFT, st);
+  HIPCHK(launch_fft_b_c2r(P->elems_d, ctx->n_cu, inst, static_cast<const FftWork*>(P->wb_d.p), P->n_wb_d, g, b0, ctx->T, out,
+                          st));
+  prof_stop(pe, st);
 }
 
 // Dirty images from the dirty half grids in P->gd.
@@ -508,18 +564,29 @@ void run_image(mi_ctx* ctx, Plan* P, float* out, hipStream_t st, const double* b
 }
 
 // Beams: real FP64 beam grid (gridder), then the two symmetric transform passes.
+// With P->fused (line-block lists from run_bin), the gridding and the first pass are one kernel.
 void run_beam(mi_ctx* ctx, Plan* P, const float* uv, const float* w_in, float* out, hipStream_t st) {
   const InstDesc* inst = static_cast<const InstDesc*>(P->inst.p);
   double* g = dev_alloc<double>(P->gbr, P->total_gb);
-  hipEvent_t pe = prof_start(ctx, MI_PROF_GRID, st);
-  HIPCHK(launch_grid_real(inst, static_cast<const int*>(P->tile_inst_b.p), P->tiles_b,
-                          reinterpret_cast<const float2*>(uv), w_in, static_cast<const float*>(P->wts.p),
-                          static_cast<const int*>(P->ent_b.p), static_cast<const int*>(P->ts_b.p),
-                          static_cast<const int*>(P->tc_b.p), ctx->T, g, st));
-  prof_stop(pe, st);
-  pe = prof_start(ctx, MI_PROF_IFFT, st);
-  HIPCHK(launch_fft_a_real(P->elems_b, ctx->n_cu, inst, static_cast<const FftWork*>(P->wa_b.p), P->n_wa_b, g, ctx->T, st));
-  prof_stop(pe, st);
+  hipEvent_t pe;
+  if (P->fused) {
+    pe = prof_start(ctx, MI_PROF_GRID_FFT, st);
+    HIPCHK(launch_grid_fft_a_real(P->elems_b, ctx->n_cu, inst, static_cast<const FftWork*>(P->wa_b.p), P->n_wa_b,
+                                  static_cast<const GridRec*>(P->rec_b.p), static_cast<const int*>(P->bs_b.p),
+                                  static_cast<const int*>(P->bc_b.p), g, ctx->T, st));
+    prof_stop(pe, st);
+  } else {
+    pe = prof_start(ctx, MI_PROF_GRID, st);
+    HIPCHK(launch_grid_real(inst, static_cast<const int*>(P->tile_inst_b.p), P->tiles_b,
+                            reinterpret_cast<const float2*>(uv), w_in, static_cast<const float*>(P->wts.p),
+                            static_cast<const int*>(P->ent_b.p), static_cast<const int*>(P->ts_b.p),
+                            static_cast<const int*>(P->tc_b.p), ctx->T, g, ctx->grid_chunk, st));
+    prof_stop(pe, st);
+    pe = prof_start(ctx, MI_PROF_IFFT, st);
+    HIPCHK(launch_fft_a_real(P->elems_b, ctx->n_cu, inst, static_cast<const FftWork*>(P->wa_b.p), P->n_wa_b, g, ctx->T,
+                             st));
+    prof_stop(pe, st);
+  }
   pe = prof_start(ctx, MI_PROF_IFFT, st);
   HIPCHK(launch_fft_b_c2r_sym(P->elems_b, ctx->n_cu, inst, static_cast<const FftWork*>(P->wb_b.p), P->n_wb_b, g,
                               static_cast<const double*>(P->b0.p), ctx->T, out, st));
@@ -933,9 +1000,29 @@ mi_status mi_phase_shift(mi_ctx* ctx, const mi_batch* batch, mi_c64* vis, const 
   });
 }
 
+mi_status mi_set_tuning(mi_ctx* ctx, const mi_tuning* t) {
+  return guard(ctx, [&] {
+    need(t, "tuning");
+    if (t->grid_chunk != 0 && (t->grid_chunk < 1 || t->grid_chunk > 32))
+      fail(MI_ERR_ARG, "grid_chunk must be 0 or in [1, 32] (got %d)", t->grid_chunk);
+    if (t->fft_elems != 0 && t->fft_elems != FFT_ELEMS_SMALL && t->fft_elems != FFT_ELEMS_LARGE)
+      fail(MI_ERR_ARG, "fft_elems must be 0, %d or %d (got %d)", FFT_ELEMS_SMALL, FFT_ELEMS_LARGE, t->fft_elems);
+    ctx->grid_chunk = t->grid_chunk ? t->grid_chunk : 8;
+    ctx->fft_elems = t->fft_elems;
+  });
+}
+
+mi_status mi_get_tuning(mi_ctx* ctx, mi_tuning* t) {
+  return guard(ctx, [&] {
+    need(t, "tuning");
+    t->grid_chunk = ctx->grid_chunk;
+    t->fft_elems = ctx->fft_elems;
+  });
+}
+
 mi_status mi_profile_begin_kinds(mi_ctx* ctx, uint32_t kinds) {
   return guard(ctx, [&] {
-    const uint32_t all = MI_PROF_CLEAN | MI_PROF_GRID | MI_PROF_IFFT;
+    const uint32_t all = MI_PROF_CLEAN | MI_PROF_GRID | MI_PROF_IFFT | MI_PROF_GRID_FFT;
     if (kinds == 0u || (kinds & ~all)) fail(MI_ERR_ARG, "kinds must be a non-empty mask of MI_PROF_* bits (got %u)", kinds);
     ctx->prof_kinds = kinds;
     ctx->prof_used = 0;
@@ -1080,10 +1167,14 @@ mi_status mi_dirty_image(mi_ctx* ctx, const mi_batch* batch, const mi_c64* vis, 
     HIPCHK(hipSetDevice(ctx->device));
     Plan* P = get_plan(ctx, batch, stream);
     const bool beam = beam_out != nullptr;
-    run_bin(ctx, P, batch, uv, w_in, beam, stream);
-    double2* gd = dev_alloc<double2>(P->gd, P->total_gd);
-    run_grid<double2>(ctx, P, vis, uv, w_in, false, gd, 1, stream);
-    run_image(ctx, P, dirty_out, stream);
+    run_bin(ctx, P, batch, uv, w_in, beam, stream, false, P->fused, vis);
+    if (P->fused) {
+      run_dirty_fused(ctx, P, vis, uv, w_in, dirty_out, stream);
+    } else {
+      double2* gd = dev_alloc<double2>(P->gd, P->total_gd);
+      run_grid<double2>(ctx, P, vis, uv, w_in, false, gd, 1, stream);
+      run_image(ctx, P, dirty_out, stream);
+    }
     if (beam) run_beam(ctx, P, uv, w_in, beam_out, stream);
     copy_b0(P, b0_out, stream);
   });
@@ -1206,7 +1297,7 @@ mi_status mi_dirty_beam(mi_ctx* ctx, const mi_batch* batch, const float* uv, con
     need(beam_out, "beam_out");
     HIPCHK(hipSetDevice(ctx->device));
     Plan* P = get_plan(ctx, batch, stream);
-    run_bin(ctx, P, batch, uv, w_in, true, stream);
+    run_bin(ctx, P, batch, uv, w_in, true, stream, false, P->fused);
     run_beam(ctx, P, uv, w_in, beam_out, stream);
   });
 }
@@ -1507,10 +1598,11 @@ mi_status mi_steer_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty,
     if (!P->steer) {                                   // work lists and workspaces of the batch
       if (capturing(stream)) fail(MI_ERR_UNSUPPORTED, "the first Steer CLEAN call on a batch cannot be captured");
       auto B = std::make_unique<SteerBase>();
+      B->elems = 2 * P->max_N > 4096 ? 8192 : 4096;   // LDS block of the transform passes
       std::vector<FftWork> rows, rows2, cols, pix;
       for (int i = 0; i < n; ++i) {
         const int N = P->n[i], Pn = 2 * N;
-        const int rb = std::min(8, 2 * 8192 / Pn), ncol = 8192 / Pn;
+        const int rb = std::min(8, 2 * B->elems / Pn), ncol = B->elems / Pn;
         B->rb.push_back(rb);
         B->x_off.push_back(B->total_x);
         B->s_off.push_back(B->total_s);
@@ -1519,7 +1611,7 @@ mi_status mi_steer_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty,
         for (int y = 0; y < N; y += rb) rows.push_back({i, y});
         for (int y = 0; y < Pn; y += rb) rows2.push_back({i, y});
         for (int kx = 0; kx <= N; kx += ncol) cols.push_back({i, kx});
-        for (int p = 0; p < N * N; p += 4096) pix.push_back({i, p});
+        for (int p = 0; p < N * N; p += ST_PIX_PER_ITEM) pix.push_back({i, p});
       }
       upload(B->rows, rows);
       upload(B->rows2, rows2);
@@ -1614,20 +1706,20 @@ mi_status mi_steer_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty,
     // the beam's spectrum, then R = dirty and the first peaks
     A.iter = 0;
     A.work = w_rows2;
-    HIPCHK(launch_st_rows(2, B->n_rows2, A, stream));
+    HIPCHK(launch_st_rows(2, B->elems, B->n_rows2, A, stream));
     A.work = w_cols;
-    HIPCHK(launch_st_cols(0, B->n_cols, A, stream));
+    HIPCHK(launch_st_cols(0, B->elems, B->n_cols, A, stream));
     A.work = w_pix;
     HIPCHK(launch_st_init(B->n_pix, A, stream));
     A.iter = 1;
     for (int k = 0; k < S->kmax; ++k) {
       A.k = k;
       A.work = w_rows;
-      HIPCHK(launch_st_rows(0, B->n_rows, A, stream));
+      HIPCHK(launch_st_rows(0, B->elems, B->n_rows, A, stream));
       A.work = w_cols;
-      HIPCHK(launch_st_cols(1, B->n_cols, A, stream));
+      HIPCHK(launch_st_cols(1, B->elems, B->n_cols, A, stream));
       A.work = w_rows;
-      HIPCHK(launch_st_rows_inv(0, B->n_inv, A, stream));
+      HIPCHK(launch_st_rows_inv(0, B->elems, B->n_inv, A, stream));
       A.work = w_pix;
       HIPCHK(launch_st_update(B->n_pix, A, stream));
     }
@@ -1639,15 +1731,15 @@ mi_status mi_steer_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty,
         A.iter = 0;
         A.cbeam = cb;
         A.work = w_rows2;
-        HIPCHK(launch_st_rows(3, B->n_rows2, A, stream));
+        HIPCHK(launch_st_rows(3, B->elems, B->n_rows2, A, stream));
         A.work = w_cols;
-        HIPCHK(launch_st_cols(0, B->n_cols, A, stream));
+        HIPCHK(launch_st_cols(0, B->elems, B->n_cols, A, stream));
         A.work = w_rows;
-        HIPCHK(launch_st_rows(1, B->n_rows, A, stream));
+        HIPCHK(launch_st_rows(1, B->elems, B->n_rows, A, stream));
         A.work = w_cols;
-        HIPCHK(launch_st_cols(1, B->n_cols, A, stream));
+        HIPCHK(launch_st_cols(1, B->elems, B->n_cols, A, stream));
         A.work = w_rows;
-        HIPCHK(launch_st_rows_inv(1, B->n_inv, A, stream));
+        HIPCHK(launch_st_rows_inv(1, B->elems, B->n_inv, A, stream));
       }
     }
   });
@@ -1687,10 +1779,14 @@ mi_status mi_predict_transpose(mi_ctx* ctx, const mi_batch* batch, const mi_c64*
     if (!P->b0_two.p) upload(P->b0_two, std::vector<double>(2 * (size_t)P->n_inst, 2.0));
     // unit weights on the kept samples, the dirty-image transform, then 1/(2 corr) per axis
     // pair instead of 1/(corr B0): Re I_raw / (2 corr) = P^T v
-    run_bin(ctx, P, batch, uv, w_in, false, stream, true);
-    double2* gd = dev_alloc<double2>(P->gd, P->total_gd);
-    run_grid<double2>(ctx, P, vis, uv, w_in, false, gd, 1, stream);
-    run_image(ctx, P, image_out, stream, static_cast<const double*>(P->b0_two.p));
+    run_bin(ctx, P, batch, uv, w_in, false, stream, true, P->fused, vis);
+    if (P->fused) {
+      run_dirty_fused(ctx, P, vis, uv, w_in, image_out, stream, static_cast<const double*>(P->b0_two.p));
+    } else {
+      double2* gd = dev_alloc<double2>(P->gd, P->total_gd);
+      run_grid<double2>(ctx, P, vis, uv, w_in, false, gd, 1, stream);
+      run_image(ctx, P, image_out, stream, static_cast<const double*>(P->b0_two.p));
+    }
   });
 }
 

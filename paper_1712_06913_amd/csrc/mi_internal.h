@@ -44,7 +44,8 @@ struct InstDesc {
   int32_t mode;        // 0 natural, 1 uniform
   int32_t tile_base_d; // first dirty tile of this instance
   int32_t tile_base_b; // first beam tile of this instance
-  int32_t pad0, pad1;
+  int32_t blk_base_d;  // first dirty line block (fused gridding + first transform pass)
+  int32_t blk_base_b;  // first beam line block
 };
 
 // Device-side constant tables (computed on the host in FP64).
@@ -54,6 +55,17 @@ struct Tables {
   const double2* twiddle;  // exp(+2 pi i t / P_MAX), t = 0..P_MAX-1
   const double* inv_corr;  // 1/corr for every P = 64..8192: block for P starts at P - 64
   double inv_corr0_sq;     // 1 / corr(0)^2
+};
+
+// An entry of the fused gridding + first transform pass: one sample (or its Hermitian
+// mirror) for one block of lines, with everything its taps need, read as two 16-byte loads.
+struct GridRec {
+  int cucv;        // (cu << 16) | (cv & 0xffff): the nearest cell (mirror: negated)
+  int ouov;        // ((ou + OS/2) << 8) | (ov + OS/2): the oversampled offsets (mirror: negated)
+  float w;         // the visibility's weight
+  int pad0;
+  float vr, vi;    // its value (mirror: conjugate); (1, 0) for the beam grid
+  float pad1, pad2;
 };
 
 // FFT work item: instance and first line (pass A) or first row (pass B).
@@ -90,6 +102,9 @@ struct CleanArgs {
   unsigned poll_limit;     // polls per team wait before giving up (0: the default)
   int test_stall;          // failure-path tests: member 0 never publishes, every wait times out
 };
+
+// Steer CLEAN: pixels per work item of its elementwise passes (4 per thread, 512 threads).
+constexpr int ST_PIX_PER_ITEM = 2048;
 
 // Steer CLEAN: per-instance layout of the workspaces (built on the host per plan).
 struct SteerInst {

@@ -5,8 +5,10 @@ no allocation, and can replay the step from a captured HIP graph (torch.cuda.CUD
 With threshold="gmm_sky" the step also fits the sky / disk levels of every dirty map
 (Sec. 4.1) and CLEAN stops at the sky level mu_a read on the device (Algorithm 1).
 `autotune_team_size` picks the CLEAN team size (workgroups per image) for a batch shape by
-timing a short proxy run of every candidate; choices are cached by shape key.  (The
-oversampling factor is not a tuning knob: it is part of the method's definition.)
+timing a short proxy run of every candidate; `autotune_imaging` picks the gridder's tiles
+per workgroup and the transform's points per workgroup (mi_set_tuning) by timing the dirty
+image and beam under each candidate; choices are cached by shape key.  (The oversampling
+factor is not a tuning knob: it is part of the method's definition.)
 """
 from __future__ import annotations
 
@@ -61,6 +63,49 @@ def autotune_team_size(batch: api.Batch, dirty, beam, niter, gain=0.1, proxy_ite
     return best
 
 
+_IMG_CACHE: Dict[Tuple, Tuple[int, int]] = {}
+
+
+def imaging_shape_key(batch: api.Batch) -> Tuple:
+    sizes, counts = np.unique(batch.n_img, return_counts=True)
+    per = max(1, int(batch.vis_offset[-1]) // max(1, batch.n_inst))
+    return (tuple(int(s) for s in sizes), tuple(int(c) for c in counts), int(np.log2(per)))
+
+
+def imaging_candidates():
+    """(grid_chunk, fft_elems) pairs: tiles per gridder workgroup x transform block size."""
+    return [(c, e) for e in (0, 8192) for c in (2, 4, 8, 16, 32)]
+
+
+def autotune_imaging(batch: api.Batch, vis, uv, w, reps: int = 3) -> Tuple[int, int]:
+    """Fastest (grid_chunk, fft_elems) for the dirty image + beam of this batch shape; the
+    choice is left set on the batch's context (it applies to every later call there)."""
+    key = imaging_shape_key(batch)
+    if key in _IMG_CACHE:
+        api.set_tuning(batch.ctx, *_IMG_CACHE[key])
+        return _IMG_CACHE[key]
+    dev = batch.device
+    dirty = torch.empty(int(batch.img_off[-1]), dtype=torch.float32, device=dev)
+    beam = torch.empty(int(batch.beam_off[-1]), dtype=torch.float32, device=dev)
+    b0 = torch.empty(2 * batch.n_inst, dtype=torch.float64, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    best, best_t = (8, 0), float("inf")
+    for cand in imaging_candidates():
+        api.set_tuning(batch.ctx, *cand)
+        api.dirty_image(batch, vis, uv, w, beam=True, out=dirty, beam_out=beam, b0_out=b0)   # plan + warm-up
+        ev[0].record()
+        for _ in range(reps):
+            api.dirty_image(batch, vis, uv, w, beam=True, out=dirty, beam_out=beam, b0_out=b0)
+        ev[1].record()
+        torch.cuda.synchronize()
+        t = ev[0].elapsed_time(ev[1]) / reps
+        if t < best_t:
+            best, best_t = cand, t
+    api.set_tuning(batch.ctx, *best)
+    _IMG_CACHE[key] = best
+    return best
+
+
 class ImagingPipeline:
     """One batch descriptor, persistent buffers, eager or graph-replayed steps."""
 
@@ -106,11 +151,13 @@ class ImagingPipeline:
         return self.res
 
     def tune(self):
-        """Pick the CLEAN team size with the autotuner (runs the imaging stage once)."""
+        """Pick the imaging schedule (gridder chunk, transform block) and the CLEAN team size
+        with the autotuners; returns (team size, (grid_chunk, fft_elems))."""
         b = self.batch
+        self.imaging_tuning = autotune_imaging(b, self.vis, self.uv, self.w)
         api.dirty_image(b, self.vis, self.uv, self.w, beam=True, out=self.dirty, beam_out=self.beam, b0_out=self.b0)
         self.team_size = autotune_team_size(b, self.dirty, self.beam, self.niter, self.gain)
-        return self.team_size
+        return self.team_size, self.imaging_tuning
 
     def capture(self):
         """Warm up (plans, workspaces) and capture one step into a HIP graph."""

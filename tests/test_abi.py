@@ -66,3 +66,15 @@ def test_bad_arguments_are_rejected_and_write_nothing():
     with pytest.raises(nat.MiError) as e:
         api.ifft2(torch.zeros(100, dtype=torch.complex64, device="cuda"), [10], [0])
     assert e.value.code == nat.MI_ERR_SHAPE
+    with pytest.raises(nat.MiError) as e:
+        api.steer_clean(b, sentinel, torch.zeros(4 * 64 * 64, device="cuda"), [10], trim=0.0)
+    assert e.value.code == nat.MI_ERR_ARG
+    with pytest.raises(nat.MiError) as e:
+        api.hogbom_clean(b, sentinel, torch.zeros(4 * 64 * 64, device="cuda"), [10], no_alloc=True,
+                         window=np.array([[0, 0, 8, 8]], np.int32))
+    assert e.value.code == nat.MI_ERR_UNSUPPORTED
+    with pytest.raises(nat.MiError) as e:
+        api.set_tuning(b.ctx, 64, 0)
+    assert e.value.code == nat.MI_ERR_ARG
+    torch.cuda.synchronize()
+    assert torch.all(sentinel == 7.0)

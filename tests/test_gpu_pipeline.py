@@ -113,9 +113,12 @@ def test_autotuner_picks_a_working_team_size():
     from paper_1712_06913_amd import pipeline
     wl = synth.c3_muser2(chans=list(range(0, 520, 40)), niter=300)
     pl = pipeline.ImagingPipeline(wl, adjoint=False)
-    ts = pl.tune()
-    log(f"  chose team size {ts} from {pipeline.team_candidates(pl.batch)}")
+    ts, it = pl.tune()
+    log(f"  chose team size {ts} from {pipeline.team_candidates(pl.batch)}, imaging tuning {it}")
     assert ts in pipeline.team_candidates(pl.batch)
+    assert it in pipeline.imaging_candidates()
+    from paper_1712_06913_amd import api
+    assert api.get_tuning(pl.batch.ctx) == (it[0], it[1])
     res = pl.step()
     torch.cuda.synchronize()
     st = pl.batch.status.cpu().numpy()
@@ -150,6 +153,44 @@ def _validate_run(pl, res, tag):
             assert nxt <= thr + eps, f"{tag} inst {i}: stopped with the peak {nxt} above the level {thr}"
             margins[i] = (nxt - thr) / eps
     return margins
+
+
+@pytest.mark.parametrize("grid_chunk,fft_elems", [(1, 0), (32, 0), (8, 8192), (3, 8192)])
+def test_imaging_tuning_choices_match_oracle(grid_chunk, fft_elems):
+    """Every schedule the imaging autotuner can choose gives the same images (to rounding)."""
+    log(f"[pipeline] dirty image + beam with grid_chunk={grid_chunk}, fft_elems={fft_elems}")
+    require_gpu()
+    from paper_1712_06913_amd import api
+    ctx = api.Context(0)
+    try:
+        api.set_tuning(ctx.handle, grid_chunk, fft_elems)
+        wl = synth.random_instances(61, [64, 256, 512, 128], m_range=(200, 400))
+        b = api.Batch.from_workload(wl, ctx=ctx)
+        vis, uv, w = api.workload_tensors(wl)
+        dirty, beam, _ = api.dirty_image(b, vis, uv, w, beam=True)
+        torch.cuda.synchronize()
+        for i in range(wl.n_inst):
+            v, uvi, wi = wl.instance(i)
+            N, cell, mode = int(wl.n_img[i]), float(wl.cell_rad[i]), int(wl.weight_mode[i])
+            ref = imager.dirty_image(v, uvi, wi, N, cell, mode)
+            assert np.max(np.abs(b.split(dirty)[i].cpu().numpy() - ref)) <= 1e-4 * np.max(np.abs(ref))
+            refb = imager.dirty_beam(uvi, wi, N, cell, mode)
+            assert np.max(np.abs(b.split(beam, beam=True)[i].cpu().numpy() - refb)) <= 1e-4
+    finally:
+        ctx.close()
+
+
+def test_tuning_rejects_bad_values():
+    require_gpu()
+    from paper_1712_06913_amd import api, _native as nat
+    ctx = api.Context(0)
+    try:
+        for c, e in ((33, 0), (-1, 0), (8, 2048), (8, 16384)):
+            with pytest.raises(nat.MiError):
+                api.set_tuning(ctx.handle, c, e)
+        assert api.get_tuning(ctx.handle) == (8, 0)
+    finally:
+        ctx.close()
 
 
 def test_gmm_sky_threshold_step_and_graph_replay():

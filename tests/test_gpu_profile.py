@@ -21,19 +21,26 @@ def test_profile_records_the_selected_kinds_in_launch_order():
     dirty, beam, _ = api.dirty_image(b, vis, uv, w, beam=True)        # plans built outside the records
     api.hogbom_clean(b, dirty, beam, wl.niter.astype(np.int32), restore=False)
     torch.cuda.synchronize()
-    G, F, C = nat.MI_PROF_GRID, nat.MI_PROF_IFFT, nat.MI_PROF_CLEAN
+    G, F, C, GF = nat.MI_PROF_GRID, nat.MI_PROF_IFFT, nat.MI_PROF_CLEAN, nat.MI_PROF_GRID_FFT
 
-    api.profile_begin(0, kinds=G | F | C)
+    api.profile_begin(0, kinds=G | F | C | GF)
     dirty, beam, _ = api.dirty_image(b, vis, uv, w, beam=True)
     api.hogbom_clean(b, dirty, beam, wl.niter.astype(np.int32), restore=False)
     ms, kinds = api.profile_end_kinds(0)
     log(f"  kinds {kinds}, ms {[round(t, 3) for t in ms]}")
-    # dirty: grid, pass A, pass B; beam: grid, pass A, pass B; then the Hogbom kernel
-    assert kinds == [G, F, F, G, F, F, C]
+    # dirty: fused gridding + pass A, pass B; beam: the same; then the Hogbom kernel
+    assert kinds == [GF, F, GF, F, C]
     assert all(t > 0.0 for t in ms)
 
     api.profile_begin(0, kinds=F)                  # one kind only
     api.dirty_image(b, vis, uv, w, beam=False, out=dirty)
+    ms, kinds = api.profile_end_kinds(0)
+    assert kinds == [F]
+
+    # the w-projected image grids on its own and runs both transform passes
+    wlam = torch.zeros(len(wl.vis), dtype=torch.float32, device="cuda")
+    api.profile_begin(0, kinds=G | F | GF)
+    api.dirty_image_w(b, vis, uv, wlam, w, np.zeros(wl.n_inst), out=dirty)
     ms, kinds = api.profile_end_kinds(0)
     assert kinds == [F, F]
 
@@ -50,6 +57,6 @@ def test_profile_rejects_bad_masks():
     log("[profile] empty and unknown kind masks are rejected")
     require_gpu()
     from paper_1712_06913_amd import _native as nat, api
-    for bad in (0, 8, 1 | 16):
+    for bad in (0, 16, 1 | 32):
         with pytest.raises(nat.MiError):
             api.profile_begin(0, kinds=bad)
