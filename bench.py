@@ -508,12 +508,13 @@ def main():
         torch.cuda.synchronize()
         sms = ge[0].elapsed_time(ge[1])
         cyc = sres["n_cycle"].cpu().numpy().astype(np.float64)
-        # algorithmic bytes of this design (FP64 spectra): per iteration the residual read
-        # twice and written once, D written and read, the N (N+1) complex row spectra written
-        # and read twice each, and the 2N (N+1) complex beam spectrum read; once per call the
-        # beam's spectrum, the initial copy and the restore through the clean beam's spectrum
+        # algorithmic bytes of this design (spectra stored as FP32 complex between the FP64
+        # transforms): per iteration the residual read twice and written once, D written and
+        # read, the N (N+1) complex row spectra written and read twice each, and the
+        # 2N (N+1) complex beam spectrum read; once per call the beam's spectrum, the
+        # initial copy and the restore through the clean beam's spectrum
         Nf = b.n_img.astype(np.float64)
-        H = Nf * (Nf + 1) * 16.0
+        H = Nf * (Nf + 1) * 8.0
         per_it = 20.0 * Nf ** 2 + 6.0 * H
         once = (16.0 * Nf ** 2 + 6.0 * H) + 16.0 * Nf ** 2 + (12.0 * H + 16.0 * Nf ** 2)
         st_bytes = float(np.sum(per_it * cyc + once))

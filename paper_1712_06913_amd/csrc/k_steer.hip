@@ -7,7 +7,10 @@
 //   alpha = gain peak / max |D|;  model += alpha C;  R -= alpha D.
 //
 // The convolution is a 2N x 2N circular one, which equals the linear one on the cropped
-// rows and columns N..2N-1 (no index wraps there), computed by FFTs in FP64:
+// rows and columns N..2N-1 (no index wraps there), computed by FFTs in FP64 in LDS; the
+// spectra go between the passes as FP32 (there is no grid correction here to amplify their
+// rounding: each store adds a relative error of 2^-24 to a spectrum element, about 1e-7 of
+// the map's RMS in D):
 //   k_st_rows     real rows of C (N nonzero of 2N) -> row spectra, two rows per complex
 //                 FFT, kx = 0..N kept (Hermitian), written as blocks of RB rows;
 //   k_st_cols     per column kx: FFT along y, times the beam spectrum, inverse FFT, rows
@@ -148,13 +151,13 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_rows(SteerArgs A) {
   lds_fft<ST_ELEMS, ST_THREADS>(buf, log2P, nl, -1.0, A.T.twiddle);
   // separate the two rows of each line: Xa = (Z(k) + conj Z(P-k)) / 2, Xb = (Z(k) - conj Z(P-k)) / 2i
   const int log2RB = __builtin_ctz(RB);
-  double2* out = A.X + s.x_off + (int64_t)(y0 >> log2RB) * (N + 1) * RB;
+  float2* out = A.X + s.x_off + (int64_t)(y0 >> log2RB) * (N + 1) * RB;
   for (int q = threadIdx.x; q < (N + 1) * RB; q += ST_THREADS) {
     const int kx = q >> log2RB, r = q & (RB - 1), l = r >> 1;
     const double2 Z = buf[pd(l * P + kx)];
     const double2 Zm = buf[pd(l * P + ((P - kx) & (P - 1)))];
-    out[q] = (r & 1) ? make_double2(0.5 * (Z.y + Zm.y), 0.5 * (Zm.x - Z.x))
-                     : make_double2(0.5 * (Z.x + Zm.x), 0.5 * (Z.y - Zm.y));
+    out[q] = (r & 1) ? make_float2((float)(0.5 * (Z.y + Zm.y)), (float)(0.5 * (Zm.x - Z.x)))
+                     : make_float2((float)(0.5 * (Z.x + Zm.x)), (float)(0.5 * (Z.y - Zm.y)));
   }
 }
 
@@ -178,7 +181,7 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_cols(SteerArgs A) {
   const int kx0 = wk.first;
   const int nc = min(ST_ELEMS >> log2P, N + 1 - kx0);
   const int Rin = MODE == 0 ? P : N;
-  double2* X = A.X + s.x_off;
+  float2* X = A.X + s.x_off;
   // element q = (yb nc + c) RB + r: row yb RB + r of column kx0 + c; for each block of rows
   // the nc columns' entries are contiguous in memory
   const int run = nc * RB;
@@ -186,27 +189,34 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_cols(SteerArgs A) {
     const int yb = q / run, rem = q - yb * run, c = rem >> log2RB, r = rem & (RB - 1);
     const int y = (yb << log2RB) + r;
     double2 v = make_double2(0.0, 0.0);
-    if (y < Rin) v = X[(int64_t)yb * (N + 1) * RB + (int64_t)(kx0 + c) * RB + r];
+    if (y < Rin) {
+      const float2 f = X[(int64_t)yb * (N + 1) * RB + (int64_t)(kx0 + c) * RB + r];
+      v = make_double2((double)f.x, (double)f.y);
+    }
     buf[pd((c << log2P) + y)] = v;
   }
   __syncthreads();
   lds_fft<ST_ELEMS, ST_THREADS>(buf, log2P, nc, -1.0, A.T.twiddle);
-  double2* Sc = A.S + s.s_off + (int64_t)kx0 * P;
+  float2* Sc = A.S + s.s_off + (int64_t)kx0 * P;
   if (MODE == 0) {
     const double sc = 1.0 / ((double)P * (double)P);
     for (int q = threadIdx.x; q < nc * P; q += ST_THREADS) {
       const double2 v = buf[pd(q)];
-      Sc[q] = make_double2(v.x * sc, v.y * sc);
+      Sc[q] = make_float2((float)(v.x * sc), (float)(v.y * sc));
     }
     return;
   }
-  for (int q = threadIdx.x; q < nc * P; q += ST_THREADS) buf[pd(q)] = cmul(buf[pd(q)], Sc[q]);
+  for (int q = threadIdx.x; q < nc * P; q += ST_THREADS) {
+    const float2 f = Sc[q];
+    buf[pd(q)] = cmul(buf[pd(q)], make_double2((double)f.x, (double)f.y));
+  }
   __syncthreads();
   lds_fft<ST_ELEMS, ST_THREADS>(buf, log2P, nc, +1.0, A.T.twiddle);
   for (int q = threadIdx.x; q < (N / RB) * run; q += ST_THREADS) {
     const int yb = q / run, rem = q - yb * run, c = rem >> log2RB, r = rem & (RB - 1);
     const int y = (yb << log2RB) + r;
-    X[(int64_t)yb * (N + 1) * RB + (int64_t)(kx0 + c) * RB + r] = buf[pd((c << log2P) + N + y)];
+    const double2 v = buf[pd((c << log2P) + N + y)];
+    X[(int64_t)yb * (N + 1) * RB + (int64_t)(kx0 + c) * RB + r] = make_float2((float)v.x, (float)v.y);
   }
 }
 
@@ -228,10 +238,11 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_rows_inv(SteerArgs A) {
   }
   const int N = d.N, P = 2 * N, log2P = d.log2N + 1, RB = s.rb, nl = RB / 2, log2nl = __builtin_ctz(nl);
   const int j0 = wk.first;
-  const double2* in = A.X + s.x_off + (int64_t)(j0 / RB) * (N + 1) * RB;
+  const float2* in = A.X + s.x_off + (int64_t)(j0 / RB) * (N + 1) * RB;
   for (int q = threadIdx.x; q < (N + 1) * nl; q += ST_THREADS) {
     const int kx = q >> log2nl, l = q & (nl - 1);
-    double2 a = in[kx * RB + 2 * l], b = in[kx * RB + 2 * l + 1];
+    const float2 fa = in[kx * RB + 2 * l], fb = in[kx * RB + 2 * l + 1];
+    double2 a = make_double2((double)fa.x, (double)fa.y), b = make_double2((double)fb.x, (double)fb.y);
     if (kx == 0 || kx == N) { a.y = 0.0; b.y = 0.0; }      // real by symmetry
     const int row = l << log2P;
     buf[pd(row + kx)] = make_double2(a.x - b.y, a.y + b.x);

@@ -1621,8 +1621,8 @@ mi_status mi_steer_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty,
       B->n_rows2 = (int)rows2.size();
       B->n_cols = (int)cols.size();
       B->n_pix = (int)pix.size();
-      dev_alloc<double2>(B->X, (size_t)B->total_x);
-      dev_alloc<double2>(B->S, (size_t)B->total_s);
+      dev_alloc<float2>(B->X, (size_t)B->total_x);
+      dev_alloc<float2>(B->S, (size_t)B->total_s);
       dev_alloc<float>(B->D, (size_t)P->total_img);
       P->steer = std::move(B);
     }
@@ -1691,8 +1691,8 @@ mi_status mi_steer_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty,
     A.R = residual_out;
     A.model = model_out ? model_out : dev_alloc<double>(B->model_ws, (size_t)P->total_img);
     A.D = static_cast<float*>(B->D.p);
-    A.X = static_cast<double2*>(B->X.p);
-    A.S = static_cast<double2*>(B->S.p);
+    A.X = static_cast<float2*>(B->X.p);
+    A.S = static_cast<float2*>(B->S.p);
     A.ctl = static_cast<unsigned*>(S->ctl.p);
     A.log = log_out;
     A.mask = mask_out;

@@ -108,8 +108,8 @@ constexpr int ST_PIX_PER_ITEM = 2048;
 
 // Steer CLEAN: per-instance layout of the workspaces (built on the host per plan).
 struct SteerInst {
-  int64_t x_off;     // blocked row spectra (complex FP64): 2N blocks of rows x (N+1) columns
-  int64_t s_off;     // spectrum of the beam / clean beam (complex FP64): (N+1) columns x 2N
+  int64_t x_off;     // blocked row spectra (complex, stored FP32): 2N rows x (N+1) columns
+  int64_t s_off;     // spectrum of the beam / clean beam (complex, stored FP32): (N+1) columns x 2N
   int64_t ctl_off;   // u32 control words: [0], [1] peak keys by iteration parity, [2] max |D| key,
                      // [3] unused, [4 + k] pixels selected in iteration k
   int64_t log_off;   // doubles: (peak, alpha, count) per iteration
@@ -136,8 +136,8 @@ struct SteerArgs {
   float* R;                // residual (the caller's output, updated in place)
   double* model;
   float* D;                // convolution of this iteration's components with the beam, N^2
-  double2* X;
-  double2* S;
+  float2* X;               // spectra between the passes (transforms run in FP64 in LDS)
+  float2* S;
   unsigned* ctl;
   double* log;             // or null
   unsigned* mask;          // or null
