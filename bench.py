@@ -178,13 +178,15 @@ def cpu_baseline_full():
     for name, wl, k in (("c2", synth.c2_muser1_batch(), 16), ("c3", synth.c3_muser2(), 4), ("c4", synth.c4_uneven(), 16)):
         jobs = [_oracle_args(wl, i) for i in range(k)]
         t0 = time.perf_counter()
-        for a in jobs:
+        for j, a in enumerate(jobs):
             oracle_image(a)
+            log(f"oracle {name}: instance {j} on one core done")
         t1 = time.perf_counter() - t0
         cores = min(host_cores(), k)
         t0 = time.perf_counter()
         with cf.ProcessPoolExecutor(max_workers=cores) as ex:
-            list(ex.map(oracle_image, jobs))
+            for j, _ in enumerate(cf.as_completed([ex.submit(oracle_image, a) for a in jobs])):
+                log(f"oracle {name}: {j + 1} of {k} instances over {cores} processes done")
         tn = time.perf_counter() - t0
         out[name] = {"instances_timed": k, "of": wl.n_inst, "one_core_s": t1, "one_core_images_per_s": k / t1,
                      "cores": cores, "all_cores_s": tn, "all_cores_images_per_s": k / tn,

@@ -248,7 +248,8 @@ mi_status mi_hogbom_clean_noalloc(mi_ctx* ctx, const mi_batch* batch, const floa
 /* Steer CLEAN with restore (Sec. 2, Sec. 4.3; Algorithm 1's deconvolver).  Per iteration:
  *   peak = max |R| (max R with positive_only); stop if peak <= threshold;
  *   C = R on the pixels with |R| >= trim peak (R >= trim peak), 0 elsewhere (FP64 test);
- *   D[y][x] = sum_q C[q] beam[y - q_y + N][x - q_x + N]  (linear convolution, FP64 FFTs);
+ *   D[y][x] = sum_q C[q] beam[y - q_y + N][x - q_x + N]  (linear convolution by FP32 FFTs
+ *     with FP64 twiddles: D is within about 1e-7 of max |D|);
  *   alpha = gain peak / max |D| (stop if D = 0);  model += alpha C;  R -= alpha D.
  * So an isolated point is subtracted exactly as a Hogbom step, and a selection covering an
  * extended source never removes more than gain x peak at any pixel.
@@ -264,7 +265,8 @@ mi_status mi_hogbom_clean_noalloc(mi_ctx* ctx, const mi_batch* batch, const floa
  *     to the beam's main lobe, as in mi_hogbom_clean, over the whole map);
  *   cbeam_out (optional): double [n_inst][6] as in mi_hogbom_clean.
  * Every image of the batch advances one iteration per launch sequence (four launches per
- * iteration, up to the largest ncycle); workspace per N x N image: about 68 N^2 bytes.  */
+ * iteration, up to the largest ncycle); workspace per N x N image: about 36 N^2 bytes (44 N^2
+ * without model_out).  */
 mi_status mi_steer_clean(mi_ctx* ctx, const mi_batch* batch, const float* dirty, const float* beam,
                          const mi_steer_params* params, float* residual_out, double* model_out,
                          int32_t* n_cycle_out, double* log_out, uint32_t* mask_out, float* restored_out,

@@ -5,7 +5,8 @@
 // A radix-R pass over nl lines of P points in LDS (line stride P, one padding element per
 // 8 against bank conflicts) reads butterfly b's inputs x[b + m P/R] and writes
 // y[(b/L) L R + b%L + q L] after twiddling by w^m, w = exp(s 2 pi i (b%L)/(L R)); twiddles
-// come from the FP64 table exp(+2 pi i t / 8192) and their powers by recurrence.
+// come from the FP64 table exp(+2 pi i t / 8192) and their powers by recurrence.  The
+// values are double2 (FP64) or float2 (FP32): the twiddles are always computed in FP64.
 #pragma once
 
 #include "mi_internal.h"
@@ -21,33 +22,55 @@ __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_doub
 // multiply by s*i (s = +1 or -1)
 __device__ __forceinline__ double2 mul_si(double2 a, double s) { return make_double2(-s * a.y, s * a.x); }
 
-template <int R> __device__ __forceinline__ void small_dft(double2* x, double s);
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 mul_si(float2 a, double s) {
+  const float f = (float)s;
+  return make_float2(-f * a.y, f * a.x);
+}
 
-template <> __device__ __forceinline__ void small_dft<2>(double2* x, double) {
+// A twiddle (computed in FP64) in the precision of the data.
+template <typename V> __device__ __forceinline__ V tw_as(double2 w);
+template <> __device__ __forceinline__ double2 tw_as<double2>(double2 w) { return w; }
+template <> __device__ __forceinline__ float2 tw_as<float2>(double2 w) { return make_float2((float)w.x, (float)w.y); }
+
+template <int R, typename V> __device__ __forceinline__ void small_dft(V* x, double s);
+
+template <> __device__ __forceinline__ void small_dft<2, double2>(double2* x, double) {
   double2 a = x[0], b = x[1];
   x[0] = cadd(a, b);
   x[1] = csub(a, b);
 }
+template <> __device__ __forceinline__ void small_dft<2, float2>(float2* x, double) {
+  float2 a = x[0], b = x[1];
+  x[0] = cadd(a, b);
+  x[1] = csub(a, b);
+}
 
-template <> __device__ __forceinline__ void small_dft<4>(double2* x, double s) {
-  double2 t0 = cadd(x[0], x[2]), t1 = csub(x[0], x[2]);
-  double2 t2 = cadd(x[1], x[3]), t3 = mul_si(csub(x[1], x[3]), s);
+template <typename V> __device__ __forceinline__ void dft4(V* x, double s) {
+  V t0 = cadd(x[0], x[2]), t1 = csub(x[0], x[2]);
+  V t2 = cadd(x[1], x[3]), t3 = mul_si(csub(x[1], x[3]), s);
   x[0] = cadd(t0, t2);
   x[2] = csub(t0, t2);
   x[1] = cadd(t1, t3);
   x[3] = csub(t1, t3);
 }
+template <> __device__ __forceinline__ void small_dft<4, double2>(double2* x, double s) { dft4(x, s); }
+template <> __device__ __forceinline__ void small_dft<4, float2>(float2* x, double s) { dft4(x, s); }
 
-template <> __device__ __forceinline__ void small_dft<8>(double2* x, double s) {
-  double2 e[4] = {x[0], x[2], x[4], x[6]};
-  double2 o[4] = {x[1], x[3], x[5], x[7]};
-  small_dft<4>(e, s);
-  small_dft<4>(o, s);
+template <typename V> __device__ __forceinline__ void dft8(V* x, double s) {
+  V e[4] = {x[0], x[2], x[4], x[6]};
+  V o[4] = {x[1], x[3], x[5], x[7]};
+  dft4(e, s);
+  dft4(o, s);
   const double r = 0.70710678118654752440;
   // w8^q = exp(s i pi q / 4)
-  double2 o1 = cmul(o[1], make_double2(r, s * r));
-  double2 o2 = mul_si(o[2], s);
-  double2 o3 = cmul(o[3], make_double2(-r, s * r));
+  V o1 = cmul(o[1], tw_as<V>(make_double2(r, s * r)));
+  V o2 = mul_si(o[2], s);
+  V o3 = cmul(o[3], tw_as<V>(make_double2(-r, s * r)));
   x[0] = cadd(e[0], o[0]);
   x[4] = csub(e[0], o[0]);
   x[1] = cadd(e[1], o1);
@@ -57,6 +80,8 @@ template <> __device__ __forceinline__ void small_dft<8>(double2* x, double s) {
   x[3] = cadd(e[3], o3);
   x[7] = csub(e[3], o3);
 }
+template <> __device__ __forceinline__ void small_dft<8, double2>(double2* x, double s) { dft8(x, s); }
+template <> __device__ __forceinline__ void small_dft<8, float2>(float2* x, double s) { dft8(x, s); }
 
 // LDS index with one padding element per 8: strided butterfly stores of 16-byte elements
 // otherwise land on the same banks.  (A further element per line, against conflicts in
@@ -66,9 +91,10 @@ __device__ __forceinline__ int pd(int i) { return i + (i >> 3); }
 // One Stockham radix-R pass over nl lines of P points held in LDS (line stride P).
 // L = product of the radices already applied.  Butterfly b of a line reads x[b + m P/R]
 // and writes y[(b/L) L R + b%L + q L] after twiddling by w^m, w = exp(s 2 pi i (b%L)/(L R));
-// w comes from the FP64 table and its powers by recurrence.
-template <int R, int ELEMS, int THREADS>
-__device__ __forceinline__ void stockham_pass(double2* buf, int log2P, int log2L, int nl, double s,
+// w comes from the FP64 table and its powers by recurrence in FP64, each rounded once to
+// the data's precision (V = double2 or float2).
+template <int R, int ELEMS, int THREADS, typename V>
+__device__ __forceinline__ void stockham_pass(V* buf, int log2P, int log2L, int nl, double s,
                                               const double2* __restrict__ tw) {
   constexpr int BPT = (ELEMS / THREADS / R) > 0 ? ELEMS / THREADS / R : 1;
   constexpr int LOG2R = R == 8 ? 3 : (R == 4 ? 2 : 1);
@@ -77,7 +103,7 @@ __device__ __forceinline__ void stockham_pass(double2* buf, int log2P, int log2L
   const int total = nl << log2nb;
   const int L = 1 << log2L;
   const int tw_shift = (13 - log2L - LOG2R);   // table length 8192 = 2^13
-  double2 x[BPT][R];
+  V x[BPT][R];
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
     const int b = threadIdx.x + q * THREADS;
@@ -99,14 +125,14 @@ __device__ __forceinline__ void stockham_pass(double2* buf, int log2P, int log2L
         double2 w1 = tw[j << tw_shift];
         w1.y *= s;
         double2 w = w1;
-        x[q][1] = cmul(x[q][1], w);
+        x[q][1] = cmul(x[q][1], tw_as<V>(w));
 #pragma unroll
         for (int m = 2; m < R; ++m) {
           w = cmul(w, w1);
-          x[q][m] = cmul(x[q][m], w);
+          x[q][m] = cmul(x[q][m], tw_as<V>(w));
         }
       }
-      small_dft<R>(x[q], s);
+      small_dft<R, V>(x[q], s);
       const int base = (line << log2P) + (blk << (log2L + LOG2R)) + j;
 #pragma unroll
       for (int m = 0; m < R; ++m) buf[pd(base + (m << log2L))] = x[q][m];
@@ -116,8 +142,8 @@ __device__ __forceinline__ void stockham_pass(double2* buf, int log2P, int log2L
 }
 
 // Full length-P FFT (sign s) of nl lines in LDS; nl * P <= ELEMS.
-template <int ELEMS, int THREADS>
-__device__ __forceinline__ void lds_fft(double2* buf, int log2P, int nl, double s, const double2* __restrict__ tw) {
+template <int ELEMS, int THREADS, typename V>
+__device__ __forceinline__ void lds_fft(V* buf, int log2P, int nl, double s, const double2* __restrict__ tw) {
   int done = 0, rem = log2P;
   while (rem > 0) {
     const int r = (rem == 4 || rem == 2) ? 2 : (rem == 1 ? 1 : 3);

@@ -7,10 +7,12 @@
 //   alpha = gain peak / max |D|;  model += alpha C;  R -= alpha D.
 //
 // The convolution is a 2N x 2N circular one, which equals the linear one on the cropped
-// rows and columns N..2N-1 (no index wraps there), computed by FFTs in FP64 in LDS; the
-// spectra go between the passes as FP32 (there is no grid correction here to amplify their
-// rounding: each store adds a relative error of 2^-24 to a spectrum element, about 1e-7 of
-// the map's RMS in D):
+// rows and columns N..2N-1 (no index wraps there), computed by FP32 FFTs in LDS with
+// twiddles computed in FP64 and rounded once; the spectra go between the passes as FP32.
+// There is no grid correction here to amplify rounding: the FP32 transforms put an error of
+// about 1e-7 of max |D| into D, so alpha D, whose largest value is gain x peak, is off by
+// about 1e-8 of the peak per iteration, against the 1e-5 x peak to which each selection is
+// checked and the 1e-4 x peak of the maps:
 //   k_st_rows     real rows of C (N nonzero of 2N) -> row spectra, two rows per complex
 //                 FFT, kx = 0..N kept (Hermitian), written as blocks of RB rows;
 //   k_st_cols     per column kx: FFT along y, times the beam spectrum, inverse FFT, rows
@@ -33,8 +35,8 @@
 namespace mi {
 
 constexpr int ST_THREADS = 512;
-// Complex doubles staged per workgroup: 4096 (72 KB with padding, two workgroups per compute
-// unit) for transforms up to 4096 points, 8192 (144 KB) for 8192-point ones (N = 4096).
+// Complex floats staged per workgroup: 4096 (36 KB with padding, four workgroups per compute
+// unit) for transforms up to 4096 points, 8192 (72 KB) for 8192-point ones (N = 4096).
 constexpr int st_lds(int elems) { return elems + elems / 8; }
 
 namespace {
@@ -90,7 +92,7 @@ __device__ __forceinline__ bool st_sel(float v, double tp, int posonly) {
 //           dy = y - N (2N rows of 2N).
 template <int MODE, int ST_ELEMS>
 __global__ void __launch_bounds__(ST_THREADS) k_st_rows(SteerArgs A) {
-  __shared__ double2 buf[st_lds(ST_ELEMS)];
+  __shared__ float2 buf[st_lds(ST_ELEMS)];
   __shared__ unsigned n_sel;
   const FftWork wk = A.work[blockIdx.x];
   const int i = wk.inst;
@@ -140,7 +142,7 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_rows(SteerArgs A) {
         }
       }
     }
-    buf[pd(q)] = make_double2(v[0], v[1]);
+    buf[pd(q)] = make_float2((float)v[0], (float)v[1]);
   }
   if (MODE == 0) {
     for (int o = 32; o > 0; o >>= 1) cnt += (unsigned)__shfl_xor((int)cnt, o);
@@ -154,10 +156,10 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_rows(SteerArgs A) {
   float2* out = A.X + s.x_off + (int64_t)(y0 >> log2RB) * (N + 1) * RB;
   for (int q = threadIdx.x; q < (N + 1) * RB; q += ST_THREADS) {
     const int kx = q >> log2RB, r = q & (RB - 1), l = r >> 1;
-    const double2 Z = buf[pd(l * P + kx)];
-    const double2 Zm = buf[pd(l * P + ((P - kx) & (P - 1)))];
-    out[q] = (r & 1) ? make_float2((float)(0.5 * (Z.y + Zm.y)), (float)(0.5 * (Zm.x - Z.x)))
-                     : make_float2((float)(0.5 * (Z.x + Zm.x)), (float)(0.5 * (Z.y - Zm.y)));
+    const float2 Z = buf[pd(l * P + kx)];
+    const float2 Zm = buf[pd(l * P + ((P - kx) & (P - 1)))];
+    out[q] = (r & 1) ? make_float2(0.5f * (Z.y + Zm.y), 0.5f * (Zm.x - Z.x))
+                     : make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
   }
 }
 
@@ -168,7 +170,7 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_rows(SteerArgs A) {
 //           N..2N-1 written back over rows 0..N-1 of the same columns.
 template <int MODE, int ST_ELEMS>
 __global__ void __launch_bounds__(ST_THREADS) k_st_cols(SteerArgs A) {
-  __shared__ double2 buf[st_lds(ST_ELEMS)];
+  __shared__ float2 buf[st_lds(ST_ELEMS)];
   const FftWork wk = A.work[blockIdx.x];
   const int i = wk.inst;
   const InstDesc d = A.inst[i];
@@ -188,35 +190,27 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_cols(SteerArgs A) {
   for (int q = threadIdx.x; q < (P / RB) * run; q += ST_THREADS) {
     const int yb = q / run, rem = q - yb * run, c = rem >> log2RB, r = rem & (RB - 1);
     const int y = (yb << log2RB) + r;
-    double2 v = make_double2(0.0, 0.0);
-    if (y < Rin) {
-      const float2 f = X[(int64_t)yb * (N + 1) * RB + (int64_t)(kx0 + c) * RB + r];
-      v = make_double2((double)f.x, (double)f.y);
-    }
-    buf[pd((c << log2P) + y)] = v;
+    buf[pd((c << log2P) + y)] =
+        y < Rin ? X[(int64_t)yb * (N + 1) * RB + (int64_t)(kx0 + c) * RB + r] : make_float2(0.0f, 0.0f);
   }
   __syncthreads();
   lds_fft<ST_ELEMS, ST_THREADS>(buf, log2P, nc, -1.0, A.T.twiddle);
   float2* Sc = A.S + s.s_off + (int64_t)kx0 * P;
   if (MODE == 0) {
-    const double sc = 1.0 / ((double)P * (double)P);
+    const float sc = 1.0f / ((float)P * (float)P);     // a power of two: exact
     for (int q = threadIdx.x; q < nc * P; q += ST_THREADS) {
-      const double2 v = buf[pd(q)];
-      Sc[q] = make_float2((float)(v.x * sc), (float)(v.y * sc));
+      const float2 v = buf[pd(q)];
+      Sc[q] = make_float2(v.x * sc, v.y * sc);
     }
     return;
   }
-  for (int q = threadIdx.x; q < nc * P; q += ST_THREADS) {
-    const float2 f = Sc[q];
-    buf[pd(q)] = cmul(buf[pd(q)], make_double2((double)f.x, (double)f.y));
-  }
+  for (int q = threadIdx.x; q < nc * P; q += ST_THREADS) buf[pd(q)] = cmul(buf[pd(q)], Sc[q]);
   __syncthreads();
   lds_fft<ST_ELEMS, ST_THREADS>(buf, log2P, nc, +1.0, A.T.twiddle);
   for (int q = threadIdx.x; q < (N / RB) * run; q += ST_THREADS) {
     const int yb = q / run, rem = q - yb * run, c = rem >> log2RB, r = rem & (RB - 1);
     const int y = (yb << log2RB) + r;
-    const double2 v = buf[pd((c << log2P) + N + y)];
-    X[(int64_t)yb * (N + 1) * RB + (int64_t)(kx0 + c) * RB + r] = make_float2((float)v.x, (float)v.y);
+    X[(int64_t)yb * (N + 1) * RB + (int64_t)(kx0 + c) * RB + r] = buf[pd((c << log2P) + N + y)];
   }
 }
 
@@ -226,7 +220,7 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_cols(SteerArgs A) {
 //   MODE 1: the restored image R + result.
 template <int MODE, int ST_ELEMS>
 __global__ void __launch_bounds__(ST_THREADS) k_st_rows_inv(SteerArgs A) {
-  __shared__ double2 buf[st_lds(ST_ELEMS)];
+  __shared__ float2 buf[st_lds(ST_ELEMS)];
   __shared__ unsigned red[ST_THREADS / 64];
   const FftWork wk = A.work[blockIdx.x];
   const int i = wk.inst;
@@ -241,12 +235,11 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_rows_inv(SteerArgs A) {
   const float2* in = A.X + s.x_off + (int64_t)(j0 / RB) * (N + 1) * RB;
   for (int q = threadIdx.x; q < (N + 1) * nl; q += ST_THREADS) {
     const int kx = q >> log2nl, l = q & (nl - 1);
-    const float2 fa = in[kx * RB + 2 * l], fb = in[kx * RB + 2 * l + 1];
-    double2 a = make_double2((double)fa.x, (double)fa.y), b = make_double2((double)fb.x, (double)fb.y);
-    if (kx == 0 || kx == N) { a.y = 0.0; b.y = 0.0; }      // real by symmetry
+    float2 a = in[kx * RB + 2 * l], b = in[kx * RB + 2 * l + 1];
+    if (kx == 0 || kx == N) { a.y = 0.0f; b.y = 0.0f; }    // real by symmetry
     const int row = l << log2P;
-    buf[pd(row + kx)] = make_double2(a.x - b.y, a.y + b.x);
-    if (kx > 0 && kx < N) buf[pd(row + P - kx)] = make_double2(a.x + b.y, b.x - a.y);
+    buf[pd(row + kx)] = make_float2(a.x - b.y, a.y + b.x);
+    if (kx > 0 && kx < N) buf[pd(row + P - kx)] = make_float2(a.x + b.y, b.x - a.y);
   }
   __syncthreads();
   lds_fft<ST_ELEMS, ST_THREADS>(buf, log2P, nl, +1.0, A.T.twiddle);
@@ -254,12 +247,12 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_rows_inv(SteerArgs A) {
   const int log2N = d.log2N;
   for (int q = threadIdx.x; q < nl * N; q += ST_THREADS) {
     const int l = q >> log2N, x = q & (N - 1);
-    const double2 z = buf[pd((l << log2P) + N + x)];
+    const float2 z = buf[pd((l << log2P) + N + x)];
     const int64_t o = d.img_off + (int64_t)(j0 + 2 * l) * N + x;
     if (MODE == 0) {
-      A.D[o] = (float)z.x;
-      A.D[o + N] = (float)z.y;
-      m = max(m, fkey((float)fmax(fabs(z.x), fabs(z.y))));
+      A.D[o] = z.x;
+      A.D[o + N] = z.y;
+      m = max(m, fkey(fmaxf(fabsf(z.x), fabsf(z.y))));
     } else {
       A.restored[o] = (float)((double)A.R[o] + z.x);
       A.restored[o + N] = (float)((double)A.R[o + N] + z.y);
