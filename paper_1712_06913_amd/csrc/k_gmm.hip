@@ -24,16 +24,35 @@ constexpr int GMM_MAX_BINS = 4096;
 
 namespace {
 
+// A double moved between lanes by a DPP pattern (both 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the wave, the same in every lane: within each row of 16 lanes by DPP (lane
+// i ^ 1, i ^ 2, then the mirrored lane of the half row and of the row), then the four row
+// sums read from lanes 0, 16, 32, 48.
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  v += dpp_f64<0xb1>(v);     // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4e>(v);     // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x141>(v);    // row_half_mirror
+  v += dpp_f64<0x140>(v);    // row_mirror
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  double t = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    t += __hiloint2double(__builtin_amdgcn_readlane(hi, 16 * r), __builtin_amdgcn_readlane(lo, 16 * r));
+  return t;
 }
 
 // Sum of NV doubles over the workgroup with one barrier: wave sums go to one of two
 // scratch buffers (alternating between calls, so a buffer is rewritten only after a later
 // barrier has passed); every thread then adds the wave sums in wave order.
 template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double (*scratch)[4][GMM_WAVES], int& parity) {
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (*scratch)[6][GMM_WAVES], int& parity) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
@@ -51,19 +70,34 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*scratch)[4][
   parity ^= 1;
 }
 
+// 1 / x and 1 / sqrt(x) for positive normal x: the hardware estimates refined by Newton
+// steps to within an ulp or two (the EM's sums carry far more rounding than that)
+__device__ __forceinline__ double rcp_f64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ double rsqrt_f64(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  // r <- r (3 - x r^2) / 2, three times from the estimate
+  for (int k = 0; k < 3; ++k) r = r * fma(-0.5 * x * r, r, 1.5);
+  return r;
+}
+
 }  // namespace
 
 // One workgroup of 256 threads per map, BPT bins per thread (8 for up to 2048 bins, so
 // that three workgroups share a compute unit and all maps of a 520-map batch are resident
 // at once).  The E step needs one exponential per bin (the larger of the two log terms
-// gives exp(0) = 1 exactly), and each of the two workgroup sums per iteration takes one
-// barrier.
+// gives exp(0) = 1 exactly), and an iteration's sums take one workgroup reduction, i.e.
+// one barrier.
 template <int GMM_BPT>
 __global__ void __launch_bounds__(GMM_THREADS)
 k_gmm(const InstDesc* __restrict__ inst, const float* __restrict__ images, int n_bins, int n_iter,
       double* __restrict__ levels, float* __restrict__ mu_a_out, float* __restrict__ mu_b_out) {
   __shared__ unsigned hist[GMM_MAX_BINS];
-  __shared__ double scratch[2][4][GMM_WAVES];
+  __shared__ double scratch[2][6][GMM_WAVES];
   __shared__ float mm[2][GMM_WAVES];
   __shared__ int qbin[2];
   const int i = blockIdx.x;
@@ -163,17 +197,27 @@ k_gmm(const InstDesc* __restrict__ inst, const float* __restrict__ images, int n
   double var[2] = {var_all, var_all};
   double pi[2] = {0.5, 0.5};
   const double LOG2PI = 1.8378770664093454836;
+  // The M step's sums in one workgroup reduction: per component n r, n r x', n r x'^2 with
+  // x' = x - xm (xm = the range's centre, so |x'| <= span / 2), and the variance about the
+  // new mean as sum n r x'^2 / nk - m'^2 (equal to sum n r (x - mk)^2 / nk; the shift keeps
+  // the cancellation small: a relative error of about 1e-16 (span / 2)^2 / var)
+  const double xm = lo + 0.5 * span;
+  double xs[GMM_BPT];
+#pragma unroll
+  for (int b = 0; b < GMM_BPT; ++b) xs[b] = xc[b] - xm;
+  const double inv_total = 1.0 / total;
   for (int t = 0; t < n_iter; ++t) {
+    // log(pi / sqrt(2 pi var)) and 1 / (2 var): one logarithm and one reciprocal square
+    // root per component (each iteration's serial part is short)
     double c0[2], iv[2];
     for (int k = 0; k < 2; ++k) {
-      c0[k] = log(pi[k]) - 0.5 * (LOG2PI + log(var[k]));
-      iv[k] = 0.5 / var[k];
+      const double rs = rsqrt_f64(var[k]);
+      c0[k] = log(pi[k] * rs) - 0.5 * LOG2PI;
+      iv[k] = 0.5 * rs * rs;
     }
-    double r0[GMM_BPT], r1[GMM_BPT];
-    double a[4] = {0.0, 0.0, 0.0, 0.0};              // n r_0, n r_0 x, n r_1, n r_1 x
+    double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int b = 0; b < GMM_BPT; ++b) {
-      r0[b] = r1[b] = 0.0;
       // an empty bin adds nothing to any sum; a wave whose 64 bins are all empty (the long
       // bright tail of a dirty map's histogram) skips the exponential altogether
       if (b < nb && cnt[b] > 0.0) {
@@ -186,32 +230,25 @@ k_gmm(const InstDesc* __restrict__ inst, const float* __restrict__ images, int n
         double inv = __builtin_amdgcn_rcp(den);
         inv = fma(inv, fma(-den, inv, 1.0), inv);
         inv = fma(inv, fma(-den, inv, 1.0), inv);
-        r0[b] = l0 >= l1 ? inv : e * inv;
-        r1[b] = l0 >= l1 ? e * inv : inv;
-        a[0] += cnt[b] * r0[b];
-        a[1] += cnt[b] * r0[b] * xc[b];
-        a[2] += cnt[b] * r1[b];
-        a[3] += cnt[b] * r1[b] * xc[b];
+        const double w0 = cnt[b] * (l0 >= l1 ? inv : e * inv);
+        const double w1 = cnt[b] * (l0 >= l1 ? e * inv : inv);
+        a[0] += w0;
+        a[1] += w0 * xs[b];
+        a[2] += w0 * xs[b] * xs[b];
+        a[3] += w1;
+        a[4] += w1 * xs[b];
+        a[5] += w1 * xs[b] * xs[b];
       }
     }
-    block_sum<4>(a, scratch, parity);
-    const double nk[2] = {a[0], a[2]};
-    const double mk[2] = {nk[0] > 0.0 ? a[1] / nk[0] : mu[0], nk[1] > 0.0 ? a[3] / nk[1] : mu[1]};
-    double v[2] = {0.0, 0.0};
-#pragma unroll
-    for (int b = 0; b < GMM_BPT; ++b) {
-      if (b < nb && cnt[b] > 0.0) {
-        const double d0 = xc[b] - mk[0], d1 = xc[b] - mk[1];
-        v[0] += cnt[b] * r0[b] * d0 * d0;
-        v[1] += cnt[b] * r1[b] * d1 * d1;
-      }
-    }
-    block_sum<2>(v, scratch, parity);
+    block_sum<6>(a, scratch, parity);
     for (int k = 0; k < 2; ++k) {
-      if (!(nk[k] > 0.0)) continue;
-      mu[k] = mk[k];
-      var[k] = fmax(v[k] / nk[k], floor_var);
-      pi[k] = nk[k] / total;
+      const double nk = a[3 * k];
+      if (!(nk > 0.0)) continue;            // no responsibility: the component keeps its values
+      const double inv_nk = rcp_f64(nk);
+      const double m = a[3 * k + 1] * inv_nk;
+      mu[k] = xm + m;
+      var[k] = fmax(a[3 * k + 2] * inv_nk - m * m, floor_var);
+      pi[k] = nk * inv_total;
     }
   }
   if (tid == 0) {
