@@ -419,8 +419,10 @@ def main():
             "imaging_stage": {"ms": grid_k_ms + ifft_k_ms, "survey_minimal_bytes": survey_min,
                               "frac_survey_minimal": survey_min / ((grid_k_ms + ifft_k_ms) * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
+    sizes = sorted(set(int(x) for x in b.n_img))
+    size_label = f"{sizes[0]}^2" if len(sizes) == 1 else f"mixed {sizes[0]}^2-{sizes[-1]}^2"
     out = {
-        "metric": "images/s (grid+iFFT+Hogbom CLEAN, 1024^2, batched)",
+        "metric": f"images/s (grid+iFFT+Hogbom CLEAN, {size_label}, batched)",
         "value": n_inst / (ms_step * 1e-3),
         "unit": "images/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
