@@ -421,6 +421,14 @@ def main():
 
     sizes = sorted(set(int(x) for x in b.n_img))
     size_label = f"{sizes[0]}^2" if len(sizes) == 1 else f"mixed {sizes[0]}^2-{sizes[-1]}^2"
+    # mi_grid alone (gridding_only): the ABI's complex64 half grids written (dirty N/2 x N,
+    # beam N x 2N with zero imaginary parts) and 20 B read per visibility, against the
+    # survey's information-minimal gridding bytes (FP32 complex dirty and real beam half grids)
+    grid_alg = 20.0 * M + float(np.sum(Nf / 2 * Nf * 8.0)) + float(np.sum(Nf * 2 * Nf * 8.0))
+    grid_min = 20.0 * M + float(np.sum(Nf * (Nf / 2 + 1) * 8.0)) + float(np.sum(2 * Nf * (Nf + 1) * 4.0))
+    imaging_roof["gridding_mi_grid"] = dict(_roof(grid_alg, grid_ms), kernels="k_bin + k_grid (dirty and beam half grids)",
+                                            survey_minimal_bytes=grid_min,
+                                            frac_survey_minimal=grid_min / (grid_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
     out = {
         "metric": f"images/s (grid+iFFT+Hogbom CLEAN, {size_label}, batched)",
         "value": n_inst / (ms_step * 1e-3),
