@@ -174,3 +174,35 @@ def test_steer_rejects_bad_arguments():
             api.steer_clean(b, d_t, b_t, [5], **kw)
     with pytest.raises(nat.MiError):
         api.steer_clean(b, d_t, b_t, [-1])
+
+
+@pytest.mark.parametrize("N", [2048, 4096])
+def test_steer_large_images_lone_point_closed_form(N):
+    """Sizes whose transforms use the 4096- and 8192-point workgroups: a lone point under a
+    Gaussian beam gives model S (1 - (1 - g)^n) at the point and residual S (1 - g)^n x the
+    beam window (trim 0.5 selects the point alone)."""
+    log(f"[steer] lone point at {N}^2 (transform length {2 * N}), closed form")
+    require_gpu()
+    from paper_1712_06913_amd import api
+    S, g, n = 2.5, 0.1, 6
+    py, px = N // 3, (2 * N) // 3 + 5
+    ax = np.arange(2 * N, dtype=np.float64) - N
+    B = np.exp(-(ax[None, :] ** 2 + ax[:, None] ** 2) / 0.5).astype(np.float32)
+    D = (S * B[N - py: 2 * N - py, N - px: 2 * N - px]).astype(np.float32)
+    wl = synth.random_instances(87, [N], m_range=(10, 10))
+    b = api.Batch.from_workload(wl)
+    res = api.steer_clean(b, torch.from_numpy(D.ravel()).cuda(), torch.from_numpy(B.ravel()).cuda(), [n], gain=g,
+                          trim=0.5)
+    torch.cuda.synchronize()
+    assert int(res["n_cycle"][0]) == n
+    M = res["model"].cpu().numpy().reshape(N, N)
+    assert abs(M[py, px] - S * (1 - (1 - g) ** n)) <= 1e-5 * S and np.count_nonzero(M) == 1
+    R = res["residual"].cpu().numpy().reshape(N, N)
+    assert max_abs(R, S * (1 - g) ** n * B[N - py: 2 * N - py, N - px: 2 * N - px].astype(np.float64)) <= 1e-5 * S
+
+
+def test_steer_2048_matches_oracle_replay():
+    """A random 2048^2 instance (its 4096-point transforms) against the oracle's replay."""
+    log("[steer] random 2048^2 instance, 6 iterations, replay")
+    wl = synth.random_instances(88, [2048], m_range=(300, 300))
+    _check(wl, np.array([6], np.int32), _inputs(wl))
