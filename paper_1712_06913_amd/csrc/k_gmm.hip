@@ -70,9 +70,11 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*scratch)[6][
   parity ^= 1;
 }
 
-// 1 / x and 1 / sqrt(x) for positive normal x: the hardware estimates refined by Newton
-// steps to within an ulp or two (the EM's sums carry far more rounding than that)
+// 1 / x and 1 / sqrt(x) for positive x: the hardware estimates refined by Newton steps to
+// within an ulp or two (the EM's sums carry far more rounding than that); a responsibility
+// sum too small for the estimate's range takes the IEEE division
 __device__ __forceinline__ double rcp_f64(double x) {
+  if (x < 1e-290) return 1.0 / x;
   double r = __builtin_amdgcn_rcp(x);
   r = fma(r, fma(-x, r, 1.0), r);
   r = fma(r, fma(-x, r, 1.0), r);
