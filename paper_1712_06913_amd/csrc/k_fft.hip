@@ -232,7 +232,13 @@ __device__ __forceinline__ void grid_rec(double2* buf, const double* tab, const 
   const int ou = ((r.a.y >> 8) & 0xff) - OS / 2, ov = (r.a.y & 0xff) - OS / 2;
   const double w = (double)__int_as_float(r.a.z);
   const double wr = w * (double)r.b.x, wim = w * (double)r.b.y;
+  // the v tap and all seven u taps are read before any accumulation, so that the table
+  // reads overlap instead of each one waiting behind the previous tap's LDS atomics (every
+  // index lies in [0, TAB_LEN) for |ou|, |ov| <= OS / 2)
   const double tv = tab[dv * OS - ov + TAB_CENTRE];
+  double tu[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) tu[k] = tab[(k - HALF_W) * OS - ou + TAB_CENTRE];
   const int j = cv + dv + h;
   // REAL: real line l is the real (l even) or imaginary (l odd) part of complex line l / 2
   double* row = reinterpret_cast<double*>(buf);
@@ -241,7 +247,7 @@ __device__ __forceinline__ void grid_rec(double2* buf, const double* tab, const 
     const int kp = cu + du + h - 1, l = kp - first;
     if (l < 0 || l >= lines || kp > h - 1) continue;
     // the (-1)^(i + j) modulation of the transform (u index i = kp + 1) goes with each tap
-    const double kk = ((kp + 1 + j) & 1) ? -(tab[du * OS - ou + TAB_CENTRE] * tv) : tab[du * OS - ou + TAB_CENTRE] * tv;
+    const double kk = ((kp + 1 + j) & 1) ? -(tu[du + HALF_W] * tv) : tu[du + HALF_W] * tv;
     if (REAL) {
       atomicAdd(row + 2 * pd(((l >> 1) << log2P) + j) + (l & 1), wr * kk);
     } else {
