@@ -180,26 +180,39 @@ class ImagingPipeline:
         return self.res
 
 
-def improved_clean(wl, radius_px, device="cuda:0", restore: bool = True, team_size: int = 0):
+def improved_clean(wl, radius_px, device="cuda:0", restore: bool = True, team_size: int = 0,
+                   deconvolver: str = "hogbom", steer_cycles: int = 200, trim: float = 0.9):
     """Algorithm 1 (improved_clean) over a whole batch, every stage one batched launch:
     dirty map and beam -> sky / disk levels (Sec. 4.1) -> CLEAN to the disk level mu_b ->
     disk offset by correlation with a disk of `radius_px` pixels (Sec. 4.2) -> phase
     correction of the visibilities -> dirty map and beam again -> levels -> CLEAN while the
     peak exceeds the sky level mu_a (Sec. 4.3; positive peaks, loop gain of the workload).
-    Returns (result dict of hogbom_clean, offsets (n, 2) radians, levels (n, 6), the
-    corrected visibilities)."""
+    deconvolver: "hogbom" (the workload's iteration caps) or "steer" (the Steer CLEAN that
+    the paper runs in MUSER, at most `steer_cycles` iterations of the given trim).
+    Returns (result dict of hogbom_clean or steer_clean, offsets (n, 2) radians, levels
+    (n, 6), the corrected visibilities)."""
+    if deconvolver not in ("hogbom", "steer"):
+        raise ValueError(f"unknown deconvolver {deconvolver!r}")
     dev = torch.device(device)
     b = api.Batch.from_workload(wl, dev)
     vis, uv, w = api.workload_tensors(wl, dev)
     niter = np.ascontiguousarray(wl.niter, np.int32)
+    cycles = np.full(b.n_inst, steer_cycles, np.int32)
+
+    def deconvolve(dirty, beam, thr, final):
+        if deconvolver == "steer":
+            return api.steer_clean(b, dirty, beam, cycles, gain=wl.gain, trim=trim, threshold=thr, positive_only=True,
+                                   restore=final and restore, want_model=final)
+        return api.hogbom_clean(b, dirty, beam, niter, gain=wl.gain, threshold=thr, positive_only=True,
+                                restore=final and restore, want_model=final, want_components=final,
+                                team_size=team_size)
+
     dirty, beam, _ = api.dirty_image(b, vis, uv, w, beam=True)
     _, _, mu_b = api.gmm_levels(b, dirty)
-    pre = api.hogbom_clean(b, dirty, beam, niter, gain=wl.gain, threshold=mu_b, positive_only=True,
-                           restore=False, want_model=False, want_components=False, team_size=team_size)
+    pre = deconvolve(dirty, beam, mu_b, False)
     offsets = api.disk_offsets(b, pre["residual"], radius_px)
     api.phase_shift(b, vis, uv, offsets)
     dirty, beam, _ = api.dirty_image(b, vis, uv, w, beam=True, out=dirty, beam_out=beam)
     levels, mu_a, _ = api.gmm_levels(b, dirty)
-    res = api.hogbom_clean(b, dirty, beam, niter, gain=wl.gain, threshold=mu_a, positive_only=True,
-                           restore=restore, team_size=team_size)
+    res = deconvolve(dirty, beam, mu_a, True)
     return res, offsets, levels, vis

@@ -9,7 +9,7 @@ import torch
 
 from oracle import centering, imager
 from paper_1712_06913_amd import synth
-from tests.gpu_helpers import log, require_gpu
+from tests.gpu_helpers import log, max_abs, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -130,3 +130,51 @@ def test_disk_offsets_follow_a_change_of_radius():
             cell = float(wl.cell_rad[i])
             ref = centering.disk_offset(m.astype(np.float64), radius[i], cell)
             assert abs(off[i, 0] - ref[0]) <= 1e-9 * cell and abs(off[i, 1] - ref[1]) <= 1e-9 * cell
+
+
+def test_improved_clean_chain_with_steer():
+    """Algorithm 1 with the paper's own deconvolver: Steer CLEAN to mu_b, centring, Steer
+    CLEAN while the peak exceeds mu_a.  The final stage agrees with a direct steer_clean call
+    on maps imaged again from the corrected visibilities (equal to LDS-atomic rounding: the
+    gridder's FP64 additions land in any order), whose every iteration and stop decision the
+    oracle's replay accepts."""
+    log("[center] pipeline.improved_clean with Steer CLEAN")
+    require_gpu()
+    from oracle import steer
+    from paper_1712_06913_amd import api, pipeline
+    wl = synth.offset_disk(n=3, niter=1500)
+    radius = np.array([16.0 * synth.ARCMIN / c for c in wl.cell_rad])
+    cycles = 60
+    res, offsets, levels, vis = pipeline.improved_clean(wl, radius, deconvolver="steer", steer_cycles=cycles)
+    torch.cuda.synchronize()
+    o = offsets.cpu().numpy()
+    for i in range(wl.n_inst):
+        err = math.hypot(o[i, 0] - wl.sky_centre[i, 0], o[i, 1] - wl.sky_centre[i, 1]) / wl.cell_rad[i]
+        log(f"  inst {i}: centring error {err:.2f} px, {int(res['n_cycle'][i])} Steer iterations")
+        assert err < 5.0
+    assert torch.isfinite(res["restored"]).all()
+    b = api.Batch.from_workload(wl)
+    _, uv, w = api.workload_tensors(wl)
+    dirty, beam, _ = api.dirty_image(b, vis, uv, w, beam=True)
+    mu_a = levels[:, 0].to(torch.float32).contiguous()
+    nc = np.full(wl.n_inst, cycles, np.int32)
+    ref = api.steer_clean(b, dirty, beam, nc, gain=wl.gain, threshold=mu_a, positive_only=True, restore=False,
+                          want_masks=True)
+    torch.cuda.synchronize()
+    assert torch.equal(ref["n_cycle"], res["n_cycle"])
+    peaks = [float(np.max(np.abs(x.cpu().numpy()))) for x in b.split(dirty)]
+    for i in range(wl.n_inst):
+        assert max_abs(b.split(ref["residual"])[i].cpu().numpy(), b.split(res["residual"])[i].cpu().numpy()) \
+            <= 1e-4 * peaks[i]
+    lg = ref["log"].cpu().numpy().reshape(-1, 3)
+    thr = mu_a.cpu().numpy()
+    for i in range(wl.n_inst):
+        D = b.split(dirty)[i].cpu().numpy().astype(np.float64)
+        B = b.split(beam, beam=True)[i].cpu().numpy().astype(np.float64)
+        n = int(ref["n_cycle"][i])
+        L = lg[ref["log_off"][i]: ref["log_off"][i] + n]
+        masks = api.steer_masks(ref, b, i, n)
+        ok, bad, R, _ = steer.replay(D, B, masks, L[:, 0], L[:, 1], L[:, 2], gain=wl.gain, trim=0.9,
+                                     threshold=float(thr[i]), positive_only=True, ncycle=cycles)
+        assert ok, f"inst {i}: iteration {bad} rejected by the replay"
+        assert max_abs(b.split(ref["residual"])[i].cpu().numpy(), R) <= 1e-4 * float(np.max(np.abs(D)))
