@@ -15,15 +15,16 @@
  *  - Every call is asynchronous on the given HIP stream (0 = the null stream).  The
  *    first call with a new batch descriptor builds a plan (workspace, device tables) and
  *    may synchronise once; later calls with an identical descriptor do not synchronise.
- *    The same holds for a new set of CLEAN parameters (mi_hogbom_clean), new w_max /
- *    phase_tol (mi_dirty_image_w) and new radii (mi_disk_offsets): each of those calls
- *    uploads its tables synchronously once; repeats with the same values do not.  No
- *    other call synchronises.
+ *    The same holds for a new set of CLEAN parameters (mi_hogbom_clean, mi_steer_clean:
+ *    caps and host thresholds), new w_max / phase_tol (mi_dirty_image_w) and new radii
+ *    (mi_disk_offsets): each of those calls uploads its tables synchronously once; repeats
+ *    with the same values do not.  No other call synchronises.
  *  - Graph capture: a call whose plan already exists (run it once outside the capture)
  *    can be captured into a HIP graph; its plan is then kept for the context's lifetime.
  *    A call that would build a new plan while its stream is capturing returns
  *    MI_ERR_UNSUPPORTED.  Other plans are evicted least recently used first (at most 16
- *    batch descriptors, 8 CLEAN parameter sets per descriptor, 16 transform layouts).
+ *    batch descriptors, 8 CLEAN and 8 Steer CLEAN parameter sets per descriptor, 16
+ *    transform layouts).
  *  - Argument errors are detected on the host before any launch; the call then returns
  *    a nonzero mi_status, writes nothing, and mi_last_error() describes the problem.
  *  - Per-instance problems (no kept visibilities, ...) do not abort the batch: they are
