@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--cpu-baseline-full", action="store_true",
                     help="also time the oracle on 16 C2, 4 C3 and 16 C4 instances (1 core, all cores)")
     ap.add_argument("--no-parity", action="store_true", help="skip the instance-0 check against the oracle")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the imaging schedule and the CLEAN team size with the autotuners before timing")
     ap.add_argument("--steer-cycles", type=int, default=40,
                     help="Steer CLEAN stage: iterations per image (0: skip the stage)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -273,6 +275,14 @@ def main():
             ev[3].record(stream)
         return res
 
+    img_tuning = None
+    if args.autotune:
+        from paper_1712_06913_amd import pipeline
+        img_tuning = pipeline.autotune_imaging(b, vis, uv, w)       # left set on the context
+        api.dirty_image(b, vis, uv, w, beam=True, out=dirty, beam_out=beam, b0_out=b0)
+        torch.cuda.synchronize()
+        args.team_size = pipeline.autotune_team_size(b, dirty, beam, niter, wl.gain)
+        log(f"autotuned: imaging (grid_chunk, fft_elems) = {img_tuning}, CLEAN team size {args.team_size or 'policy'}")
     if args.calib_copy_mib:
         src = torch.ones(args.calib_copy_mib * (1 << 18), dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -439,7 +449,9 @@ def main():
         "config": {"workload": wl.name, "n_inst": n_inst, "N": sorted(set(int(x) for x in b.n_img)),
                    "visibilities": int(wl.vis_offset[-1]), "niter_total": int(niter.sum()),
                    "gain": wl.gain, "weighting": "natural" if not wl.weight_mode.any() else "mixed/uniform",
-                   "clean_team_size": args.team_size or "library policy"},
+                   "clean_team_size": args.team_size or "library policy",
+                   "imaging_tuning": ({"grid_chunk": img_tuning[0], "fft_elems": img_tuning[1], "source": "autotuner"}
+                                      if img_tuning else "library default")},
         "stage_ms": {"dirty_image_and_beam": img_ms, "clean_restore": clean_ms, "adjoint": adj_ms,
                      "gridding_only": grid_ms, "gmm_levels": gmm_ms, "disk_offsets": center_ms},
         "gmm_levels_read_GBps": float(np.sum(8.0 * N2)) / (gmm_ms * 1e-3) / 1e9,
