@@ -3,7 +3,10 @@
 // centre, and the visibilities' phases are corrected by that offset.  Choices the paper
 // leaves open: a uniform disk of the given radius (pixels) centred on pixel (N/2, N/2);
 // circular correlation C[d] = sum_x map[x] disk[x - d] through plain FP64 DFTs (the
-// transforms run in k_fft.hip); the peak is the largest Re C, ties to the lowest linear
+// transforms run in k_fft.hip; two real maps of equal size share one complex transform,
+// Z = A + i B, separated in the spectrum by Hermitian symmetry: A^(k) = (Z^(k) +
+// conj Z^(-k)) / 2, B^(k) = (Z^(k) - conj Z^(-k)) / 2i, and the two correlations come back
+// as the real and imaginary parts of one inverse transform); the peak is the largest Re C, ties to the lowest linear
 // index, wrapped to [-N/2, N/2), refined per axis by the parabola through the peak and its
 // neighbours; the correction multiplies each visibility by exp(+2 pi i (u dl + v dm)).
 #include <algorithm>
@@ -27,17 +30,49 @@ k_corr_prep(const InstDesc* __restrict__ inst, const float* __restrict__ images,
   for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256) {
     const int y = (int)(q >> d.log2N), x = (int)(q & (N - 1));
     const double dx = x - h, dy = y - h;
-    X[d.img_off + q] = make_double2((double)images[d.img_off + q], 0.0);
+    if (X) X[d.img_off + q] = make_double2((double)images[d.img_off + q], 0.0);          // null: maps paired
     if (D) D[d.img_off + q] = make_double2(dx * dx + dy * dy <= r2 ? 1.0 : 0.0, 0.0);   // null: model cached
   }
 }
 
-// A[q] *= conj(B[q])
+// maps of a slot -> Z = A + i B (double2)
 __global__ void __launch_bounds__(256)
-k_corr_mul(double2* __restrict__ A, const double2* __restrict__ B, int64_t n) {
+k_corr_prep_pair(const CorrSlot* __restrict__ slots, const InstDesc* __restrict__ inst, const float* __restrict__ images,
+                 double2* __restrict__ Z) {
+  const CorrSlot sl = slots[blockIdx.y];
+  const int64_t n = (int64_t)sl.N * sl.N;
+  const float* a = images + inst[sl.a].img_off;
+  const float* b = sl.b >= 0 ? images + inst[sl.b].img_off : nullptr;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
+    Z[sl.off + q] = make_double2((double)a[q], b ? (double)b[q] : 0.0);
+}
+
+// W = A^ conj(DA) + i B^ conj(DB) from the slot's spectrum Z^ (out of place: Z^(-k) is read
+// by another thread); a slot with one map has Z^ = A^.
+__global__ void __launch_bounds__(256)
+k_corr_mul_pair(const CorrSlot* __restrict__ slots, const InstDesc* __restrict__ inst, const double2* __restrict__ Z,
+                const double2* __restrict__ D, double2* __restrict__ W) {
+  const CorrSlot sl = slots[blockIdx.y];
+  const int N = sl.N;
+  const int64_t n = (int64_t)N * N;
+  const double2* z = Z + sl.off;
+  const double2* da = D + inst[sl.a].img_off;
+  const double2* db = sl.b >= 0 ? D + inst[sl.b].img_off : nullptr;
+  double2* w = W + sl.off;
   for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256) {
-    const double2 a = A[q], b = B[q];
-    A[q] = make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+    const double2 zk = z[q], ea = da[q];
+    if (!db) {
+      w[q] = make_double2(zk.x * ea.x + zk.y * ea.y, zk.y * ea.x - zk.x * ea.y);
+      continue;
+    }
+    const int ky = (int)(q >> sl.log2N), kx = (int)(q & (N - 1));
+    const double2 zm = z[(int64_t)((N - ky) & (N - 1)) * N + ((N - kx) & (N - 1))];
+    const double2 fa = make_double2(0.5 * (zk.x + zm.x), 0.5 * (zk.y - zm.y));     // (Z + conj Zm) / 2
+    const double2 fb = make_double2(0.5 * (zk.y + zm.y), 0.5 * (zm.x - zk.x));     // (Z - conj Zm) / 2i
+    const double2 eb = db[q];
+    const double2 pa = make_double2(fa.x * ea.x + fa.y * ea.y, fa.y * ea.x - fa.x * ea.y);   // A^ conj(DA)
+    const double2 pb = make_double2(fb.x * eb.x + fb.y * eb.y, fb.y * eb.x - fb.x * eb.y);   // B^ conj(DB)
+    w[q] = make_double2(pa.x - pb.y, pa.y + pb.x);                                      // pa + i pb
   }
 }
 
@@ -50,18 +85,21 @@ __device__ __forceinline__ double parabola(double cm, double c0, double cp) {
 
 // Peak of Re C per instance (one workgroup each) -> offsets (dl, dm) in radians.
 __global__ void __launch_bounds__(CTR_THREADS)
-k_corr_peak(const InstDesc* __restrict__ inst, const double2* __restrict__ C, double* __restrict__ offsets) {
+k_corr_peak(const InstDesc* __restrict__ inst, const double2* __restrict__ C, const int64_t* __restrict__ c_off,
+            double* __restrict__ offsets) {
   __shared__ double sv[CTR_WAVES];
   __shared__ int si[CTR_WAVES];
   const int i = blockIdx.x;
   const InstDesc d = inst[i];
   const int N = d.N;
   const int64_t n = (int64_t)N * N;
-  const double2* c = C + d.img_off;
+  // instance i's correlation: the real (c_off even) or imaginary (odd) part of its slot,
+  // whose complex values start at c_off / 2
+  const double* c = reinterpret_cast<const double*>(C + (c_off[i] >> 1)) + (c_off[i] & 1);
   double best = -INFINITY;
   int bi = 0x7fffffff;
   for (int64_t q = threadIdx.x; q < n; q += CTR_THREADS) {
-    const double v = c[q].x;
+    const double v = c[2 * q];
     if (v > best) { best = v; bi = (int)q; }     // ascending q per thread: first maximum kept
   }
   for (int o = 32; o > 0; o >>= 1) {
@@ -78,9 +116,11 @@ k_corr_peak(const InstDesc* __restrict__ inst, const double2* __restrict__ C, do
     for (int w = 1; w < CTR_WAVES; ++w)
       if (sv[w] > best || (sv[w] == best && si[w] < bi)) { best = sv[w]; bi = si[w]; }
     const int py = bi >> d.log2N, px = bi & (N - 1);
-    const double c0 = c[bi].x;
-    const double fx = parabola(c[(int64_t)py * N + ((px - 1) & (N - 1))].x, c0, c[(int64_t)py * N + ((px + 1) & (N - 1))].x);
-    const double fy = parabola(c[(int64_t)((py - 1) & (N - 1)) * N + px].x, c0, c[(int64_t)((py + 1) & (N - 1)) * N + px].x);
+    const double c0 = c[2 * (int64_t)bi];
+    const double fx = parabola(c[2 * ((int64_t)py * N + ((px - 1) & (N - 1)))], c0,
+                               c[2 * ((int64_t)py * N + ((px + 1) & (N - 1)))]);
+    const double fy = parabola(c[2 * ((int64_t)((py - 1) & (N - 1)) * N + px)], c0,
+                               c[2 * ((int64_t)((py + 1) & (N - 1)) * N + px)]);
     const int ix = px >= N / 2 ? px - N : px, iy = py >= N / 2 ? py - N : py;
     const double cell = d.scale / (double)N;
     offsets[2 * i] = ((double)ix + fx) * cell;
@@ -111,13 +151,21 @@ hipError_t launch_corr_prep(const InstDesc* inst, int n_inst, int max_N, const f
   hipLaunchKernelGGL(k_corr_prep, dim3(blocks, n_inst), dim3(256), 0, st, inst, images, radius_px, X, D);
   return hipGetLastError();
 }
-hipError_t launch_corr_mul(double2* A, const double2* B, int64_t n, hipStream_t st) {
-  const int64_t blocks = std::min<int64_t>(65536, (n + 255) / 256);
-  hipLaunchKernelGGL(k_corr_mul, dim3((unsigned)std::max<int64_t>(1, blocks)), dim3(256), 0, st, A, B, n);
+hipError_t launch_corr_peak(const InstDesc* inst, int n_inst, const double2* C, const int64_t* c_off, double* offsets,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_corr_peak, dim3(n_inst), dim3(CTR_THREADS), 0, st, inst, C, c_off, offsets);
   return hipGetLastError();
 }
-hipError_t launch_corr_peak(const InstDesc* inst, int n_inst, const double2* C, double* offsets, hipStream_t st) {
-  hipLaunchKernelGGL(k_corr_peak, dim3(n_inst), dim3(CTR_THREADS), 0, st, inst, C, offsets);
+hipError_t launch_corr_prep_pair(const CorrSlot* slots, int n_slots, const InstDesc* inst, int max_N, const float* images,
+                                 double2* Z, hipStream_t st) {
+  const int blocks = std::max(1, std::min(1024, max_N * max_N / 2048));
+  hipLaunchKernelGGL(k_corr_prep_pair, dim3(blocks, n_slots), dim3(256), 0, st, slots, inst, images, Z);
+  return hipGetLastError();
+}
+hipError_t launch_corr_mul_pair(const CorrSlot* slots, int n_slots, const InstDesc* inst, int max_N, const double2* Z,
+                                const double2* D, double2* W, hipStream_t st) {
+  const int blocks = std::max(1, std::min(1024, max_N * max_N / 2048));
+  hipLaunchKernelGGL(k_corr_mul_pair, dim3(blocks, n_slots), dim3(256), 0, st, slots, inst, Z, D, W);
   return hipGetLastError();
 }
 hipError_t launch_phase_shift(const InstDesc* inst, int n_inst, int max_nvis, float2* vis, const float2* uv,

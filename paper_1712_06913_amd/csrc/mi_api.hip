@@ -73,8 +73,10 @@ hipError_t launch_gmm(const InstDesc*, int, const float*, int, int, double*, flo
 hipError_t launch_fft_c2c_t_d2d(int, const int*, const int64_t*, const FftWork*, int, const double2*, double2*,
                                 const Tables&, double, int, int, hipStream_t);
 hipError_t launch_corr_prep(const InstDesc*, int, int, const float*, const double*, double2*, double2*, hipStream_t);
-hipError_t launch_corr_mul(double2*, const double2*, int64_t, hipStream_t);
-hipError_t launch_corr_peak(const InstDesc*, int, const double2*, double*, hipStream_t);
+hipError_t launch_corr_peak(const InstDesc*, int, const double2*, const int64_t*, double*, hipStream_t);
+hipError_t launch_corr_prep_pair(const CorrSlot*, int, const InstDesc*, int, const float*, double2*, hipStream_t);
+hipError_t launch_corr_mul_pair(const CorrSlot*, int, const InstDesc*, int, const double2*, const double2*, double2*,
+                                hipStream_t);
 hipError_t launch_phase_shift(const InstDesc*, int, int, float2*, const float2*, const double*, hipStream_t);
 hipError_t launch_beam_symcheck(const InstDesc*, int, int, const float*, int*, hipStream_t);
 hipError_t launch_degrid(const InstDesc*, int, int, const float2*, const float*, const float*, const double*,
@@ -241,6 +243,10 @@ struct Plan : CacheEntry {
   int corr_elems = 0, corr_nwork = 0;
   bool corr_model_ready = false;      // corr_d holds the disk models' transforms for `radius`
   DevBuf radius_d, corr_n, corr_offs, corr_work, corr_x, corr_d, corr_s, offsets_ws;
+  // the maps' transforms: two maps of equal N per slot
+  int corr_nslots = 0, corr_snwork = 0;
+  int64_t corr_slot_total = 0;
+  DevBuf corr_slots, corr_sn, corr_soffs, corr_swork, corr_coff;
 };
 
 struct IfftPlan : CacheEntry {
@@ -944,7 +950,8 @@ mi_status mi_disk_offsets(mi_ctx* ctx, const mi_batch* batch, const float* image
       upload(P->radius_d, P->radius);
       P->corr_model_ready = false;
     }
-    if (!P->corr_work.p) {                              // 2-D transform plan over the packed maps
+    if (!P->corr_work.p) {                              // 2-D transform plans
+      // the disk models, one per instance
       std::vector<int32_t> nn(P->n.begin(), P->n.end());
       std::vector<int64_t> offs(n);
       std::vector<FftWork> work;
@@ -959,31 +966,80 @@ mi_status mi_disk_offsets(mi_ctx* ctx, const mi_batch* batch, const float* image
       upload(P->corr_n, nn);
       upload(P->corr_offs, offs);
       upload(P->corr_work, work);
+      // the maps, paired in instance order among equal sizes (a map without a partner of
+      // its size keeps a slot of its own); coff[i] = 2 x (slot offset) + (0: real part,
+      // 1: imaginary part)
+      std::vector<CorrSlot> slots;
+      std::vector<int64_t> coff(n);
+      std::map<int, int> waiting;                       // N -> slot still missing its second map
+      int64_t so = 0;
+      for (int i = 0; i < n; ++i) {
+        const int N = nn[i];
+        auto it = waiting.find(N);
+        if (it != waiting.end()) {
+          CorrSlot& sl = slots[it->second];
+          sl.b = i;
+          coff[i] = 2 * sl.off + 1;
+          waiting.erase(it);
+        } else {
+          waiting[N] = (int)slots.size();
+          slots.push_back(CorrSlot{i, -1, N, ilog2i(N), so});
+          coff[i] = 2 * so;
+          so += (int64_t)N * N;
+        }
+      }
+      std::vector<int32_t> sn;
+      std::vector<int64_t> soffs;
+      std::vector<FftWork> swork;
+      for (int k = 0; k < (int)slots.size(); ++k) {
+        const int N = slots[k].N;
+        sn.push_back(N);
+        soffs.push_back(slots[k].off);
+        int nl = P->corr_elems / N;
+        if (nl > N) nl = N;
+        for (int l = 0; l < N; l += nl) swork.push_back({k, l});
+      }
+      P->corr_nslots = (int)slots.size();
+      P->corr_snwork = (int)swork.size();
+      P->corr_slot_total = so;
+      upload(P->corr_slots, slots);
+      upload(P->corr_sn, sn);
+      upload(P->corr_soffs, soffs);
+      upload(P->corr_swork, swork);
+      upload(P->corr_coff, coff);
     }
     const int64_t total = P->total_img;
-    double2* X = dev_alloc<double2>(P->corr_x, total);
+    double2* Z = dev_alloc<double2>(P->corr_x, (size_t)P->corr_slot_total);
     double2* D = dev_alloc<double2>(P->corr_d, total);
-    double2* S = dev_alloc<double2>(P->corr_s, total);
+    double2* S = dev_alloc<double2>(P->corr_s, total);   // >= the slots' total
     const InstDesc* inst = static_cast<const InstDesc*>(P->inst.p);
-    const int* nd = static_cast<const int*>(P->corr_n.p);
-    const int64_t* od = static_cast<const int64_t*>(P->corr_offs.p);
-    const FftWork* wk = static_cast<const FftWork*>(P->corr_work.p);
-    const int e = P->corr_elems, nw = P->corr_nwork;
-    const bool model = !P->corr_model_ready;            // the disk models' transforms are kept
-    HIPCHK(launch_corr_prep(inst, n, P->max_N, images, static_cast<const double*>(P->radius_d.p), X,
-                            model ? D : nullptr, stream));
-    // forward 2-D DFTs (two line passes with transposed writes), plain (no centring)
-    HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, nw, X, S, ctx->T, -1.0, 0, 0, stream));
-    HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, nw, S, X, ctx->T, -1.0, 0, 0, stream));
-    if (model) {
-      HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, nw, D, S, ctx->T, -1.0, 0, 0, stream));
-      HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, nw, S, D, ctx->T, -1.0, 0, 0, stream));
+    const int e = P->corr_elems;
+    const CorrSlot* slots = static_cast<const CorrSlot*>(P->corr_slots.p);
+    const int ns = P->corr_nslots;
+    const int* snd = static_cast<const int*>(P->corr_sn.p);
+    const int64_t* sod = static_cast<const int64_t*>(P->corr_soffs.p);
+    const FftWork* swk = static_cast<const FftWork*>(P->corr_swork.p);
+    const int snw = P->corr_snwork;
+    if (!P->corr_model_ready) {                         // the disk models' transforms are kept
+      const int* nd = static_cast<const int*>(P->corr_n.p);
+      const int64_t* od = static_cast<const int64_t*>(P->corr_offs.p);
+      const FftWork* wk = static_cast<const FftWork*>(P->corr_work.p);
+      HIPCHK(launch_corr_prep(inst, n, P->max_N, images, static_cast<const double*>(P->radius_d.p), nullptr, D,
+                              stream));
+      HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, P->corr_nwork, D, S, ctx->T, -1.0, 0, 0, stream));
+      HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, P->corr_nwork, S, D, ctx->T, -1.0, 0, 0, stream));
       P->corr_model_ready = true;
     }
-    HIPCHK(launch_corr_mul(X, D, total, stream));
-    HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, nw, X, S, ctx->T, +1.0, 0, 0, stream));
-    HIPCHK(launch_fft_c2c_t_d2d(e, nd, od, wk, nw, S, X, ctx->T, +1.0, 0, 0, stream));
-    HIPCHK(launch_corr_peak(inst, n, X, offsets_out, stream));
+    // Z = A + i B per slot; forward 2-D DFTs (two line passes with transposed writes,
+    // plain, no centring); W = A^ conj(DA) + i B^ conj(DB); inverse: Re / Im = the two
+    // correlations
+    HIPCHK(launch_corr_prep_pair(slots, ns, inst, P->max_N, images, Z, stream));
+    HIPCHK(launch_fft_c2c_t_d2d(e, snd, sod, swk, snw, Z, S, ctx->T, -1.0, 0, 0, stream));
+    HIPCHK(launch_fft_c2c_t_d2d(e, snd, sod, swk, snw, S, Z, ctx->T, -1.0, 0, 0, stream));
+    HIPCHK(launch_corr_mul_pair(slots, ns, inst, P->max_N, Z, D, S, stream));
+    HIPCHK(launch_fft_c2c_t_d2d(e, snd, sod, swk, snw, S, Z, ctx->T, +1.0, 0, 0, stream));
+    HIPCHK(launch_fft_c2c_t_d2d(e, snd, sod, swk, snw, Z, S, ctx->T, +1.0, 0, 0, stream));
+    HIPCHK(launch_corr_peak(inst, n, S, static_cast<const int64_t*>(P->corr_coff.p), offsets_out, stream));
   });
 }
 

@@ -106,6 +106,14 @@ struct CleanArgs {
 // Steer CLEAN: pixels per work item of its elementwise passes (4 per thread, 512 threads).
 constexpr int ST_PIX_PER_ITEM = 2048;
 
+// Disk centering: two maps of equal size share one complex transform (map a in the real
+// part, map b in the imaginary part; b = -1 for a map left alone).
+struct CorrSlot {
+  int a, b;          // instances
+  int N, log2N;
+  int64_t off;       // element offset of the slot's N^2 complex values
+};
+
 // Steer CLEAN: per-instance layout of the workspaces (built on the host per plan).
 struct SteerInst {
   int64_t x_off;     // blocked row spectra (complex, stored FP32): 2N rows x (N+1) columns
