@@ -622,9 +622,9 @@ k_fft_b_r2c(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
     if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
     lds_fft<ELEMS, THREADS>(buf, log2P, nz, -1.0, T.twiddle);
     double2* dst = yb + d.gd_off;
-    const int nblk = h / nl, per_blk = nz * nl;
+    const int nblk = h / nl, per_blk = nz * nl, log2pb = ilog2(per_blk);   // powers of two
     for (int q = threadIdx.x; q < nblk * per_blk; q += THREADS) {
-      const int b = q / per_blk, r = q - b * per_blk;
+      const int b = q >> log2pb, r = q & (per_blk - 1);
       const int zl = r >> log2nl, l = r & (nl - 1);
       const int k = b * nl + l + 1;
       const double2 A = buf[pd((zl << log2P) + k)];

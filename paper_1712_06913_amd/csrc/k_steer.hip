@@ -185,10 +185,12 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_cols(SteerArgs A) {
   const int Rin = MODE == 0 ? P : N;
   float2* X = A.X + s.x_off;
   // element q = (yb nc + c) RB + r: row yb RB + r of column kx0 + c; for each block of rows
-  // the nc columns' entries are contiguous in memory
-  const int run = nc * RB;
+  // the nc columns' entries are contiguous in memory.  nc is a power of two (the block's
+  // column count, or 1 for the last column kx = N: N is a multiple of it), so q splits by
+  // shifts
+  const int run = nc * RB, log2run = __builtin_ctz(nc) + log2RB;
   for (int q = threadIdx.x; q < (P / RB) * run; q += ST_THREADS) {
-    const int yb = q / run, rem = q - yb * run, c = rem >> log2RB, r = rem & (RB - 1);
+    const int yb = q >> log2run, rem = q & (run - 1), c = rem >> log2RB, r = rem & (RB - 1);
     const int y = (yb << log2RB) + r;
     buf[pd((c << log2P) + y)] =
         y < Rin ? X[(int64_t)yb * (N + 1) * RB + (int64_t)(kx0 + c) * RB + r] : make_float2(0.0f, 0.0f);
@@ -208,7 +210,7 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_cols(SteerArgs A) {
   __syncthreads();
   lds_fft<ST_ELEMS, ST_THREADS>(buf, log2P, nc, +1.0, A.T.twiddle);
   for (int q = threadIdx.x; q < (N / RB) * run; q += ST_THREADS) {
-    const int yb = q / run, rem = q - yb * run, c = rem >> log2RB, r = rem & (RB - 1);
+    const int yb = q >> log2run, rem = q & (run - 1), c = rem >> log2RB, r = rem & (RB - 1);
     const int y = (yb << log2RB) + r;
     X[(int64_t)yb * (N + 1) * RB + (int64_t)(kx0 + c) * RB + r] = buf[pd((c << log2P) + N + y)];
   }
