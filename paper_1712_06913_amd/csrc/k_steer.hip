@@ -35,8 +35,9 @@
 namespace mi {
 
 constexpr int ST_THREADS = 512;
-// Complex floats staged per workgroup: 4096 (36 KB with padding, four workgroups per compute
-// unit) for transforms up to 4096 points, 8192 (72 KB) for 8192-point ones (N = 4096).
+// Complex floats staged per workgroup: 4096 (36 KB with padding; at 72 VGPRs three
+// workgroups share a compute unit) for transforms up to 4096 points, 8192 (72 KB) for
+// 8192-point ones (N = 4096).
 constexpr int st_lds(int elems) { return elems + elems / 8; }
 
 namespace {
