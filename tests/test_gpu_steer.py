@@ -206,3 +206,11 @@ def test_steer_2048_matches_oracle_replay():
     log("[steer] random 2048^2 instance, 6 iterations, replay")
     wl = synth.random_instances(88, [2048], m_range=(300, 300))
     _check(wl, np.array([6], np.int32), _inputs(wl))
+
+
+def test_steer_mixed_64_to_2048_in_one_batch():
+    """One batch mixing 64^2 (32 columns per column workgroup), 512^2 and 2048^2 (two per
+    workgroup, 4096-point blocks for every size): every instance against the oracle's replay."""
+    log("[steer] mixed 64 / 512 / 2048 batch, 5 iterations, replay")
+    wl = synth.random_instances(89, [64, 512, 2048], m_range=(200, 300))
+    _check(wl, np.array([5, 5, 5], np.int32), _inputs(wl))
