@@ -20,7 +20,9 @@
 //   pass B  (k_fft_b_c2r): ny rows y per workgroup; rebuilds the Hermitian spectrum
 //           along u from the blocks, length-P FFT, real part, correction, normalisation.
 // The beam's grid is also real and even, which k_fft_a_real / k_fft_b_c2r_sym use to halve
-// its transform work and bytes (see there).
+// its transform work and bytes (see there).  In the imaging calls pass A is fused with the
+// gridding (k_grid_fft_a, k_grid_fft_a_real: the block's samples are gridded straight into
+// LDS); the separate pass A kernels serve grids built elsewhere (the w-projection gridder).
 // The adjoint runs the mirror image (k_fft_b_r2c then k_fft_a_fwd); mi_ifft2 uses
 // k_fft_c2c_t twice on full complex arrays.
 //
