@@ -212,7 +212,8 @@ k_fft_b_c2r(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
 // straight into the LDS lines, each tap already carrying the (-1)^(i+j) modulation,
 // transforms along v and writes the block once in pass A's blocked layout, so the half grid never goes to HBM and
 // back.  The block's entries are self-contained records (cells, offsets, weight, value)
-// written by k_bin; work item w is block w, so its entry range is tstart[w], tcount[w].
+// written by k_bin; work item w covers line block rec_block(w), whose entries are
+// tstart[b] .. tstart[b] + tcount[b] - 1.
 // Thread t of a round takes entry t / 7 and v tap t % 7 - 3 and adds that cell in each of
 // the sample's seven lines: the seven threads of a sample touch seven consecutive cells of
 // a line (different LDS banks).  The next work item's range and its first round of records
@@ -260,6 +261,16 @@ __device__ __forceinline__ void grid_rec(double2* buf, const double* tab, const 
   }
 }
 
+// The line block (index of its record range) of work item w of a fused first pass: blocks
+// are numbered instance by instance, the work list deals them out in another order.
+template <int ELEMS, bool REAL>
+__device__ __forceinline__ int rec_block(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int w) {
+  const FftWork wk = work[w];
+  const InstDesc& d = inst[wk.inst];
+  if (REAL) return d.blk_base_b + (wk.first >> ilog2(real_lines_per_block<ELEMS>(2 * d.N)));
+  return d.blk_base_d + (wk.first >> ilog2(lines_per_block<ELEMS>(d.N)));
+}
+
 // One work item's gridding: round 0 from the prefetched registers, later rounds loaded here.
 template <int THREADS, bool REAL>
 __device__ __forceinline__ void grid_block(double2* buf, const double* tab, const GridRec* __restrict__ rec,
@@ -286,13 +297,15 @@ k_grid_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work
   int st = 0, cnt = 0;
   RecRegs r0{};
   if (w < n_work) {
-    st = tstart[w];
-    cnt = tcount[w];
+    const int bk = rec_block<ELEMS, false>(inst, work, w);
+    st = tstart[bk];
+    cnt = tcount[bk];
     if (eo < PER && eo < cnt) r0 = load_rec(rec, st + eo);
   }
   for (; w < n_work; w += gridDim.x) {
     const int wn = w + gridDim.x;
-    const int stn = wn < n_work ? tstart[wn] : 0, cntn = wn < n_work ? tcount[wn] : 0;
+    const int bn = wn < n_work ? rec_block<ELEMS, false>(inst, work, wn) : 0;
+    const int stn = wn < n_work ? tstart[bn] : 0, cntn = wn < n_work ? tcount[bn] : 0;
     const FftWork wk = work[w];
     const InstDesc d = inst[wk.inst];
     const int P = d.N, log2P = ilog2(P);
@@ -331,13 +344,15 @@ k_grid_fft_a_real(const InstDesc* __restrict__ inst, const FftWork* __restrict__
   int st = 0, cnt = 0;
   RecRegs r0{};
   if (w < n_work) {
-    st = tstart[w];
-    cnt = tcount[w];
+    const int bk = rec_block<ELEMS, true>(inst, work, w);
+    st = tstart[bk];
+    cnt = tcount[bk];
     if (eo < PER && eo < cnt) r0 = load_rec(rec, st + eo);
   }
   for (; w < n_work; w += gridDim.x) {
     const int wn = w + gridDim.x;
-    const int stn = wn < n_work ? tstart[wn] : 0, cntn = wn < n_work ? tcount[wn] : 0;
+    const int bn = wn < n_work ? rec_block<ELEMS, true>(inst, work, wn) : 0;
+    const int stn = wn < n_work ? tstart[bn] : 0, cntn = wn < n_work ? tcount[bn] : 0;
     const FftWork wk = work[w];
     const InstDesc d = inst[wk.inst];
     const int P = 2 * d.N, log2P = ilog2(P), h = P / 2;

@@ -396,6 +396,11 @@ Plan* get_plan(mi_ctx* ctx, const mi_batch* b, hipStream_t st) {
   P->h_inst.resize(n);
   std::vector<int> tile_inst_d, tile_inst_b;
   std::vector<FftWork> wa_d, wb_d, wa_b, wb_b;
+  // first-pass work items per instance, dealt out line block by line block over the
+  // instances: the blocks around u = 0 hold most of the gridding records, and in instance
+  // order they would all fall to the same few persistent workgroups
+  std::vector<std::vector<FftWork>> pa_d(n), pa_b(n);
+  int32_t blocks_d = 0, blocks_b = 0;
   int max_tiles = 0;
   int maxN = 0;
   for (int i = 0; i < n; ++i) maxN = std::max(maxN, (int)b->n_img[i]);
@@ -434,16 +439,25 @@ Plan* get_plan(mi_ctx* ctx, const mi_batch* b, hipStream_t st) {
     for (int t = 0; t < ntd; ++t) tile_inst_d.push_back(i);
     for (int t = 0; t < ntb; ++t) tile_inst_b.push_back(i);
     const int nld = fft_lines_per_block_host(N, P->elems_d), nrb = fft_real_lines_per_block_host(2 * N, P->elems_b);
-    d.blk_base_d = (int32_t)wa_d.size();
-    d.blk_base_b = (int32_t)wa_b.size();
+    // line blocks are numbered instance by instance (the gridding records' block index)
+    d.blk_base_d = blocks_d;
+    d.blk_base_b = blocks_b;
     fused = fused && nld >= 2 && nrb >= 2;
     const int nyd = fft_rows_per_block_host(N, P->elems_d), nyb = fft_rows_per_block_host(2 * N, P->elems_b);
-    for (int l = 0; l < N / 2; l += nld) wa_d.push_back({i, l});
+    for (int l = 0; l < N / 2; l += nld, ++blocks_d) pa_d[i].push_back({i, l});
     for (int y = 0; y < N; y += nyd) wb_d.push_back({i, y});
-    for (int l = 0; l < N; l += nrb) wa_b.push_back({i, l});        // beam: N real lines
+    for (int l = 0; l < N; l += nrb, ++blocks_b) pa_b[i].push_back({i, l});   // beam: N real lines
     for (int y = 0; y <= N; y += nyb) wb_b.push_back({i, y});       // beam: rows 0..N
     P->max_N = std::max(P->max_N, N);
     P->max_nvis = std::max(P->max_nvis, d.n_vis);
+  }
+  for (size_t k = 0;; ++k) {
+    bool any = false;
+    for (int i = 0; i < n; ++i) {
+      if (k < pa_d[i].size()) { wa_d.push_back(pa_d[i][k]); any = true; }
+      if (k < pa_b[i].size()) { wa_b.push_back(pa_b[i][k]); any = true; }
+    }
+    if (!any) break;
   }
   if (P->total_ent >= (1LL << 31)) fail(MI_ERR_SHAPE, "batch too large: %lld gridding entries", (long long)P->total_ent);
   P->bin_lds = (size_t)max_tiles * sizeof(int);
