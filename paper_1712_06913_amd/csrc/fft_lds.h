@@ -93,9 +93,11 @@ __device__ __forceinline__ int pd(int i) { return i + (i >> 3); }
 // and writes y[(b/L) L R + b%L + q L] after twiddling by w^m, w = exp(s 2 pi i (b%L)/(L R));
 // w comes from the FP64 table and its powers by recurrence in FP64, each rounded once to
 // the data's precision (V = double2 or float2).
+// wreg: when not null, the twiddle w (sign applied) shared by all of this thread's
+// butterflies in the pass (TwRegs); otherwise read from the table.
 template <int R, int ELEMS, int THREADS, typename V>
 __device__ __forceinline__ void stockham_pass(V* buf, int log2P, int log2L, int nl, double s,
-                                              const double2* __restrict__ tw) {
+                                              const double2* __restrict__ tw, const double2* wreg = nullptr) {
   constexpr int BPT = (ELEMS / THREADS / R) > 0 ? ELEMS / THREADS / R : 1;
   constexpr int LOG2R = R == 8 ? 3 : (R == 4 ? 2 : 1);
   const int log2nb = log2P - LOG2R;
@@ -122,8 +124,13 @@ __device__ __forceinline__ void stockham_pass(V* buf, int log2P, int log2L, int 
       const int line = b >> log2nb, bb = b & (nb - 1);
       const int j = bb & (L - 1), blk = bb >> log2L;
       if (L > 1) {
-        double2 w1 = tw[j << tw_shift];
-        w1.y *= s;
+        double2 w1;
+        if (wreg) {
+          w1 = *wreg;
+        } else {
+          w1 = tw[j << tw_shift];
+          w1.y *= s;
+        }
         double2 w = w1;
         x[q][1] = cmul(x[q][1], tw_as<V>(w));
 #pragma unroll
@@ -141,17 +148,80 @@ __device__ __forceinline__ void stockham_pass(V* buf, int log2P, int log2L, int 
   __syncthreads();
 }
 
+// log2 of the radix of the next pass when rem of log2P bits are left: radix 8 while more
+// than 4 bits remain, then 4 (4 bits as 4 x 4, 2 bits), 8 (3 bits) or 2 (1 bit).
+__device__ __forceinline__ int pass_log2r(int rem) { return (rem == 4 || rem == 2) ? 2 : (rem == 1 ? 1 : 3); }
+
 // Full length-P FFT (sign s) of nl lines in LDS; nl * P <= ELEMS.
 template <int ELEMS, int THREADS, typename V>
 __device__ __forceinline__ void lds_fft(V* buf, int log2P, int nl, double s, const double2* __restrict__ tw) {
   int done = 0, rem = log2P;
   while (rem > 0) {
-    const int r = (rem == 4 || rem == 2) ? 2 : (rem == 1 ? 1 : 3);
+    const int r = pass_log2r(rem);
     if (r == 3) stockham_pass<8, ELEMS, THREADS>(buf, log2P, done, nl, s, tw);
     else if (r == 2) stockham_pass<4, ELEMS, THREADS>(buf, log2P, done, nl, s, tw);
     else stockham_pass<2, ELEMS, THREADS>(buf, log2P, done, nl, s, tw);
     done += r;
     rem -= r;
+  }
+}
+
+// Twiddles held in registers.  A pass's twiddle depends only on the thread, P and the
+// pass, not on the data, so a persistent kernel loads its threads' twiddles once per line
+// length (ensure) and its transforms then issue no global loads at all: a global load
+// inside a transform would also wait for every older load and store of the workgroup (the
+// vector memory counter completes in order), i.e. for the next work item's prefetch.
+// Covers P = 4 .. 4096 in 4096-point workgroups of at least 512 threads: at most four
+// passes (radix 8 or 4), the first without twiddles, and in each pass P / R <= THREADS, so
+// the butterflies b and b + THREADS of a thread share j = (b mod P/R) mod L and one
+// twiddle per pass serves them all.  Larger workgroups keep the table reads.
+template <int ELEMS, int THREADS>
+struct TwRegs {
+  static constexpr bool ON = ELEMS <= 4096 && THREADS >= 512;
+  static constexpr int NP = 3;                                             // passes after the first
+  double2 w[NP];
+  int log2P = -1;
+
+  __device__ __forceinline__ void ensure(int lp, double s, const double2* __restrict__ tw) {
+    if (!ON || lp == log2P) return;
+    log2P = lp;
+    int done = 0, rem = lp;
+#pragma unroll
+    for (int p = 0; p <= NP; ++p) {
+      if (rem > 0) {
+        const int r = pass_log2r(rem);
+        if (p > 0) {
+          const int j = ((int)threadIdx.x & ((1 << (lp - r)) - 1)) & ((1 << done) - 1);
+          double2 w1 = tw[j << (13 - done - r)];
+          w1.y *= s;
+          w[p - 1] = w1;
+        }
+        done += r;
+        rem -= r;
+      }
+    }
+  }
+};
+
+// lds_fft with the twiddles of t (loaded by t.ensure for this log2P and sign).
+template <int ELEMS, int THREADS, typename V>
+__device__ __forceinline__ void lds_fft(V* buf, int log2P, int nl, double s, const double2* __restrict__ tw,
+                                        const TwRegs<ELEMS, THREADS>& t) {
+  if constexpr (!TwRegs<ELEMS, THREADS>::ON) {
+    lds_fft<ELEMS, THREADS>(buf, log2P, nl, s, tw);
+  } else {
+    int done = 0, rem = log2P;
+#pragma unroll
+    for (int p = 0; p <= TwRegs<ELEMS, THREADS>::NP; ++p) {
+      if (rem > 0) {
+        const int r = pass_log2r(rem);
+        const double2* wr = &t.w[p > 0 ? p - 1 : 0];
+        if (r == 3) stockham_pass<8, ELEMS, THREADS>(buf, log2P, done, nl, s, tw, wr);
+        else stockham_pass<4, ELEMS, THREADS>(buf, log2P, done, nl, s, tw, wr);
+        done += r;
+        rem -= r;
+      }
+    }
   }
 }
 

@@ -92,6 +92,7 @@ k_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int
   };
   int w = blockIdx.x;
   if (w < n_work) fetch(w);
+  TwRegs<ELEMS, THREADS> twr;
   for (; w < n_work; w += gridDim.x) {
     const FftWork wk = work[w];
     const InstDesc d = inst[wk.inst];
@@ -109,9 +110,10 @@ k_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int
       const int q = threadIdx.x + i * THREADS;
       if (q < n) buf[pd(q)] = r[i];
     }
+    twr.ensure(log2P, +1.0, T.twiddle);
     __syncthreads();
     if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
-    lds_fft<ELEMS, THREADS>(buf, log2P, nl, +1.0, T.twiddle);
+    lds_fft<ELEMS, THREADS>(buf, log2P, nl, +1.0, T.twiddle, twr);
     for (int q = threadIdx.x; q < n; q += THREADS) {
       const int y = q >> log2nl, l = q & (nl - 1);
       blk[q] = buf[pd((l << log2P) + y)];
@@ -153,6 +155,7 @@ k_fft_b_c2r(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
   };
   int w = blockIdx.x;
   if (w < n_work) fetch(w);
+  TwRegs<ELEMS, THREADS> twr;
   for (; w < n_work; w += gridDim.x) {
     const FftWork wk = work[w];
     const InstDesc d = inst[wk.inst];
@@ -178,9 +181,10 @@ k_fft_b_c2r(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
       }
     }
     for (int zl = threadIdx.x; zl < nz; zl += THREADS) buf[pd(zl << log2P)] = make_double2(0.0, 0.0);
+    twr.ensure(log2P, +1.0, T.twiddle);
     __syncthreads();
     if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
-    lds_fft<ELEMS, THREADS>(buf, log2P, nz, +1.0, T.twiddle);
+    lds_fft<ELEMS, THREADS>(buf, log2P, nz, +1.0, T.twiddle, twr);
     const double bd = b0[2 * wk.inst];
     const double inv_b0 = bd > 0.0 ? 1.0 / bd : 0.0;
     const double* ic = T.inv_corr + (P - 64);
@@ -302,6 +306,7 @@ k_grid_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work
     cnt = tcount[bk];
     if (eo < PER && eo < cnt) r0 = load_rec(rec, st + eo);
   }
+  TwRegs<ELEMS, THREADS> twr;
   for (; w < n_work; w += gridDim.x) {
     const int wn = w + gridDim.x;
     const int bn = wn < n_work ? rec_block<ELEMS, false>(inst, work, wn) : 0;
@@ -311,6 +316,7 @@ k_grid_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work
     const int P = d.N, log2P = ilog2(P);
     const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
     const int n = nl * P;
+    twr.ensure(log2P, +1.0, T.twiddle);
     for (int q = threadIdx.x; q < n; q += THREADS) buf[pd(q)] = make_double2(0.0, 0.0);
     __syncthreads();
     grid_block<THREADS, false>(buf, tab, rec, r0, st, cnt, P, wk.first, nl);
@@ -318,7 +324,7 @@ k_grid_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work
     st = stn;
     cnt = cntn;
     __syncthreads();
-    lds_fft<ELEMS, THREADS>(buf, log2P, nl, +1.0, T.twiddle);
+    lds_fft<ELEMS, THREADS>(buf, log2P, nl, +1.0, T.twiddle, twr);
     double2* blk = grid + d.gd_off + (int64_t)wk.first * P;
     for (int q = threadIdx.x; q < n; q += THREADS) {
       const int y = q >> log2nl, l = q & (nl - 1);
@@ -349,6 +355,7 @@ k_grid_fft_a_real(const InstDesc* __restrict__ inst, const FftWork* __restrict__
     cnt = tcount[bk];
     if (eo < PER && eo < cnt) r0 = load_rec(rec, st + eo);
   }
+  TwRegs<ELEMS, THREADS> twr;
   for (; w < n_work; w += gridDim.x) {
     const int wn = w + gridDim.x;
     const int bn = wn < n_work ? rec_block<ELEMS, true>(inst, work, wn) : 0;
@@ -358,6 +365,7 @@ k_grid_fft_a_real(const InstDesc* __restrict__ inst, const FftWork* __restrict__
     const int P = 2 * d.N, log2P = ilog2(P), h = P / 2;
     const int nr = real_lines_per_block<ELEMS>(P), log2nr = ilog2(nr), nc = nr / 2;
     const int n = nc * P;
+    twr.ensure(log2P, +1.0, T.twiddle);
     for (int q = threadIdx.x; q < n; q += THREADS) buf[pd(q)] = make_double2(0.0, 0.0);
     __syncthreads();
     grid_block<THREADS, true>(buf, tab, rec, r0, st, cnt, P, wk.first, nr);
@@ -365,7 +373,7 @@ k_grid_fft_a_real(const InstDesc* __restrict__ inst, const FftWork* __restrict__
     st = stn;
     cnt = cntn;
     __syncthreads();
-    lds_fft<ELEMS, THREADS>(buf, log2P, nc, +1.0, T.twiddle);
+    lds_fft<ELEMS, THREADS>(buf, log2P, nc, +1.0, T.twiddle, twr);
     double2* o = reinterpret_cast<double2*>(grid + d.gb_off + (int64_t)wk.first * P);   // nr x P/2 complex
     const int log2nc = log2nr - 1;
     for (int q = threadIdx.x; q < nc * h; q += THREADS) {   // slot sl of lines 2c and 2c + 1
@@ -427,6 +435,7 @@ k_fft_a_real(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work
   };
   int w = blockIdx.x;
   if (w < n_work) fetch(w);
+  TwRegs<ELEMS, THREADS> twr;
   for (; w < n_work; w += gridDim.x) {
     const FftWork wk = work[w];
     const InstDesc d = inst[wk.inst];
@@ -440,9 +449,10 @@ k_fft_a_real(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work
         buf[pd(2 * q + 1)] = make_double2(ra[i].y, rb[i].y);
       }
     }
+    twr.ensure(log2P, +1.0, T.twiddle);
     __syncthreads();
     if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
-    lds_fft<ELEMS, THREADS>(buf, log2P, nc, +1.0, T.twiddle);
+    lds_fft<ELEMS, THREADS>(buf, log2P, nc, +1.0, T.twiddle, twr);
     double2* o = reinterpret_cast<double2*>(grid + d.gb_off + (int64_t)wk.first * P);   // nr x P/2 complex
     const int log2nc = log2nr - 1;
     for (int q = threadIdx.x; q < nc * h; q += THREADS) {   // slot sl of lines 2c and 2c + 1
@@ -512,6 +522,7 @@ k_fft_b_c2r_sym(const InstDesc* __restrict__ inst, const FftWork* __restrict__ w
   };
   int w = blockIdx.x;
   if (w < n_work) fetch(w);
+  TwRegs<ELEMS, THREADS> twr;
   for (; w < n_work; w += gridDim.x) {
     const FftWork wk = work[w];
     const InstDesc d = inst[wk.inst];
@@ -537,9 +548,10 @@ k_fft_b_c2r_sym(const InstDesc* __restrict__ inst, const FftWork* __restrict__ w
       }
     }
     for (int zl = threadIdx.x; zl < nz; zl += THREADS) buf[pd(zl << log2P)] = make_double2(0.0, 0.0);
+    twr.ensure(log2P, +1.0, T.twiddle);
     __syncthreads();
     if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
-    lds_fft<ELEMS, THREADS>(buf, log2P, nz, +1.0, T.twiddle);
+    lds_fft<ELEMS, THREADS>(buf, log2P, nz, +1.0, T.twiddle, twr);
     const double bd = b0[2 * wk.inst + 1];
     const double inv_b0 = bd > 0.0 ? 1.0 / bd : 0.0;
     const double* ic = T.inv_corr + (P - 64);
@@ -615,6 +627,7 @@ k_fft_b_r2c(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
   };
   int w = blockIdx.x;
   if (w < n_work) fetch(w);
+  TwRegs<ELEMS, THREADS> twr;
   for (; w < n_work; w += gridDim.x) {
     const FftWork wk = work[w];
     const InstDesc d = inst[wk.inst];
@@ -635,9 +648,10 @@ k_fft_b_r2c(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
         buf[pd(q)] = make_double2((double)ra[i] * s, (double)rb[i] * s2);
       }
     }
+    twr.ensure(log2P, -1.0, T.twiddle);
     __syncthreads();
     if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
-    lds_fft<ELEMS, THREADS>(buf, log2P, nz, -1.0, T.twiddle);
+    lds_fft<ELEMS, THREADS>(buf, log2P, nz, -1.0, T.twiddle, twr);
     double2* dst = yb + d.gd_off;
     const int nblk = h / nl, per_blk = nz * nl, log2pb = ilog2(per_blk);   // powers of two
     for (int q = threadIdx.x; q < nblk * per_blk; q += THREADS) {
@@ -683,6 +697,7 @@ k_fft_a_fwd(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
   };
   int w = blockIdx.x;
   if (w < n_work) fetch(w);
+  TwRegs<ELEMS, THREADS> twr;
   for (; w < n_work; w += gridDim.x) {
     const FftWork wk = work[w];
     const InstDesc d = inst[wk.inst];
@@ -700,9 +715,10 @@ k_fft_a_fwd(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
       const int q = threadIdx.x + i * THREADS;
       if (q < n) buf[pd(((q & (nl - 1)) << log2P) + (q >> log2nl))] = r[i];
     }
+    twr.ensure(log2P, -1.0, T.twiddle);
     __syncthreads();
     if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
-    lds_fft<ELEMS, THREADS>(buf, log2P, nl, -1.0, T.twiddle);
+    lds_fft<ELEMS, THREADS>(buf, log2P, nl, -1.0, T.twiddle, twr);
     for (int q = threadIdx.x; q < n; q += THREADS) {
       const int l = q >> log2P, j = q & (P - 1);
       double2 v = buf[pd(q)];
