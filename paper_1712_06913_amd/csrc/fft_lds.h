@@ -200,6 +200,11 @@ struct TwRegs {
         rem -= r;
       }
     }
+    // Settle the loads here, once per line length: otherwise the compiler cannot tell at
+    // a twiddle's use whether the load that wrote it is still pending and waits for every
+    // outstanding memory operation there, i.e. for the prefetch the twiddles are meant to
+    // let the transform overlap.
+    __builtin_amdgcn_s_waitcnt(0);
   }
 };
 

@@ -114,7 +114,12 @@ k_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int
     __syncthreads();
     if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
     lds_fft<ELEMS, THREADS>(buf, log2P, nl, +1.0, T.twiddle, twr);
-    for (int q = threadIdx.x; q < n; q += THREADS) {
+    // a fixed number of unconditional store rounds (n is a power of two; for P < 128 the
+    // extra rounds repeat elements with identical values), so that the compiler can count
+    // them and a later wait for an older load does not wait for these stores too
+#pragma unroll
+    for (int rd = 0; rd < ELEMS / THREADS; ++rd) {
+      const int q = (threadIdx.x + rd * THREADS) & (n - 1);
       const int y = q >> log2nl, l = q & (nl - 1);
       blk[q] = buf[pd((l << log2P) + y)];
     }
@@ -140,21 +145,25 @@ k_fft_b_c2r(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
     const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
     const int nz = rows_per_block<ELEMS>(P) / 2, log2pb = ilog2(nz * nl);
     const double2* src = yb + d.gd_off;
+    // unconditional loads (lanes past the item's h * nz elements, only for P < 128, load
+    // duplicates that staging ignores): a load under a lane condition leaves the compiler
+    // unsure at later joins whether it is still pending, and it then waits for everything
 #pragma unroll
     for (int i = 0; i < NPT; ++i) {
-      const int q = threadIdx.x + i * THREADS;
-      if (q < h * nz) {
-        const int b = q >> log2pb, r = q & ((1 << log2pb) - 1);
-        const int zl = r >> log2nl, l = r & (nl - 1);
-        const int64_t e = (int64_t)b * nl * P + (int64_t)(wk.first + 2 * zl) * nl + l;
-        const double2 v1 = src[e], v2 = src[e + nl];
-        r1[i] = make_double2(v1.x, v1.y);
-        r2[i] = make_double2(v2.x, v2.y);
-      }
+      const int q = (threadIdx.x + i * THREADS) & (h * nz - 1);
+      const int b = q >> log2pb, r = q & ((1 << log2pb) - 1);
+      const int zl = r >> log2nl, l = r & (nl - 1);
+      const int64_t e = (int64_t)b * nl * P + (int64_t)(wk.first + 2 * zl) * nl + l;
+      const double2 v1 = src[e], v2 = src[e + nl];
+      r1[i] = make_double2(v1.x, v1.y);
+      r2[i] = make_double2(v2.x, v2.y);
     }
   };
   int w = blockIdx.x;
   if (w < n_work) fetch(w);
+  // the first item's loads settled here, so that the staging of every later item (reached
+  // with the previous item's stores still in flight) waits only for its prefetch
+  __builtin_amdgcn_s_waitcnt(0);
   TwRegs<ELEMS, THREADS> twr;
   for (; w < n_work; w += gridDim.x) {
     const FftWork wk = work[w];
@@ -164,40 +173,57 @@ k_fft_b_c2r(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
     const int ny = rows_per_block<ELEMS>(P), nz = ny / 2, log2pb = ilog2(nz * nl);
     const int y0 = wk.first;
 #pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-      const int q = threadIdx.x + i * THREADS;
-      if (q < h * nz) {
-        const int b = q >> log2pb, r = q & ((1 << log2pb) - 1);
-        const int zl = r >> log2nl, l = r & (nl - 1);
-        const double2 v1 = r1[i], v2 = r2[i];
-        const int k = b * nl + l + 1;          // u frequency index 1..P/2
-        const int row = zl << log2P;
-        if (k < h) {
-          buf[pd(row + k)] = make_double2(v1.x - v2.y, v1.y + v2.x);
-          buf[pd(row + P - k)] = make_double2(v1.x + v2.y, v2.x - v1.y);
-        } else {
-          buf[pd(row + k)] = make_double2(v1.x, v2.x);   // u = 0 column: real by symmetry
-        }
+    for (int i = 0; i < NPT; ++i) {            // registers read by every lane, LDS written for the item's elements
+      const int qi = threadIdx.x + i * THREADS, q = qi & (h * nz - 1);
+      const int b = q >> log2pb, r = q & ((1 << log2pb) - 1);
+      const int zl = r >> log2nl, l = r & (nl - 1);
+      const double2 v1 = r1[i], v2 = r2[i];
+      const int k = b * nl + l + 1;            // u frequency index 1..P/2
+      const int row = zl << log2P;
+      // u = 0 column (k = P/2): real by symmetry
+      const double2 za = k < h ? make_double2(v1.x - v2.y, v1.y + v2.x) : make_double2(v1.x, v2.x);
+      const double2 zb = make_double2(v1.x + v2.y, v2.x - v1.y);
+      if (qi < h * nz) {
+        buf[pd(row + k)] = za;
+        if (k < h) buf[pd(row + P - k)] = zb;
       }
     }
     for (int zl = threadIdx.x; zl < nz; zl += THREADS) buf[pd(zl << log2P)] = make_double2(0.0, 0.0);
     twr.ensure(log2P, +1.0, T.twiddle);
     __syncthreads();
-    if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
+    fetch(min(w + (int)gridDim.x, n_work - 1));   // after the last item: a harmless reload
     lds_fft<ELEMS, THREADS>(buf, log2P, nz, +1.0, T.twiddle, twr);
     const double bd = b0[2 * wk.inst];
     const double inv_b0 = bd > 0.0 ? 1.0 / bd : 0.0;
     const double* ic = T.inv_corr + (P - 64);
     float* o = out + d.img_off + (int64_t)y0 * P;
-    for (int q4 = threadIdx.x; q4 < nz * P / 4; q4 += THREADS) {   // pixels x .. x + 3 of rows y0 + 2 zl, + 1
-      const int q = 4 * q4;
+    // Output phase with a fixed number of rounds: when the item holds fewer pixels (P < 128)
+    // the extra rounds repeat earlier ones with identical values.  All correction factors are
+    // loaded before the first store and every store is unconditional, so no load here waits
+    // behind a store and the next item's staging waits only for its own prefetch (the vector
+    // memory counter completes in order and counts stores too).
+    constexpr int NRD = ELEMS / 4 / THREADS;
+    const int nq4 = nz * P / 4;                                    // a power of two
+    double cx[NRD][4], cy[NRD][2];
+#pragma unroll
+    for (int rd = 0; rd < NRD; ++rd) {
+      const int q = 4 * ((threadIdx.x + rd * THREADS) & (nq4 - 1));
+      const int x = q & (P - 1), y = y0 + 2 * (q >> log2P);
+      cy[rd][0] = ic[y];
+      cy[rd][1] = ic[y + 1];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) cx[rd][e] = ic[x + e];
+    }
+#pragma unroll
+    for (int rd = 0; rd < NRD; ++rd) {   // pixels x .. x + 3 of rows y0 + 2 zl, + 1
+      const int q = 4 * ((threadIdx.x + rd * THREADS) & (nq4 - 1));
       const int zl = q >> log2P, x = q & (P - 1);
       const int y = y0 + 2 * zl;
-      const double ry = ic[y] * inv_b0, ry1 = ic[y + 1] * inv_b0;
+      const double ry = cy[rd][0] * inv_b0, ry1 = cy[rd][1] * inv_b0;
       float fa[4], fb[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        double s0 = ic[x + e] * ry, s1 = ic[x + e] * ry1;
+        double s0 = cx[rd][e] * ry, s1 = cx[rd][e] * ry1;
         if ((x + e + y) & 1) s0 = -s0;
         else s1 = -s1;
         const double2 z = buf[pd(q + e)];
@@ -222,13 +248,16 @@ k_fft_b_c2r(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
 // the sample's seven lines: the seven threads of a sample touch seven consecutive cells of
 // a line (different LDS banks).  The next work item's range and its first round of records
 // are loaded into registers before the current transform, so their latency hides behind it.
-struct RecRegs { int4 a; float4 b; };
+// Only the fields the gridder uses are loaded (12 + 8 bytes): a loaded register that is
+// never read is free for reuse at once, and overwriting it means waiting for the load, which
+// turns the next item's prefetch into a stall.
+struct RecRegs { int3 a; float2 b; };
 
 __device__ __forceinline__ RecRegs load_rec(const GridRec* __restrict__ rec, int i) {
-  const int4* p = reinterpret_cast<const int4*>(rec + i);
+  const int* p = reinterpret_cast<const int*>(rec + i);
   RecRegs r;
-  r.a = p[0];
-  r.b = __builtin_bit_cast(float4, p[1]);
+  r.a = *reinterpret_cast<const int3*>(p);
+  r.b = *reinterpret_cast<const float2*>(p + 4);
   return r;
 }
 
@@ -306,6 +335,9 @@ k_grid_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work
     cnt = tcount[bk];
     if (eo < PER && eo < cnt) r0 = load_rec(rec, st + eo);
   }
+  // settled once: every later item then waits for its prefetched records only, not for the
+  // previous item's stores (the first item's path would otherwise decide the wait)
+  __builtin_amdgcn_s_waitcnt(0);
   TwRegs<ELEMS, THREADS> twr;
   for (; w < n_work; w += gridDim.x) {
     const int wn = w + gridDim.x;
@@ -326,7 +358,12 @@ k_grid_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work
     __syncthreads();
     lds_fft<ELEMS, THREADS>(buf, log2P, nl, +1.0, T.twiddle, twr);
     double2* blk = grid + d.gd_off + (int64_t)wk.first * P;
-    for (int q = threadIdx.x; q < n; q += THREADS) {
+    // a fixed number of unconditional store rounds (n is a power of two; for P < 128 the
+    // extra rounds repeat elements with identical values), so that the compiler can count
+    // them and a later wait for an older load does not wait for these stores too
+#pragma unroll
+    for (int rd = 0; rd < ELEMS / THREADS; ++rd) {
+      const int q = (threadIdx.x + rd * THREADS) & (n - 1);
       const int y = q >> log2nl, l = q & (nl - 1);
       blk[q] = buf[pd((l << log2P) + y)];
     }
@@ -355,6 +392,9 @@ k_grid_fft_a_real(const InstDesc* __restrict__ inst, const FftWork* __restrict__
     cnt = tcount[bk];
     if (eo < PER && eo < cnt) r0 = load_rec(rec, st + eo);
   }
+  // settled once: every later item then waits for its prefetched records only, not for the
+  // previous item's stores (the first item's path would otherwise decide the wait)
+  __builtin_amdgcn_s_waitcnt(0);
   TwRegs<ELEMS, THREADS> twr;
   for (; w < n_work; w += gridDim.x) {
     const int wn = w + gridDim.x;
@@ -376,7 +416,10 @@ k_grid_fft_a_real(const InstDesc* __restrict__ inst, const FftWork* __restrict__
     lds_fft<ELEMS, THREADS>(buf, log2P, nc, +1.0, T.twiddle, twr);
     double2* o = reinterpret_cast<double2*>(grid + d.gb_off + (int64_t)wk.first * P);   // nr x P/2 complex
     const int log2nc = log2nr - 1;
-    for (int q = threadIdx.x; q < nc * h; q += THREADS) {   // slot sl of lines 2c and 2c + 1
+    // fixed, unconditional store rounds as in k_grid_fft_a (nc h is a power of two)
+#pragma unroll
+    for (int rd = 0; rd < ELEMS / 2 / THREADS; ++rd) {   // slot sl of lines 2c and 2c + 1
+      const int q = (threadIdx.x + rd * THREADS) & (nc * h - 1);
       const int sl = q >> log2nc, c = q & (nc - 1);
       const int row = c << log2P;
       const double2 Z = buf[pd(row + sl)];
@@ -455,7 +498,10 @@ k_fft_a_real(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work
     lds_fft<ELEMS, THREADS>(buf, log2P, nc, +1.0, T.twiddle, twr);
     double2* o = reinterpret_cast<double2*>(grid + d.gb_off + (int64_t)wk.first * P);   // nr x P/2 complex
     const int log2nc = log2nr - 1;
-    for (int q = threadIdx.x; q < nc * h; q += THREADS) {   // slot sl of lines 2c and 2c + 1
+    // fixed, unconditional store rounds as in k_grid_fft_a (nc h is a power of two)
+#pragma unroll
+    for (int rd = 0; rd < ELEMS / 2 / THREADS; ++rd) {   // slot sl of lines 2c and 2c + 1
+      const int q = (threadIdx.x + rd * THREADS) & (nc * h - 1);
       const int sl = q >> log2nc, c = q & (nc - 1);
       const int row = c << log2P;
       const double2 Z = buf[pd(row + sl)];
@@ -488,6 +534,9 @@ k_fft_b_c2r_sym(const InstDesc* __restrict__ inst, const FftWork* __restrict__ w
   __shared__ double2 buf[LDS_PADDED(ELEMS)];
   constexpr int NPT = ELEMS / 2 / THREADS;
   double2 r1[NPT], r2[NPT];
+  // As in k_fft_b_c2r, every global load and store below is unconditional (lanes without an
+  // element of their own load or store duplicates), so that the compiler can count the
+  // memory operations in flight instead of waiting for all of them.
   auto fetch = [&](int wi) {
     const FftWork wk = work[wi];
     const InstDesc d = inst[wk.inst];
@@ -497,31 +546,23 @@ k_fft_b_c2r_sym(const InstDesc* __restrict__ inst, const FftWork* __restrict__ w
     const double2* src = reinterpret_cast<const double2*>(grid + d.gb_off);
 #pragma unroll
     for (int i = 0; i < NPT; ++i) {
-      const int q = threadIdx.x + i * THREADS;
-      if (q < h * nz) {
-        const int b = q >> log2pb, r = q & ((1 << log2pb) - 1);
-        const int zl = r >> log2nr, l = r & (nr - 1);
-        const int ya = wk.first + 2 * zl;
-        const double2* e = src + (int64_t)b * nr * h + l;
-        // ya and P/2 are even, so row P/2 always starts a pair (and is the last row)
-        double2 v1, v2;
-        if (ya == 0) {                       // rows 0 and 1
-          v1 = make_double2(e[0].x, 0.0);
-          v2 = e[nr];
-        } else if (ya < h) {
-          v1 = e[ya * nr];
-          v2 = e[(ya + 1) * nr];
-        } else {                             // row P/2 alone, or past it
-          v1 = make_double2(ya == h ? e[0].y : 0.0, 0.0);
-          v2 = make_double2(0.0, 0.0);
-        }
-        r1[i] = make_double2(v1.x, v1.y);
-        r2[i] = make_double2(v2.x, v2.y);
-      }
+      const int q = (threadIdx.x + i * THREADS) & (h * nz - 1);
+      const int b = q >> log2pb, r = q & ((1 << log2pb) - 1);
+      const int zl = r >> log2nr, l = r & (nr - 1);
+      const int ya = wk.first + 2 * zl;
+      const double2* e = src + (int64_t)b * nr * h + l;
+      // ya and P/2 are even, so row P/2 always starts a pair (and is the last row); slot
+      // row 0 holds rows 0 (real part) and P/2 (imaginary part).  The raw slots are kept:
+      // selecting from them here would wait for the loads at once.
+      const int a1 = ya < h ? ya * nr : 0, a2 = ya < h ? (ya + 1) * nr : 0;
+      const double2 u1 = e[a1], u2 = e[a2];
+      r1[i] = make_double2(u1.x, u1.y);
+      r2[i] = make_double2(u2.x, u2.y);
     }
   };
   int w = blockIdx.x;
   if (w < n_work) fetch(w);
+  __builtin_amdgcn_s_waitcnt(0);           // see k_fft_b_c2r
   TwRegs<ELEMS, THREADS> twr;
   for (; w < n_work; w += gridDim.x) {
     const FftWork wk = work[w];
@@ -532,65 +573,87 @@ k_fft_b_c2r_sym(const InstDesc* __restrict__ inst, const FftWork* __restrict__ w
     const int y0 = wk.first;
 #pragma unroll
     for (int i = 0; i < NPT; ++i) {
-      const int q = threadIdx.x + i * THREADS;
-      if (q < h * nz) {
-        const int b = q >> log2pb, r = q & ((1 << log2pb) - 1);
-        const int zl = r >> log2nr, l = r & (nr - 1);
-        const double2 v1 = r1[i], v2 = r2[i];
-        const int k = b * nr + l + 1;        // u frequency index 1..P/2
-        const int row = zl << log2P;
-        if (k < h) {
-          buf[pd(row + k)] = make_double2(v1.x - v2.y, v1.y + v2.x);
-          buf[pd(row + P - k)] = make_double2(v1.x + v2.y, v2.x - v1.y);
-        } else {
-          buf[pd(row + k)] = make_double2(v1.x, v2.x);   // u = 0 column: real by symmetry
-        }
+      const int qi = threadIdx.x + i * THREADS, q = qi & (h * nz - 1);
+      const int b = q >> log2pb, r = q & ((1 << log2pb) - 1);
+      const int zl = r >> log2nr, l = r & (nr - 1);
+      const int ya = y0 + 2 * zl;
+      const double2 u1 = r1[i], u2 = r2[i];
+      double2 v1 = u1, v2 = u2;            // rows ya, ya + 1
+      if (ya == 0) v1.y = 0.0;             // rows 0 and 1
+      if (ya >= h) {                       // row P/2 alone, or past it
+        v1 = make_double2(ya == h ? u1.y : 0.0, 0.0);
+        v2 = make_double2(0.0, 0.0);
+      }
+      const int k = b * nr + l + 1;        // u frequency index 1..P/2
+      const int row = zl << log2P;
+      // u = 0 column (k = P/2): real by symmetry
+      const double2 za = k < h ? make_double2(v1.x - v2.y, v1.y + v2.x) : make_double2(v1.x, v2.x);
+      const double2 zb = make_double2(v1.x + v2.y, v2.x - v1.y);
+      if (qi < h * nz) {
+        buf[pd(row + k)] = za;
+        if (k < h) buf[pd(row + P - k)] = zb;
       }
     }
     for (int zl = threadIdx.x; zl < nz; zl += THREADS) buf[pd(zl << log2P)] = make_double2(0.0, 0.0);
     twr.ensure(log2P, +1.0, T.twiddle);
     __syncthreads();
-    if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
+    fetch(min(w + (int)gridDim.x, n_work - 1));   // after the last item: a harmless reload
     lds_fft<ELEMS, THREADS>(buf, log2P, nz, +1.0, T.twiddle, twr);
     const double bd = b0[2 * wk.inst + 1];
     const double inv_b0 = bd > 0.0 ? 1.0 / bd : 0.0;
     const double* ic = T.inv_corr + (P - 64);
     float* o = out + d.beam_off;
+    // Output rounds: pixels x, x + 1 of rows ya, ya + 1 (ya <= P/2).  The item's npair row
+    // pairs (nz, or 1 for the item holding row P/2 alone) make npair P/2 pixel pairs, a
+    // power of two; a fixed number of rounds covers them, the extra rounds repeating
+    // earlier ones.  All correction factors are loaded before the first store.
+    constexpr int NRD = ELEMS / 2 / THREADS;
     const int npair = (min(ny, h + 1 - y0) + 1) / 2;
-    for (int q2 = threadIdx.x; q2 < npair * P / 2; q2 += THREADS) {   // pixels x, x + 1 of rows ya, ya + 1
-      const int q = 2 * q2;
+    const int nq2 = npair * P / 2;
+    double cx[NRD][2], cy[NRD][2];
+#pragma unroll
+    for (int rd = 0; rd < NRD; ++rd) {
+      const int q = 2 * ((threadIdx.x + rd * THREADS) & (nq2 - 1));
+      const int x = q & (P - 1), ya = y0 + 2 * (q >> log2P);
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {        // row P/2: its right half from the left half
+        const int xs = (ya == h && x + e > h) ? P - x - e : x + e;
+        cx[rd][e] = ic[xs];
+      }
+      cy[rd][0] = ic[ya];
+      cy[rd][1] = ic[ya + 1];
+    }
+#pragma unroll
+    for (int rd = 0; rd < NRD; ++rd) {
+      const int q = 2 * ((threadIdx.x + rd * THREADS) & (nq2 - 1));
       const int zl = q >> log2P, x = q & (P - 1);
       const int ya = y0 + 2 * zl;
       const int row = zl << log2P;
+      const bool mid = ya == h;            // row P/2 alone: no second row, no mirror row
+      const double ra = cy[rd][0] * inv_b0, rb = cy[rd][1] * inv_b0;
       float fa[2], fb[2];
-      if (ya == h) {                       // row P/2: its right half mirrors its left half
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const int xs = x + e > h ? P - x - e : x + e;
-          double s = ic[xs] * (ic[ya] * inv_b0);
-          if ((xs + ya) & 1) s = -s;
-          fa[e] = (float)(buf[pd(row + xs)].x * s);
-        }
-        *reinterpret_cast<float2*>(o + (ya << log2P) + x) = make_float2(fa[0], fa[1]);
-        continue;
-      }
-      const double ra = ic[ya] * inv_b0, rb = ic[ya + 1] * inv_b0;
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
-        double sa = ic[x + e] * ra, sb = ic[x + e] * rb;
-        if ((x + e + ya) & 1) sa = -sa;
+        const int xs = (mid && x + e > h) ? P - x - e : x + e;
+        double sa = cx[rd][e] * ra, sb = cx[rd][e] * rb;
+        if ((xs + ya) & 1) sa = -sa;
         else sb = -sb;
-        const double2 z = buf[pd(row + x + e)];
+        const double2 z = buf[pd(row + xs)];
         fa[e] = (float)(z.x * sa);
-        fb[e] = (float)(z.y * sb);
+        fb[e] = mid ? fa[e] : (float)(z.y * sb);
       }
+      // stores: row ya; row ya + 1 (row P/2: row P/2 again, same values); the mirror of row
+      // ya at P - ya (row 0: itself, same values) and of row ya + 1 at P - ya - 1 (row P/2:
+      // the mirrored half of row P/2, whose values equal those of its left half)
+      const int yb = mid ? ya : ya + 1;
       *reinterpret_cast<float2*>(o + (ya << log2P) + x) = make_float2(fa[0], fa[1]);
-      *reinterpret_cast<float2*>(o + ((ya + 1) << log2P) + x) = make_float2(fb[0], fb[1]);
+      *reinterpret_cast<float2*>(o + (yb << log2P) + x) = make_float2(fb[0], fb[1]);
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const int xm = (P - x - e) & (P - 1);
         if (ya > 0) o[((P - ya) << log2P) + xm] = fa[e];
-        o[((P - ya - 1) << log2P) + xm] = fb[e];
+        else o[x + e] = fa[e];
+        o[((P - yb) << log2P) + xm] = fb[e];
       }
     }
     __syncthreads();
