@@ -93,7 +93,7 @@ __device__ __forceinline__ int pd(int i) { return i + (i >> 3); }
 // and writes y[(b/L) L R + b%L + q L] after twiddling by w^m, w = exp(s 2 pi i (b%L)/(L R));
 // w comes from the FP64 table and its powers by recurrence in FP64, each rounded once to
 // the data's precision (V = double2 or float2).
-// wreg: when not null, the twiddle w (sign applied) shared by all of this thread's
+// wreg: when not null, the twiddle exp(+2 pi i j / (L R)) shared by all of this thread's
 // butterflies in the pass (TwRegs); otherwise read from the table.
 template <int R, int ELEMS, int THREADS, typename V>
 __device__ __forceinline__ void stockham_pass(V* buf, int log2P, int log2L, int nl, double s,
@@ -124,13 +124,8 @@ __device__ __forceinline__ void stockham_pass(V* buf, int log2P, int log2L, int 
       const int line = b >> log2nb, bb = b & (nb - 1);
       const int j = bb & (L - 1), blk = bb >> log2L;
       if (L > 1) {
-        double2 w1;
-        if (wreg) {
-          w1 = *wreg;
-        } else {
-          w1 = tw[j << tw_shift];
-          w1.y *= s;
-        }
+        double2 w1 = wreg ? *wreg : tw[j << tw_shift];
+        w1.y *= s;
         double2 w = w1;
         x[q][1] = cmul(x[q][1], tw_as<V>(w));
 #pragma unroll
@@ -167,14 +162,15 @@ __device__ __forceinline__ void lds_fft(V* buf, int log2P, int nl, double s, con
 }
 
 // Twiddles held in registers.  A pass's twiddle depends only on the thread, P and the
-// pass, not on the data, so a persistent kernel loads its threads' twiddles once per line
-// length (ensure) and its transforms then issue no global loads at all: a global load
-// inside a transform would also wait for every older load and store of the workgroup (the
-// vector memory counter completes in order), i.e. for the next work item's prefetch.
-// Covers P = 4 .. 4096 in 4096-point workgroups of at least 512 threads: at most four
-// passes (radix 8 or 4), the first without twiddles, and in each pass P / R <= THREADS, so
-// the butterflies b and b + THREADS of a thread share j = (b mod P/R) mod L and one
-// twiddle per pass serves them all.  Larger workgroups keep the table reads.
+// pass, not on the data, so a kernel loads its threads' twiddles before its data and its
+// transforms then issue no global loads: a global load inside a transform waits for its
+// own round trip, pass after pass, and also for every older load and store of the
+// workgroup (the vector memory counter completes in order), e.g. a persistent kernel's
+// prefetch of its next item.  Covers P = 4 .. 4096 in 4096-point workgroups of at least
+// 512 threads: at most four passes (radix 8 or 4), the first without twiddles, and in each
+// pass P / R <= THREADS, so the butterflies b and b + THREADS of a thread share
+// j = (b mod P/R) mod L and one twiddle per pass serves them all.  Larger workgroups keep
+// the table reads.
 template <int ELEMS, int THREADS>
 struct TwRegs {
   static constexpr bool ON = ELEMS <= 4096 && THREADS >= 512;
@@ -182,8 +178,9 @@ struct TwRegs {
   double2 w[NP];
   int log2P = -1;
 
-  __device__ __forceinline__ void ensure(int lp, double s, const double2* __restrict__ tw) {
-    if (!ON || lp == log2P) return;
+  // Issue the loads for line length 2^lp (the first use waits for them).
+  __device__ __forceinline__ void load(int lp, const double2* __restrict__ tw) {
+    if (!ON) return;
     log2P = lp;
     int done = 0, rem = lp;
 #pragma unroll
@@ -192,18 +189,21 @@ struct TwRegs {
         const int r = pass_log2r(rem);
         if (p > 0) {
           const int j = ((int)threadIdx.x & ((1 << (lp - r)) - 1)) & ((1 << done) - 1);
-          double2 w1 = tw[j << (13 - done - r)];
-          w1.y *= s;
-          w[p - 1] = w1;
+          w[p - 1] = tw[j << (13 - done - r)];
         }
         done += r;
         rem -= r;
       }
     }
-    // Settle the loads here, once per line length: otherwise the compiler cannot tell at
-    // a twiddle's use whether the load that wrote it is still pending and waits for every
-    // outstanding memory operation there, i.e. for the prefetch the twiddles are meant to
-    // let the transform overlap.
+  }
+
+  // Persistent kernels: load when the line length changes, and settle the loads there, once
+  // per line length; otherwise the compiler cannot tell at a twiddle's use whether the load
+  // that wrote it is still pending and waits for every outstanding memory operation there,
+  // i.e. for the prefetch the twiddles are meant to let the transform overlap.
+  __device__ __forceinline__ void ensure(int lp, const double2* __restrict__ tw) {
+    if (!ON || lp == log2P) return;
+    load(lp, tw);
     __builtin_amdgcn_s_waitcnt(0);
   }
 };

@@ -110,7 +110,7 @@ k_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work, int
       const int q = threadIdx.x + i * THREADS;
       if (q < n) buf[pd(q)] = r[i];
     }
-    twr.ensure(log2P, +1.0, T.twiddle);
+    twr.ensure(log2P, T.twiddle);
     __syncthreads();
     if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
     lds_fft<ELEMS, THREADS>(buf, log2P, nl, +1.0, T.twiddle, twr);
@@ -189,7 +189,7 @@ k_fft_b_c2r(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
       }
     }
     for (int zl = threadIdx.x; zl < nz; zl += THREADS) buf[pd(zl << log2P)] = make_double2(0.0, 0.0);
-    twr.ensure(log2P, +1.0, T.twiddle);
+    twr.ensure(log2P, T.twiddle);
     __syncthreads();
     fetch(min(w + (int)gridDim.x, n_work - 1));   // after the last item: a harmless reload
     lds_fft<ELEMS, THREADS>(buf, log2P, nz, +1.0, T.twiddle, twr);
@@ -348,7 +348,7 @@ k_grid_fft_a(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work
     const int P = d.N, log2P = ilog2(P);
     const int nl = lines_per_block<ELEMS>(P), log2nl = ilog2(nl);
     const int n = nl * P;
-    twr.ensure(log2P, +1.0, T.twiddle);
+    twr.ensure(log2P, T.twiddle);
     for (int q = threadIdx.x; q < n; q += THREADS) buf[pd(q)] = make_double2(0.0, 0.0);
     __syncthreads();
     grid_block<THREADS, false>(buf, tab, rec, r0, st, cnt, P, wk.first, nl);
@@ -405,7 +405,7 @@ k_grid_fft_a_real(const InstDesc* __restrict__ inst, const FftWork* __restrict__
     const int P = 2 * d.N, log2P = ilog2(P), h = P / 2;
     const int nr = real_lines_per_block<ELEMS>(P), log2nr = ilog2(nr), nc = nr / 2;
     const int n = nc * P;
-    twr.ensure(log2P, +1.0, T.twiddle);
+    twr.ensure(log2P, T.twiddle);
     for (int q = threadIdx.x; q < n; q += THREADS) buf[pd(q)] = make_double2(0.0, 0.0);
     __syncthreads();
     grid_block<THREADS, true>(buf, tab, rec, r0, st, cnt, P, wk.first, nr);
@@ -492,7 +492,7 @@ k_fft_a_real(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work
         buf[pd(2 * q + 1)] = make_double2(ra[i].y, rb[i].y);
       }
     }
-    twr.ensure(log2P, +1.0, T.twiddle);
+    twr.ensure(log2P, T.twiddle);
     __syncthreads();
     if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
     lds_fft<ELEMS, THREADS>(buf, log2P, nc, +1.0, T.twiddle, twr);
@@ -595,7 +595,7 @@ k_fft_b_c2r_sym(const InstDesc* __restrict__ inst, const FftWork* __restrict__ w
       }
     }
     for (int zl = threadIdx.x; zl < nz; zl += THREADS) buf[pd(zl << log2P)] = make_double2(0.0, 0.0);
-    twr.ensure(log2P, +1.0, T.twiddle);
+    twr.ensure(log2P, T.twiddle);
     __syncthreads();
     fetch(min(w + (int)gridDim.x, n_work - 1));   // after the last item: a harmless reload
     lds_fft<ELEMS, THREADS>(buf, log2P, nz, +1.0, T.twiddle, twr);
@@ -711,7 +711,7 @@ k_fft_b_r2c(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
         buf[pd(q)] = make_double2((double)ra[i] * s, (double)rb[i] * s2);
       }
     }
-    twr.ensure(log2P, -1.0, T.twiddle);
+    twr.ensure(log2P, T.twiddle);
     __syncthreads();
     if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
     lds_fft<ELEMS, THREADS>(buf, log2P, nz, -1.0, T.twiddle, twr);
@@ -778,7 +778,7 @@ k_fft_a_fwd(const InstDesc* __restrict__ inst, const FftWork* __restrict__ work,
       const int q = threadIdx.x + i * THREADS;
       if (q < n) buf[pd(((q & (nl - 1)) << log2P) + (q >> log2nl))] = r[i];
     }
-    twr.ensure(log2P, -1.0, T.twiddle);
+    twr.ensure(log2P, T.twiddle);
     __syncthreads();
     if (w + (int)gridDim.x < n_work) fetch(w + gridDim.x);
     lds_fft<ELEMS, THREADS>(buf, log2P, nl, -1.0, T.twiddle, twr);

@@ -100,6 +100,8 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_rows(SteerArgs A) {
   const InstDesc d = A.inst[i];
   const SteerInst s = A.sti[i];
   const int N = d.N, P = 2 * N, log2P = d.log2N + 1, RB = s.rb, nl = RB / 2;
+  TwRegs<ST_ELEMS, ST_THREADS> twr;               // issued before the data loads, waited for with them
+  twr.load(log2P, A.T.twiddle);
   const int y0 = wk.first;
   double tp = 0.0;
   if (MODE == 0) {
@@ -151,7 +153,7 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_rows(SteerArgs A) {
   }
   __syncthreads();
   if (MODE == 0 && threadIdx.x == 0 && n_sel) atomicAdd(&A.ctl[s.ctl_off + 4 + A.k], n_sel);
-  lds_fft<ST_ELEMS, ST_THREADS>(buf, log2P, nl, -1.0, A.T.twiddle);
+  lds_fft<ST_ELEMS, ST_THREADS>(buf, log2P, nl, -1.0, A.T.twiddle, twr);
   // separate the two rows of each line: Xa = (Z(k) + conj Z(P-k)) / 2, Xb = (Z(k) - conj Z(P-k)) / 2i
   const int log2RB = __builtin_ctz(RB);
   float2* out = A.X + s.x_off + (int64_t)(y0 >> log2RB) * (N + 1) * RB;
@@ -181,6 +183,8 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_cols(SteerArgs A) {
     if (!st_active(A, s, i, peak)) return;
   }
   const int N = d.N, P = 2 * N, log2P = d.log2N + 1, RB = s.rb, log2RB = __builtin_ctz(RB);
+  TwRegs<ST_ELEMS, ST_THREADS> twr;               // issued before the data loads, waited for with them
+  twr.load(log2P, A.T.twiddle);
   const int kx0 = wk.first;
   const int nc = min(ST_ELEMS >> log2P, N + 1 - kx0);
   const int Rin = MODE == 0 ? P : N;
@@ -197,7 +201,7 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_cols(SteerArgs A) {
         y < Rin ? X[(int64_t)yb * (N + 1) * RB + (int64_t)(kx0 + c) * RB + r] : make_float2(0.0f, 0.0f);
   }
   __syncthreads();
-  lds_fft<ST_ELEMS, ST_THREADS>(buf, log2P, nc, -1.0, A.T.twiddle);
+  lds_fft<ST_ELEMS, ST_THREADS>(buf, log2P, nc, -1.0, A.T.twiddle, twr);
   float2* Sc = A.S + s.s_off + (int64_t)kx0 * P;
   if (MODE == 0) {
     const float sc = 1.0f / ((float)P * (float)P);     // a power of two: exact
@@ -209,7 +213,7 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_cols(SteerArgs A) {
   }
   for (int q = threadIdx.x; q < nc * P; q += ST_THREADS) buf[pd(q)] = cmul(buf[pd(q)], Sc[q]);
   __syncthreads();
-  lds_fft<ST_ELEMS, ST_THREADS>(buf, log2P, nc, +1.0, A.T.twiddle);
+  lds_fft<ST_ELEMS, ST_THREADS>(buf, log2P, nc, +1.0, A.T.twiddle, twr);
   for (int q = threadIdx.x; q < (N / RB) * run; q += ST_THREADS) {
     const int yb = q >> log2run, rem = q & (run - 1), c = rem >> log2RB, r = rem & (RB - 1);
     const int y = (yb << log2RB) + r;
@@ -234,6 +238,8 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_rows_inv(SteerArgs A) {
     if (!st_active(A, s, i, peak)) return;
   }
   const int N = d.N, P = 2 * N, log2P = d.log2N + 1, RB = s.rb, nl = RB / 2, log2nl = __builtin_ctz(nl);
+  TwRegs<ST_ELEMS, ST_THREADS> twr;               // issued before the data loads, waited for with them
+  twr.load(log2P, A.T.twiddle);
   const int j0 = wk.first;
   const float2* in = A.X + s.x_off + (int64_t)(j0 / RB) * (N + 1) * RB;
   for (int q = threadIdx.x; q < (N + 1) * nl; q += ST_THREADS) {
@@ -245,7 +251,7 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_rows_inv(SteerArgs A) {
     if (kx > 0 && kx < N) buf[pd(row + P - kx)] = make_float2(a.x + b.y, b.x - a.y);
   }
   __syncthreads();
-  lds_fft<ST_ELEMS, ST_THREADS>(buf, log2P, nl, +1.0, A.T.twiddle);
+  lds_fft<ST_ELEMS, ST_THREADS>(buf, log2P, nl, +1.0, A.T.twiddle, twr);
   unsigned m = 0u;
   const int log2N = d.log2N;
   for (int q = threadIdx.x; q < nl * N; q += ST_THREADS) {
