@@ -29,6 +29,8 @@
 // are order-preserving 32-bit images of float values, 0 meaning "none": iteration k's rows
 // pass clears the key that iteration k's update will fill (it last held iteration k - 1's
 // peak, read by then) and the max |D| key.
+#include <type_traits>
+
 #include "mi_internal.h"
 #include "fft_lds.h"
 
@@ -123,7 +125,29 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_rows(SteerArgs A) {
     gc = A.cbeam[6 * i + 2];
   }
   unsigned cnt = 0u;
-  for (int q = threadIdx.x; q < nl * P; q += ST_THREADS) {
+  // staging in fixed rounds (nl P <= ST_ELEMS), all loads first and then the LDS writes: one
+  // wait per thread instead of one memory round trip per element
+  constexpr int NPT = ST_ELEMS / ST_THREADS;
+  using LT = typename std::conditional<MODE == 1, double, float>::type;
+  LT ld[NPT][2];
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int q = threadIdx.x + k * ST_THREADS;
+    const int l = q >> log2P, x = q & (P - 1);
+    const bool in = q < nl * P && x < Lin;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int y = y0 + 2 * l + h;
+      if (MODE == 0) ld[k][h] = in ? A.R[d.img_off + (int64_t)y * N + x] : 0.0f;
+      else if (MODE == 1) ld[k][h] = in ? A.model[d.img_off + (int64_t)y * N + x] : 0.0;
+      else if (MODE == 2) ld[k][h] = in ? A.beam[d.beam_off + (int64_t)y * P + x] : 0.0f;
+      else ld[k][h] = 0;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int q = threadIdx.x + k * ST_THREADS;
+    if (q >= nl * P) continue;
     const int l = q >> log2P, x = q & (P - 1);
     double v[2] = {0.0, 0.0};
     if (x < Lin) {
@@ -131,14 +155,12 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_rows(SteerArgs A) {
       for (int h = 0; h < 2; ++h) {
         const int y = y0 + 2 * l + h;
         if (MODE == 0) {
-          const float r = A.R[d.img_off + (int64_t)y * N + x];
+          const float r = ld[k][h];
           const bool sel = st_sel(r, tp, A.posonly);
           cnt += sel ? 1u : 0u;
           v[h] = sel ? (double)r : 0.0;
-        } else if (MODE == 1) {
-          v[h] = A.model[d.img_off + (int64_t)y * N + x];
-        } else if (MODE == 2) {
-          v[h] = (double)A.beam[d.beam_off + (int64_t)y * P + x];
+        } else if (MODE == 1 || MODE == 2) {
+          v[h] = (double)ld[k][h];
         } else {
           const double dx = (double)(x - N), dy = (double)(y - N);
           v[h] = exp(-(dx * (ga * dx + gb * dy) + gc * dy * dy));
@@ -194,11 +216,25 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_cols(SteerArgs A) {
   // column count, or 1 for the last column kx = N: N is a multiple of it), so q splits by
   // shifts
   const int run = nc * RB, log2run = __builtin_ctz(nc) + log2RB;
-  for (int q = threadIdx.x; q < (P / RB) * run; q += ST_THREADS) {
+  // staging in fixed rounds (nc P <= ST_ELEMS elements), all loads before the LDS writes
+  constexpr int NPT = ST_ELEMS / ST_THREADS;
+  float2 sv[NPT];
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int q = threadIdx.x + k * ST_THREADS;
     const int yb = q >> log2run, rem = q & (run - 1), c = rem >> log2RB, r = rem & (RB - 1);
     const int y = (yb << log2RB) + r;
-    buf[pd((c << log2P) + y)] =
-        y < Rin ? X[(int64_t)yb * (N + 1) * RB + (int64_t)(kx0 + c) * RB + r] : make_float2(0.0f, 0.0f);
+    // an unconditional load (element 0 where nothing is read), then the selection: a load
+    // under a lane condition would be waited for inside its branch
+    const bool in = q < (P / RB) * run && y < Rin;
+    const float2 t = X[in ? (int64_t)yb * (N + 1) * RB + (int64_t)(kx0 + c) * RB + r : 0];
+    sv[k] = in ? t : make_float2(0.0f, 0.0f);
+  }
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int q = threadIdx.x + k * ST_THREADS;
+    const int yb = q >> log2run, rem = q & (run - 1), c = rem >> log2RB, r = rem & (RB - 1);
+    if (q < (P / RB) * run) buf[pd((c << log2P) + (yb << log2RB) + r)] = sv[k];
   }
   __syncthreads();
   lds_fft<ST_ELEMS, ST_THREADS>(buf, log2P, nc, -1.0, A.T.twiddle, twr);
@@ -242,9 +278,24 @@ __global__ void __launch_bounds__(ST_THREADS) k_st_rows_inv(SteerArgs A) {
   twr.load(log2P, A.T.twiddle);
   const int j0 = wk.first;
   const float2* in = A.X + s.x_off + (int64_t)(j0 / RB) * (N + 1) * RB;
-  for (int q = threadIdx.x; q < (N + 1) * nl; q += ST_THREADS) {
+  // staging in fixed rounds ((N + 1) nl <= ST_ELEMS / 2 + nl elements), all loads before
+  // the LDS writes
+  constexpr int NPT = ST_ELEMS / 2 / ST_THREADS + 1;
+  float2 sa[NPT], sb[NPT];
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int q = threadIdx.x + k * ST_THREADS;
     const int kx = q >> log2nl, l = q & (nl - 1);
-    float2 a = in[kx * RB + 2 * l], b = in[kx * RB + 2 * l + 1];
+    const bool ok = q < (N + 1) * nl;
+    sa[k] = ok ? in[kx * RB + 2 * l] : make_float2(0.0f, 0.0f);
+    sb[k] = ok ? in[kx * RB + 2 * l + 1] : make_float2(0.0f, 0.0f);
+  }
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int q = threadIdx.x + k * ST_THREADS;
+    if (q >= (N + 1) * nl) continue;
+    const int kx = q >> log2nl, l = q & (nl - 1);
+    float2 a = sa[k], b = sb[k];
     if (kx == 0 || kx == N) { a.y = 0.0f; b.y = 0.0f; }    // real by symmetry
     const int row = l << log2P;
     buf[pd(row + kx)] = make_float2(a.x - b.y, a.y + b.x);
