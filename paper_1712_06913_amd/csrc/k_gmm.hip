@@ -91,9 +91,13 @@ __device__ __forceinline__ double rsqrt_f64(double x) {
 
 // One workgroup of 256 threads per map, BPT bins per thread (8 for up to 2048 bins, so
 // that three workgroups share a compute unit and all maps of a 520-map batch are resident
-// at once).  The E step needs one exponential per bin (the larger of the two log terms
-// gives exp(0) = 1 exactly), and an iteration's sums take one workgroup reduction, i.e.
-// one barrier.
+// at once).  Each wave owns 64 BPT consecutive bins (bin of lane l, slot b: wave 64 BPT +
+// 64 b + l).  A wave whose bins are all empty (the bright tail of a dirty map's histogram)
+// skips the E step; the others run it without branches, so that a thread's BPT
+// exponentials overlap (an empty bin adds exact zeros: its count multiplies every term).
+// The E step needs one exponential per bin (the larger of the two log terms gives
+// exp(0) = 1 exactly), and an iteration's sums take one workgroup reduction, i.e. one
+// barrier.
 template <int GMM_BPT>
 __global__ void __launch_bounds__(GMM_THREADS)
 k_gmm(const InstDesc* __restrict__ inst, const float* __restrict__ images, int n_bins, int n_iter,
@@ -158,16 +162,18 @@ k_gmm(const InstDesc* __restrict__ inst, const float* __restrict__ images, int n
   }
   __syncthreads();
 
-  // bin centres and counts owned by this thread
+  // bin centres and counts owned by this thread (bins past n_bins count zero)
   const double h = span / B;
   double cnt[GMM_BPT], xc[GMM_BPT];
-  const int nb = (n_bins + GMM_THREADS - 1) / GMM_THREADS;   // bins per thread in use (uniform)
+  bool mine = false;
 #pragma unroll
   for (int b = 0; b < GMM_BPT; ++b) {
-    const int j = tid + b * GMM_THREADS;
+    const int j = wave * 64 * GMM_BPT + b * 64 + lane;
     cnt[b] = j < n_bins ? (double)hist[j] : 0.0;
     xc[b] = lo + ((double)j + 0.5) * h;
+    mine |= cnt[b] > 0.0;
   }
+  const bool wave_busy = __any(mine);                 // uniform over the wave
   // start: median and 90th-percentile bins (integer cumulative counts), histogram moments
   if (tid == 0) {
     int64_t tot = 0;
@@ -184,14 +190,12 @@ k_gmm(const InstDesc* __restrict__ inst, const float* __restrict__ images, int n
   }
   double s[2] = {0.0, 0.0};
 #pragma unroll
-  for (int b = 0; b < GMM_BPT; ++b)
-    if (b < nb) { s[0] += cnt[b]; s[1] += cnt[b] * xc[b]; }
+  for (int b = 0; b < GMM_BPT; ++b) { s[0] += cnt[b]; s[1] += cnt[b] * xc[b]; }
   block_sum<2>(s, scratch, parity);
   const double total = s[0], mean_all = s[1] / total;
   double v1[1] = {0.0};
 #pragma unroll
-  for (int b = 0; b < GMM_BPT; ++b)
-    if (b < nb) v1[0] += cnt[b] * (xc[b] - mean_all) * (xc[b] - mean_all);
+  for (int b = 0; b < GMM_BPT; ++b) v1[0] += cnt[b] * (xc[b] - mean_all) * (xc[b] - mean_all);
   block_sum<1>(v1, scratch, parity);
   const double floor_var = h * h;
   const double var_all = fmax(v1[0] / total, floor_var);
@@ -218,11 +222,9 @@ k_gmm(const InstDesc* __restrict__ inst, const float* __restrict__ images, int n
       iv[k] = 0.5 * rs * rs;
     }
     double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (wave_busy) {
 #pragma unroll
-    for (int b = 0; b < GMM_BPT; ++b) {
-      // an empty bin adds nothing to any sum; a wave whose 64 bins are all empty (the long
-      // bright tail of a dirty map's histogram) skips the exponential altogether
-      if (b < nb && cnt[b] > 0.0) {
+      for (int b = 0; b < GMM_BPT; ++b) {
         const double d0 = xc[b] - mu[0], d1 = xc[b] - mu[1];
         const double l0 = c0[0] - d0 * d0 * iv[0];
         const double l1 = c0[1] - d1 * d1 * iv[1];
