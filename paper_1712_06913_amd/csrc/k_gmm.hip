@@ -21,6 +21,7 @@ namespace mi {
 constexpr int GMM_THREADS = 256;
 constexpr int GMM_WAVES = GMM_THREADS / 64;
 constexpr int GMM_MAX_BINS = 4096;
+constexpr int GMM_UNROLL = 8;        // map loads in flight per thread
 
 namespace {
 
@@ -113,18 +114,30 @@ k_gmm(const InstDesc* __restrict__ inst, const float* __restrict__ images, int n
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int parity = 0;
 
-  // pass 1: range of the finite values (16-byte loads; N^2 is a multiple of 4)
+  // pass 1: range of the finite values (16-byte loads; N^2 is a multiple of 4), GMM_UNROLL
+  // loads in flight per thread (one map per workgroup leaves few waves to hide latency);
+  // a position past the map loads element 0 and is ignored where the values are used
   float mn = INFINITY, mx = -INFINITY;
   const float4* img4 = reinterpret_cast<const float4*>(img);
-  for (int64_t q = tid; q < n / 4; q += GMM_THREADS) {
-    const float4 v4 = img4[q];
-    const float v[4] = {v4.x, v4.y, v4.z, v4.w};
+  const int64_t n4 = n / 4;
+  for (int64_t q0 = tid; q0 < n4; q0 += GMM_UNROLL * GMM_THREADS) {
+    float4 v4[GMM_UNROLL];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (isfinite(v[j])) {
-        mn = fminf(mn, v[j]);
-        mx = fmaxf(mx, v[j]);
-      }
+    for (int u = 0; u < GMM_UNROLL; ++u) {
+      const int64_t q = q0 + u * GMM_THREADS;
+      v4[u] = img4[q < n4 ? q : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < GMM_UNROLL; ++u) {
+      const bool in = q0 + u * GMM_THREADS < n4;
+      const float v[4] = {v4[u].x, v4[u].y, v4[u].z, v4[u].w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (in && isfinite(v[j])) {
+          mn = fminf(mn, v[j]);
+          mx = fmaxf(mx, v[j]);
+        }
+    }
   }
   for (int o = 32; o > 0; o >>= 1) {
     mn = fminf(mn, __shfl_xor(mn, o));
@@ -149,15 +162,24 @@ k_gmm(const InstDesc* __restrict__ inst, const float* __restrict__ images, int n
   }
   // pass 2: histogram
   const double span = hi - lo, B = (double)n_bins;
-  for (int64_t q = tid; q < n / 4; q += GMM_THREADS) {
-    const float4 v4 = img4[q];
-    const float v[4] = {v4.x, v4.y, v4.z, v4.w};
+  for (int64_t q0 = tid; q0 < n4; q0 += GMM_UNROLL * GMM_THREADS) {
+    float4 v4[GMM_UNROLL];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (!isfinite(v[j])) continue;
-      int b = (int)floor(((double)v[j] - lo) / span * B);
-      b = min(b, n_bins - 1);
-      atomicAdd(&hist[b], 1u);
+    for (int u = 0; u < GMM_UNROLL; ++u) {
+      const int64_t q = q0 + u * GMM_THREADS;
+      v4[u] = img4[q < n4 ? q : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < GMM_UNROLL; ++u) {
+      const bool in = q0 + u * GMM_THREADS < n4;
+      const float v[4] = {v4[u].x, v4[u].y, v4[u].z, v4[u].w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (!in || !isfinite(v[j])) continue;
+        int b = (int)floor(((double)v[j] - lo) / span * B);
+        b = min(b, n_bins - 1);
+        atomicAdd(&hist[b], 1u);
+      }
     }
   }
   __syncthreads();
