@@ -808,9 +808,18 @@ k_fft_c2c_t(const int* __restrict__ n_arr, const int64_t* __restrict__ offs, con
   const int64_t off = offs[wk.inst];
   const TIn* in = src + off + (int64_t)wk.first * P;
   const int n = nl * P;
-  for (int q = threadIdx.x; q < n; q += THREADS) {
-    const TIn v = in[q];
-    double2 d = make_double2((double)v.x, (double)v.y);
+  // staging in fixed rounds (n <= ELEMS, a power of two), every load issued before the first
+  // LDS write (lanes past n load a duplicate, unused): one wait instead of one round trip per
+  // element
+  constexpr int NPT = ELEMS / THREADS;
+  TIn v[NPT];
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) v[k] = in[(threadIdx.x + k * THREADS) & (n - 1)];
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int q = threadIdx.x + k * THREADS;
+    if (q >= n) continue;
+    double2 d = make_double2((double)v[k].x, (double)v[k].y);
     if (pre && (((q >> log2P) + wk.first + (q & (P - 1))) & 1)) { d.x = -d.x; d.y = -d.y; }
     buf[pd(q)] = d;
   }
