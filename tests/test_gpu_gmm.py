@@ -20,9 +20,9 @@ def _dirty_maps(wl):
     return out
 
 
-def _compare(levels_gpu, maps):
+def _compare(levels_gpu, maps, n_bins=gmm.N_BINS):
     for i, m in enumerate(maps):
-        ref = gmm.levels(m)
+        ref = gmm.levels(m, n_bins=n_bins)
         got = levels_gpu[i]
         span = float(np.nanmax(np.where(np.isfinite(m), m, np.nan)) - np.nanmin(np.where(np.isfinite(m), m, np.nan))) \
             if np.isfinite(m).any() else 1.0
@@ -55,6 +55,29 @@ def test_levels_match_oracle_on_dirty_maps_and_edge_cases():
     assert np.array_equal(mu_a.cpu().numpy(), L[:, 0].astype(np.float32))
     assert np.array_equal(mu_b.cpu().numpy(), L[:, 3].astype(np.float32))
     assert tuple(L[3]) == (0.125, 0.0, 1.0, 0.125, 0.0, 0.0)
+
+
+def test_levels_sparse_histogram_and_more_bins():
+    """A map of three narrow clusters (sky, disk, a few bright pixels): its histogram leaves
+    the bin ranges of whole waves empty, which skip the E step; and 3000 bins, 16 per thread."""
+    log("[gmm] clustered map (empty waves) and 3000 bins")
+    require_gpu()
+    from paper_1712_06913_amd import api
+    wl = synth.random_instances(52, [64, 64, 128], m_range=(150, 300))
+    maps = _dirty_maps(wl)
+    rng = np.random.default_rng(7)
+    m = np.where(rng.random((64, 64)) < 0.7, 0.0, 1.0) + 1e-3 * rng.standard_normal((64, 64))
+    m[rng.integers(0, 64, 5), rng.integers(0, 64, 5)] = 10.0
+    maps[0] = m.astype(np.float32)
+    counts, lo, hi = gmm.histogram(maps[0])
+    occupied = np.nonzero(counts)[0]
+    assert not np.any((occupied >= 512) & (occupied < 1536))   # bins of waves 1 and 2 all empty
+    b = api.Batch.from_workload(wl)
+    imgs = torch.from_numpy(np.concatenate([mm.ravel() for mm in maps])).cuda()
+    for nb in (2000, 3000):
+        levels, _, _ = api.gmm_levels(b, imgs, n_bins=nb)
+        torch.cuda.synchronize()
+        _compare(levels.cpu().numpy(), maps, n_bins=nb)
 
 
 def test_levels_match_oracle_on_c1_and_c3_maps():
