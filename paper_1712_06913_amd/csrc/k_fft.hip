@@ -66,7 +66,13 @@ constexpr int LDS_PADDED(int elems) { return elems + elems / 8; }
 // The four inverse passes below are persistent: a workgroup takes work items w =
 // blockIdx.x, blockIdx.x + gridDim.x, ... and issues the global loads of its next item into
 // registers as soon as the current one is staged in LDS, so those loads are in flight
-// during the transform and the stores (LDS barriers do not wait for global loads).
+// during the transform and the stores (LDS barriers do not wait for global loads).  That
+// only holds if nothing waits for them early: the vector memory counter completes loads
+// and stores in order, and where the compiler cannot count what was issued after the load
+// it needs, it waits for everything.  Hence no global load inside a transform (twiddles in
+// registers, TwRegs), prefetched values kept raw until staging, only the record fields
+// that are used loaded, unconditional loads, and store loops with a fixed number of
+// unconditional rounds.
 
 // Pass A (inverse, dirty grid): half-grid lines -> FFT along v -> contiguous block Yb[b][y][l].
 template <int ELEMS, int THREADS>
