@@ -88,6 +88,45 @@ __device__ __forceinline__ double rsqrt_f64(double x) {
   return r;
 }
 
+// 2^(j/64), j = 0..63, correctly rounded
+__constant__ double kExp2Tab64[64] = {
+    0x1.0000000000000p+0, 0x1.02c9a3e778061p+0, 0x1.059b0d3158574p+0, 0x1.0874518759bc8p+0,
+    0x1.0b5586cf9890fp+0, 0x1.0e3ec32d3d1a2p+0, 0x1.11301d0125b51p+0, 0x1.1429aaea92de0p+0,
+    0x1.172b83c7d517bp+0, 0x1.1a35beb6fcb75p+0, 0x1.1d4873168b9aap+0, 0x1.2063b88628cd6p+0,
+    0x1.2387a6e756238p+0, 0x1.26b4565e27cddp+0, 0x1.29e9df51fdee1p+0, 0x1.2d285a6e4030bp+0,
+    0x1.306fe0a31b715p+0, 0x1.33c08b26416ffp+0, 0x1.371a7373aa9cbp+0, 0x1.3a7db34e59ff7p+0,
+    0x1.3dea64c123422p+0, 0x1.4160a21f72e2ap+0, 0x1.44e086061892dp+0, 0x1.486a2b5c13cd0p+0,
+    0x1.4bfdad5362a27p+0, 0x1.4f9b2769d2ca7p+0, 0x1.5342b569d4f82p+0, 0x1.56f4736b527dap+0,
+    0x1.5ab07dd485429p+0, 0x1.5e76f15ad2148p+0, 0x1.6247eb03a5585p+0, 0x1.6623882552225p+0,
+    0x1.6a09e667f3bcdp+0, 0x1.6dfb23c651a2fp+0, 0x1.71f75e8ec5f74p+0, 0x1.75feb564267c9p+0,
+    0x1.7a11473eb0187p+0, 0x1.7e2f336cf4e62p+0, 0x1.82589994cce13p+0, 0x1.868d99b4492edp+0,
+    0x1.8ace5422aa0dbp+0, 0x1.8f1ae99157736p+0, 0x1.93737b0cdc5e5p+0, 0x1.97d829fde4e50p+0,
+    0x1.9c49182a3f090p+0, 0x1.a0c667b5de565p+0, 0x1.a5503b23e255dp+0, 0x1.a9e6b5579fdbfp+0,
+    0x1.ae89f995ad3adp+0, 0x1.b33a2b84f15fbp+0, 0x1.b7f76f2fb5e47p+0, 0x1.bcc1e904bc1d2p+0,
+    0x1.c199bdd85529cp+0, 0x1.c67f12e57d14bp+0, 0x1.cb720dcef9069p+0, 0x1.d072d4a07897cp+0,
+    0x1.d5818dcfba487p+0, 0x1.da9e603db3285p+0, 0x1.dfc97337b9b5fp+0, 0x1.e502ee78b3ff6p+0,
+    0x1.ea4afa2a490dap+0, 0x1.efa1bee615a27p+0, 0x1.f50765b6e4540p+0, 0x1.fa7c1819e90d8p+0};
+
+// exp(t) for the E step (t <= 0, finite) by Tang's table-driven method (ACM TOMS 15, 1989):
+// t = (64 m + j) ln2 / 64 + r with |r| <= ln2 / 128, exp(t) = 2^m 2^(j/64) exp(r), exp(r) - 1
+// from its Taylor polynomial to degree 5 (truncation below 4e-17 at |r| <= ln2 / 128), the
+// reduction with ln2 / 64 split in two parts.  Within a few ulp of exp(t), ten FP64
+// operations and one LDS read instead of the library's longer sequence; very negative t
+// gives 0 through ldexp.
+__device__ __forceinline__ double exp_tang(double t, const double* __restrict__ tab64) {
+  const double INV = 0x1.71547652b82fep+6;            // 64 / ln2
+  const double L_HI = 0x1.62e42fefa39efp-7, L_LO = 0x1.abc9e3b39803fp-62;   // ln2 / 64
+  const double k = rint(t * INV);
+  const int n = (int)k;
+  const double r = fma(-k, L_LO, fma(-k, L_HI, t));
+  double c = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+  c = fma(r, c, 1.0 / 6.0);
+  c = fma(r, c, 0.5);
+  const double p = fma(r * r, c, r);                  // exp(r) - 1
+  const double tj = tab64[n & 63];
+  return ldexp(fma(tj, p, tj), n >> 6);
+}
+
 }  // namespace
 
 // One workgroup of 256 threads per map, BPT bins per thread (8 for up to 2048 bins, so
@@ -107,6 +146,8 @@ k_gmm(const InstDesc* __restrict__ inst, const float* __restrict__ images, int n
   __shared__ double scratch[2][6][GMM_WAVES];
   __shared__ float mm[2][GMM_WAVES];
   __shared__ int qbin[2];
+  __shared__ double tab64[64];
+  if (threadIdx.x < 64) tab64[threadIdx.x] = kExp2Tab64[threadIdx.x];   // read after the histogram barriers
   const int i = blockIdx.x;
   const InstDesc d = inst[i];
   const int64_t n = (int64_t)d.N * d.N;
@@ -250,7 +291,7 @@ k_gmm(const InstDesc* __restrict__ inst, const float* __restrict__ images, int n
         const double d0 = xc[b] - mu[0], d1 = xc[b] - mu[1];
         const double l0 = c0[0] - d0 * d0 * iv[0];
         const double l1 = c0[1] - d1 * d1 * iv[1];
-        const double e = exp(fmin(l0, l1) - fmax(l0, l1));   // the other term is exp(0) = 1
+        const double e = exp_tang(fmin(l0, l1) - fmax(l0, l1), tab64);   // the other term is exp(0) = 1
         // 1 / (1 + e) from the hardware reciprocal and two Newton steps (1 + e is in [1, 2])
         const double den = 1.0 + e;
         double inv = __builtin_amdgcn_rcp(den);
